@@ -1,0 +1,173 @@
+"""Density filter, objective and adjoint sensitivities (oracle).
+
+Paper §3.3.2: the PDE (Helmholtz) filter -d_ij d^2 g~/dxi_i dxi_j + g~ = g with
+d = diag(r_x^2, r_x^2, r_t^2)/12, and the chain rule that sends sensitivities
+through the same filter equation.  §3.3.3: adjoint sensitivities
+dphi/drho_e = -lambda^T dr/drho_e with J^T lambda = (dphi/ds)^T.
+
+Readings:
+  * the filter is discretised with the same trilinear elements (nodal g~),
+    homogeneous Neumann boundaries, consistent mass; the element value is the
+    mean of its 8 nodal values, and the element input enters through
+    int_e N_a dV = V_e/8;  F = (1/8) E^T (K_d + M)^{-1} (V/8) E is symmetric;
+  * a time-constant design ([ny, nx]) is filtered on a single slab, which is
+    exactly the space-time filter of its extrusion (§3.4.1);
+  * the objective of the differentiation workload is J = int Q T = f^T s with
+    the unmasked consistent load f; it has no explicit density dependence.
+"""
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .element import mass_1d, stiff_1d
+from .grid import Grid
+
+
+def filter_element_matrix(dx, dt, rx, rt):
+    dxx = rx * rx / 12.0
+    dtt = rt * rt / 12.0
+    Mx, Sx, Mt, St = mass_1d(dx), stiff_1d(dx), mass_1d(dt), stiff_1d(dt)
+    K = dxx * (np.kron(Mt, np.kron(Mx, Sx)) + np.kron(Mt, np.kron(Sx, Mx))) \
+        + dtt * np.kron(St, np.kron(Mx, Mx))
+    M = np.kron(Mt, np.kron(Mx, Mx))
+    return K + M
+
+
+def filter_operators(nx, ny, nt, dx, dt, rx, rt):
+    """Return (H, E, V): nodal Helmholtz matrix, element->node incidence
+    [n_nodes, n_elems], element volume."""
+    g = Grid(nx, ny, nt, dx, dt)
+    He = filter_element_matrix(dx, dt, rx, rt)
+    conn = g.connectivity()
+    rows = np.repeat(conn[:, :, None], 8, axis=2).ravel()
+    cols = np.repeat(conn[:, None, :], 8, axis=1).ravel()
+    vals = np.broadcast_to(He, (conn.shape[0], 8, 8)).ravel()
+    H = sp.coo_matrix((vals, (rows, cols)), shape=(g.n_nodes, g.n_nodes)).tocsc()
+    E = sp.coo_matrix((np.ones(conn.size), (conn.ravel(), np.repeat(np.arange(g.n_elems), 8))),
+                      shape=(g.n_nodes, g.n_elems)).tocsr()
+    return H, E, dx * dx * dt
+
+
+def filter_apply(gamma, dx, dt, rx, rt):
+    """Filtered element field F gamma for gamma of shape [nt, ny, nx] or [ny, nx]."""
+    gam = np.asarray(gamma, dtype=np.float64)
+    two_d = gam.ndim == 2
+    if two_d:
+        gam = gam[None]
+    nt, ny, nx = gam.shape
+    H, E, V = filter_operators(nx, ny, nt, dx, dt, rx, rt)
+    rhs = (V / 8.0) * (E @ gam.ravel())
+    gn = spla.spsolve(H, rhs)
+    out = (E.T @ gn / 8.0).reshape(gam.shape)
+    return out[0] if two_d else out
+
+
+def objective(f_full, s):
+    """J = f^T s (int Q T with the consistent load)."""
+    return float(np.dot(np.asarray(f_full).ravel(), np.asarray(s).ravel()))
+
+
+def element_sensitivity(grid, s, lam, dk_e, dC_e):
+    """g_e = -lambda_e^T (dk_e A + dC_e B) s_e per space-time element (§3.3.3).
+
+    s holds the full state (Dirichlet values included), lam is zero on the
+    Dirichlet set."""
+    from .element import element_matrices
+    from .assemble import broadcast_elements
+    A, B = element_matrices(grid.dx, grid.dt)
+    conn = grid.connectivity()
+    se = np.asarray(s).ravel()[conn]          # [E, 8]
+    le = np.asarray(lam).ravel()[conn]
+    la = np.einsum("ea,ab,eb->e", le, A, se)
+    lb = np.einsum("ea,ab,eb->e", le, B, se)
+    dk = broadcast_elements(grid, dk_e).ravel()
+    dC = broadcast_elements(grid, dC_e).ravel()
+    return (-(dk * la + dC * lb)).reshape(grid.shape_elems)
+
+
+def reduce_to_design(g_elem, design_shape):
+    """Chain rule through the extrusion of a time-constant design (§3.4.1):
+    the sensitivity of a driving variable is the sum over time slabs."""
+    if len(design_shape) == 2 or design_shape[0] == 1:
+        return g_elem.sum(axis=0).reshape(design_shape)
+    return g_elem.reshape(design_shape)
+
+
+def objective_and_gradient(grid, mat, rho, patches, q0=1.0, r_elems=None, with_grad=True):
+    """Full chain of the differentiation workload (§3.3): filter -> SIMP ->
+    state solve -> J = f^T s -> adjoint solve -> element sensitivities ->
+    extrusion sum (time-constant designs) -> filter transpose.
+
+    rho: unfiltered design, [ny, nx] (time-constant) or [nt, ny, nx].
+    r_elems: filter radius in elements (r_x = r dx, r_t = r dt); None = no filter.
+    Returns dict(J, grad, s, lam, rho_phys)."""
+    from .assemble import simp, assemble_matrix, load_vector, apply_dirichlet
+    from .grid import dirichlet_mask
+    from .solve import solve_direct, solve_adjoint_direct
+    rho = np.asarray(rho, dtype=np.float64)
+    if r_elems is not None:
+        rho_phys = filter_apply(rho, grid.dx, grid.dt, r_elems * grid.dx, r_elems * grid.dt)
+    else:
+        rho_phys = rho
+    k, C, dk, dC = simp(rho_phys, mat)
+    mask = dirichlet_mask(grid, patches)
+    f = load_vector(grid, q0)
+    J = assemble_matrix(grid, k, C)
+    Jm, fm = apply_dirichlet(J, f, mask)
+    s = solve_direct(Jm, fm)
+    out = dict(J=objective(f, s), s=s, rho_phys=rho_phys)
+    if not with_grad:
+        return out
+    lam = solve_adjoint_direct(Jm, f, mask)
+    ge = element_sensitivity(grid, s, lam, dk, dC)
+    g = reduce_to_design(ge, rho.shape)
+    if r_elems is not None:
+        g = filter_apply(g, grid.dx, grid.dt, r_elems * grid.dx, r_elems * grid.dt)
+    out.update(grad=g, lam=lam)
+    return out
+
+
+def central_difference(grid, mat, rho, patches, e, h=1e-6, q0=1.0, r_elems=None):
+    """(J(rho + h e_i) - J(rho - h e_i)) / (2h) without cancellation.
+
+    With J+ and J- the masked matrices at rho +- h e_i, s+ - s- solves
+    J+ (s+ - s-) = -(J+ - J-) s-, where J+ - J- is assembled directly from
+    k(rho+) - k(rho-) and C(rho+) - C(rho-); then dJ = f^T (s+ - s-).  This is
+    algebraically the two-solve central difference, but the small difference
+    is never formed by subtracting two nearly equal objective values."""
+    from .assemble import simp, assemble_matrix, load_vector, apply_dirichlet
+    from .grid import dirichlet_mask
+    from .solve import solve_direct
+    rho = np.asarray(rho, dtype=np.float64)
+    rp = rho.copy().ravel(); rp[e] += h
+    rm = rho.copy().ravel(); rm[e] -= h
+    rp, rm = rp.reshape(rho.shape), rm.reshape(rho.shape)
+    if r_elems is not None:
+        fp = filter_apply(rp, grid.dx, grid.dt, r_elems * grid.dx, r_elems * grid.dt)
+        fm_ = filter_apply(rm, grid.dx, grid.dt, r_elems * grid.dx, r_elems * grid.dt)
+        dphys = filter_apply((rp - rm), grid.dx, grid.dt, r_elems * grid.dx, r_elems * grid.dt)
+    else:
+        fp, fm_, dphys = rp, rm, rp - rm
+    kp, Cp, _, _ = simp(fp, mat)
+    km, Cm, _, _ = simp(fm_, mat)
+    # k(a) - k(b) = (k_con - k_ins) (a^p - b^p), formed from the difference a - b
+    # itself: a^p - b^p = (a - b) * sum_{q<p} a^q b^(p-1-q) for integer p.
+    def powdiff(a, b, p, d):
+        pi = int(round(p))
+        if abs(p - pi) > 0 or pi < 1:
+            return a ** p - b ** p
+        acc = np.zeros_like(a)
+        for q in range(pi):
+            acc = acc + a ** q * b ** (pi - 1 - q)
+        return d * acc
+    dk = (mat.k_con - mat.k_ins) * powdiff(fp, fm_, mat.p_k, dphys)
+    dC = (mat.c_con - mat.c_ins) * powdiff(fp, fm_, mat.p_c, dphys)
+    mask = dirichlet_mask(grid, patches)
+    f = load_vector(grid, q0)
+    Jp, _ = apply_dirichlet(assemble_matrix(grid, kp, Cp), f, mask)
+    Jn, fmask = apply_dirichlet(assemble_matrix(grid, km, Cm), f, mask)
+    dJ = assemble_matrix(grid, dk, dC)
+    keep = (~np.asarray(mask).ravel()).astype(np.float64)
+    sm = solve_direct(Jn, fmask)
+    ds = solve_direct(Jp, -(keep * (dJ @ (keep * sm))))
+    return float(f @ ds) / (2 * h)

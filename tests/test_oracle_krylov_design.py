@@ -1,0 +1,124 @@
+"""Pins of the oracle's Krylov solvers, filter and adjoint gradient."""
+import numpy as np
+import pytest
+
+from oracle.assemble import Material, assemble_matrix, apply_dirichlet, load_vector
+from oracle.design import filter_apply, filter_operators, objective_and_gradient
+from oracle.grid import Grid, dirichlet_mask
+from oracle.hierarchy import build_hierarchy
+from oracle.krylov import gmres_jacobi, fgmres, VCycle
+from oracle.multigrid import build_operators
+from oracle.solve import solve_direct
+
+PATCH = [(0, 0.5, 0.05)]
+MAT = Material()
+
+
+def _system(n, nt, seed=0, tv=False):
+    g = Grid(n, n, nt, 1.0 / n, 1.0 / nt)
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(1e-3, 1, (nt, n, n) if tv else (n, n))
+    k = 1e-3 + (1 - 1e-3) * rho ** 3
+    mask = dirichlet_mask(g, PATCH)
+    Jm, fm = apply_dirichlet(assemble_matrix(g, k, np.ones_like(k)), load_vector(g, 1.0), mask)
+    return g, Jm, fm, mask
+
+
+@pytest.mark.parametrize("kit", [1, 3, 6])
+def test_gmres_minimises_over_krylov_space(kit):
+    """k steps of left-Jacobi GMRES from x0 give the minimiser of
+    ||D^-1 (b - A x)|| over x0 + span{r, (D^-1 A) r, ...} (explicit basis)."""
+    g, A, b, _ = _system(4, 4, seed=1)
+    rng = np.random.default_rng(2)
+    x0 = rng.standard_normal(b.size) * 0.01
+    dinv = 1.0 / A.diagonal()
+    x, its, _ = gmres_jacobi(A, b, x0, maxit=kit, rtol=0.0, dinv=dinv)
+    assert its == kit
+    B = dinv[:, None] * A.toarray()
+    r = dinv * (b - A @ x0)
+    K = [r]
+    for _ in range(kit - 1):
+        K.append(B @ K[-1])
+    Q, _ = np.linalg.qr(np.array(K).T)
+    y, *_ = np.linalg.lstsq(B @ Q, r, rcond=None)
+    x_ls = x0 + Q @ y
+    assert np.linalg.norm(x - x_ls) <= 1e-10 * np.linalg.norm(x_ls)
+
+
+def test_gmres_restarted_reaches_exact_solution():
+    g, A, b, _ = _system(4, 4, seed=3)
+    x, its, est = gmres_jacobi(A, b, None, maxit=400, rtol=1e-13, restart=30)
+    xs = solve_direct(A, b)
+    assert est <= 1e-13 and its < 400
+    assert np.linalg.norm(x - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+def test_fgmres_exact_preconditioner_one_step():
+    g, A, b, _ = _system(4, 4, seed=4)
+    import scipy.sparse.linalg as spla
+    lu = spla.splu(A.tocsc())
+    x, its, rel = fgmres(A, b, lu.solve, m=5, rtol=1e-12)
+    assert its == 1 and rel < 1e-12
+
+
+def test_fgmres_vcycle_matches_direct_small_workload():
+    """FGMRES(30) + V-cycle on the small workload converges to the direct
+    solution; the iteration count stays in a small band (sanity, not a gate)."""
+    from paper_2508_09589_amd.inputs import uniform_density
+    rho = uniform_density(32, seed=0)
+    g = Grid(32, 32, 32, 1 / 32, 1 / 32)
+    k = 1e-3 + (1 - 1e-3) * rho ** 3
+    mask = dirichlet_mask(g, PATCH)
+    Jm, fm = apply_dirichlet(assemble_matrix(g, k, np.ones_like(k)), load_vector(g, 1.0), mask)
+    lv = build_hierarchy(32, 32, 32, 1 / 32, 1 / 32, 1.0, 1e-3, 1.0, 1.0)
+    A, masks, Pm = build_operators(lv, Jm, mask)
+    x, its, rel = fgmres(Jm, fm, VCycle(A, Pm), m=30, rtol=1e-10)
+    xs = solve_direct(Jm, fm)
+    assert rel <= 1e-10
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+    assert 2 <= its <= 25
+
+
+def test_filter_preserves_constants_and_is_symmetric():
+    for shape in [(3, 4, 5), (4, 5)]:
+        one = np.ones(shape)
+        assert np.max(np.abs(filter_apply(one, 0.2, 0.3, 0.3, 0.45) - 1.0)) < 1e-13
+    shape = (3, 3, 4)
+    n = int(np.prod(shape))
+    F = np.zeros((n, n))
+    for e in range(n):
+        u = np.zeros(n); u[e] = 1.0
+        F[:, e] = filter_apply(u.reshape(shape), 0.25, 0.5, 0.375, 0.75).ravel()
+    assert np.max(np.abs(F - F.T)) < 1e-14
+
+
+def test_time_constant_filter_equals_filter_of_extrusion():
+    rng = np.random.default_rng(5)
+    g2 = rng.uniform(0, 1, (5, 6))
+    f2 = filter_apply(g2, 0.2, 0.1, 0.3, 0.15)
+    f3 = filter_apply(np.broadcast_to(g2, (4, 5, 6)).copy(), 0.2, 0.1, 0.3, 0.15)
+    assert np.max(np.abs(f3 - f2[None])) < 1e-13
+
+
+@pytest.mark.parametrize("tv,filt", [(True, 1.5), (False, None), (False, 1.5)])
+def test_adjoint_gradient_matches_central_differences(tv, filt):
+    """dJ/drho from the adjoint chain equals the central difference (h = 1e-6)
+    of J = f^T s on a 6x6x5 grid to 1e-7 relative (difference-system form),
+    and the naive two-solve central difference at h = 1e-4 to 1e-4."""
+    from oracle.design import central_difference
+    nx, nt = 6, 5
+    g = Grid(nx, nx, nt, 1 / 6, 0.2)
+    rng = np.random.default_rng(7)
+    rho = rng.uniform(0.1, 0.9, (nt, nx, nx) if tv else (nx, nx))
+    out = objective_and_gradient(g, MAT, rho, PATCH, 1.0, filt)
+    idx = rng.choice(rho.size, 5, replace=False)
+    for e in idx:
+        ad = out["grad"].ravel()[e]
+        fd = central_difference(g, MAT, rho, PATCH, e, 1e-6, 1.0, filt)
+        assert abs(fd - ad) <= 1e-7 * abs(ad), (e, fd, ad)
+        h = 1e-4
+        rp = rho.copy().ravel(); rp[e] += h
+        rm = rho.copy().ravel(); rm[e] -= h
+        Jp = objective_and_gradient(g, MAT, rp.reshape(rho.shape), PATCH, 1.0, filt, False)["J"]
+        Jn = objective_and_gradient(g, MAT, rm.reshape(rho.shape), PATCH, 1.0, filt, False)["J"]
+        assert abs((Jp - Jn) / (2 * h) - ad) <= 1e-4 * abs(ad)
