@@ -1,0 +1,609 @@
+// Fine-level kernels: SIMP coefficients, the matrix-free stabilised space-time
+// Q1 operator and its transpose, its diagonal, the consistent load, the density
+// sensitivities and the constant-coefficient tensor operator of the filter.
+//
+// Operator (paper §3.1.1, §3.1.2).  For a dx x dx x dt brick the element matrix
+// is k_e A + C_e B with A = Mt (x) Kq and B = U (x) Mq, where Kq is the 2-D
+// bilinear stiffness (independent of dx for square elements), Mq the 2-D mass,
+// Mt = dt/6 [[2,1],[1,2]] and U = [[0,0],[-1,1]] (the capacity term plus the
+// artificial time diffusion C dt/2 collapses to this upwind block).  Summing
+// slab s (elements between time levels s and s+1) gives, with K_s, M_s the
+// 2-D operators weighted by the slab's k and C,
+//   y_s     += dt/6 K_s (2 x_s + x_{s+1})
+//   y_{s+1} += dt/6 K_s (x_s + 2 x_{s+1}) + M_s (x_{s+1} - x_s)
+// and for the transpose the capacity part moves to  y_s -= M_s x_{s+1},
+// y_{s+1} += M_s x_{s+1}.  A thread owns one (i, j) node column and marches
+// through a chunk of time levels, so every x value is loaded once per chunk
+// from its plane and the stiffness of the lower plane is reused when the
+// coefficients do not change in time.  Dirichlet nodes: inputs are masked to
+// zero and rows become identity rows (N J N + I - N).
+#include "st_internal.hpp"
+
+namespace st {
+
+__device__ __forceinline__ bool on_patch(const PatchSet& P, int nx, int ny, int i, int j) {
+    bool r = false;
+#pragma unroll
+    for (int q = 0; q < ST_MAX_PATCHES; ++q) {
+        if (q < P.n) {
+            const int e = P.edge[q];
+            const int lo = P.lo[q], hi = P.hi[q];
+            if (e == ST_EDGE_X1_LO) r |= (i == 0 && j >= lo && j <= hi);
+            else if (e == ST_EDGE_X1_HI) r |= (i == nx && j >= lo && j <= hi);
+            else if (e == ST_EDGE_X2_LO) r |= (j == 0 && i >= lo && i <= hi);
+            else r |= (j == ny && i >= lo && i <= hi);
+        }
+    }
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// SIMP (§2.2): k, C and their derivatives per element.
+__global__ void k_simp(long long ne, const double* __restrict__ rho, double kins, double kcon,
+                       double pk, double cins, double ccon, double pc, double* __restrict__ k,
+                       double* __restrict__ c, double* __restrict__ dk, double* __restrict__ dc,
+                       float* __restrict__ k32, float* __restrict__ c32, int cuniform) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < ne;
+         e += (long long)gridDim.x * blockDim.x) {
+        const double r = rho[e];
+        const double kv = kins + (kcon - kins) * pow(r, pk);
+        k[e] = kv;
+        dk[e] = pk * (kcon - kins) * pow(r, pk - 1.0);
+        if (k32) k32[e] = (float)kv;
+        if (!cuniform) {
+            const double cv = cins + (ccon - cins) * pow(r, pc);
+            c[e] = cv;
+            dc[e] = pc * (ccon - cins) * pow(r, pc - 1.0);
+            if (c32) c32[e] = (float)cv;
+        }
+    }
+}
+
+void launch_simp(hipStream_t s, long long ne, const double* rho, const st_material* m, double* k,
+                 double* c, double* dk, double* dc, float* k32, float* c32, int cuniform) {
+    long long nb = (ne + 255) / 256;
+    if (nb > 65535) nb = 65535;
+    hipLaunchKernelGGL(k_simp, dim3((unsigned)nb), dim3(256), 0, s, ne, rho, m->k_ins, m->k_con,
+                       m->p_k, m->c_ins, m->c_con, m->p_c, k, c, dk, dc, k32, c32, cuniform);
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-free apply.
+template <typename TC>
+__device__ __forceinline__ TC stiff6(const TC u[9], const TC kq[4]) {
+    // 6 * (2-D bilinear stiffness) at the centre node; quads SW, SE, NW, NE.
+    const TC ks = kq[0] + kq[1] + kq[2] + kq[3];
+    TC v = (TC)4 * u[4] * ks;
+    v -= u[3] * (kq[0] + kq[2]);
+    v -= u[5] * (kq[1] + kq[3]);
+    v -= u[1] * (kq[0] + kq[1]);
+    v -= u[7] * (kq[2] + kq[3]);
+    v -= (TC)2 * (kq[0] * u[0] + kq[1] * u[2] + kq[2] * u[6] + kq[3] * u[8]);
+    return v;
+}
+
+template <typename TC>
+__device__ __forceinline__ TC mass36(const TC u[9], const TC cq[4]) {
+    // (36 / dx^2) * (2-D bilinear mass) at the centre node.
+    const TC cs = cq[0] + cq[1] + cq[2] + cq[3];
+    TC v = (TC)4 * u[4] * cs;
+    v += (TC)2 * u[3] * (cq[0] + cq[2]);
+    v += (TC)2 * u[5] * (cq[1] + cq[3]);
+    v += (TC)2 * u[1] * (cq[0] + cq[1]);
+    v += (TC)2 * u[7] * (cq[2] + cq[3]);
+    v += cq[0] * u[0] + cq[1] * u[2] + cq[2] * u[6] + cq[3] * u[8];
+    return v;
+}
+
+template <typename TIN, typename TOUT, typename TC, bool TRANS, bool TCONST>
+__global__ __launch_bounds__(256) void k_fine_apply(
+    FineGeom g, const TC* __restrict__ kc, const TC* __restrict__ cc, const TIN* __restrict__ x,
+    TOUT* __restrict__ y, const TOUT* __restrict__ b, const TOUT* __restrict__ invd,
+    const double* __restrict__ scale, const int* __restrict__ skip, int nchunk, int mask_in,
+    int dir_rows) {
+    if (skip && *skip) return;
+    const int nx = g.nx, ny = g.ny, nt = g.nt;
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    const int j = blockIdx.y * 4 + threadIdx.y;
+    if (i > nx || j > ny) return;
+    const int n0 = blockIdx.z * nchunk;
+    if (n0 > nt) return;
+    const int n1 = min(n0 + nchunk, nt + 1);
+    const long long rowp = nx + 1;
+    const long long P = rowp * (ny + 1);
+    const long long cidx = (long long)j * rowp + i;
+
+    // Neighbour validity and patch membership (time-invariant).
+    unsigned valid = 0, patch = 0;
+    long long off[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const int di = q % 3 - 1, dj = q / 3 - 1;
+        const int ii = i + di, jj = j + dj;
+        off[q] = (long long)dj * rowp + di;
+        const bool v = ii >= 0 && ii <= nx && jj >= 0 && jj <= ny;
+        if (v) valid |= 1u << q;
+        if (v && on_patch(g.patches, nx, ny, ii, jj)) patch |= 1u << q;
+    }
+    const unsigned live_in = mask_in ? (valid & ~patch) : valid;
+    const bool centre_patch = (patch >> 4) & 1u;
+
+    // Quad existence: SW, SE, NW, NE.
+    const bool qv[4] = {i >= 1 && j >= 1, i < nx && j >= 1, i >= 1 && j < ny, i < nx && j < ny};
+    const long long qoff[4] = {(long long)(j - 1) * nx + (i - 1), (long long)(j - 1) * nx + i,
+                               (long long)j * nx + (i - 1), (long long)j * nx + i};
+    const long long slab = (long long)nx * ny;
+
+    TC kq[4], cq[4];
+    auto load_coef = [&](int s) {
+        const long long base = TCONST ? 0 : (long long)s * slab;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            kq[q] = qv[q] ? kc[base + qoff[q]] : (TC)0;
+            cq[q] = qv[q] ? (g.cuniform ? (TC)g.c0 : cc[base + qoff[q]]) : (TC)0;
+        }
+    };
+    auto load_plane = [&](int n, TC u[9]) {
+        const TIN* xp = x + (long long)n * P + cidx;
+        const unsigned live = (mask_in && g.ic_dir && n == 0) ? 0u : live_in;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) u[q] = ((live >> q) & 1u) ? (TC)xp[off[q]] : (TC)0;
+    };
+    const TC kt = (TC)g.dt6;
+    const TC mw = (TC)g.mw;
+    const TC sc = scale ? (TC)(*scale) : (TC)1;
+    auto emit = [&](int n, TC v) {
+        const long long idx = (long long)n * P + cidx;
+        const bool dir = dir_rows && ((g.ic_dir && n == 0) || centre_patch);
+        TC val = dir ? (TC)x[idx] : v;
+        if (b) val = (TC)b[idx] - val;
+        if (invd) val *= (TC)invd[idx];
+        y[idx] = (TOUT)(val * sc);
+    };
+
+    const int sa = max(n0 - 1, 0);
+    const int sb = min(n1 - 1, nt - 1);
+    TC ulo[9], uhi[9];
+    load_plane(sa, ulo);
+    TC Plo = 0, Rlo = 0;
+    if (TCONST) {
+        load_coef(0);
+        Plo = kt * stiff6(ulo, kq);
+        Rlo = mw * mass36(ulo, cq);
+    }
+    TC acc = 0;
+    for (int s = sa; s <= sb; ++s) {
+        load_plane(s + 1, uhi);
+        if (!TCONST) load_coef(s);
+        const TC Pv = TCONST ? Plo : kt * stiff6(ulo, kq);
+        const TC Qv = kt * stiff6(uhi, kq);
+        const TC Sv = mw * mass36(uhi, cq);
+        TC bottom = (TC)2 * Pv + Qv;
+        TC top = Pv + (TC)2 * Qv;
+        if (TRANS) {
+            bottom -= Sv;
+            top += Sv;
+        } else {
+            const TC Rv = TCONST ? Rlo : mw * mass36(ulo, cq);
+            top += Sv - Rv;
+        }
+        if (s >= n0) emit(s, acc + bottom);
+        acc = top;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) ulo[q] = uhi[q];
+        if (TCONST) {
+            Plo = Qv;
+            Rlo = Sv;
+        }
+    }
+    if (sb + 1 == nt && nt >= n0 && nt < n1) emit(nt, acc);
+}
+
+template <typename TIN, typename TOUT, typename TC>
+static void fine_dispatch(hipStream_t s, const FineGeom& g, const TC* kc, const TC* cc, int trans,
+                          const void* x, void* y, const void* b, const void* invd,
+                          const double* scale, const int* skip, int mask_in, int dir_rows) {
+    const int gx = (g.nx + 1 + 63) / 64, gy = (g.ny + 1 + 3) / 4;
+    long long cols = (long long)gx * gy;
+    int nchunk = 32;
+    while (nchunk > 4 && cols * ((g.nt + 1 + nchunk - 1) / nchunk) < 4096) nchunk /= 2;
+    const int gz = (g.nt + 1 + nchunk - 1) / nchunk;
+    dim3 grid(gx, gy, gz), block(64, 4);
+    const TIN* xi = (const TIN*)x;
+    TOUT* yo = (TOUT*)y;
+    const TOUT* bi = (const TOUT*)b;
+    const TOUT* di = (const TOUT*)invd;
+    if (g.tconst) {
+        if (trans)
+            hipLaunchKernelGGL((k_fine_apply<TIN, TOUT, TC, true, true>), grid, block, 0, s, g, kc,
+                               cc, xi, yo, bi, di, scale, skip, nchunk, mask_in, dir_rows);
+        else
+            hipLaunchKernelGGL((k_fine_apply<TIN, TOUT, TC, false, true>), grid, block, 0, s, g,
+                               kc, cc, xi, yo, bi, di, scale, skip, nchunk, mask_in, dir_rows);
+    } else {
+        if (trans)
+            hipLaunchKernelGGL((k_fine_apply<TIN, TOUT, TC, true, false>), grid, block, 0, s, g,
+                               kc, cc, xi, yo, bi, di, scale, skip, nchunk, mask_in, dir_rows);
+        else
+            hipLaunchKernelGGL((k_fine_apply<TIN, TOUT, TC, false, false>), grid, block, 0, s, g,
+                               kc, cc, xi, yo, bi, di, scale, skip, nchunk, mask_in, dir_rows);
+    }
+}
+
+// prec_in / prec_out: 0 = double, 1 = float.  compute64: arithmetic and
+// coefficients in FP64 (else FP32).
+void launch_fine_apply(hipStream_t s, const FineGeom& g, const Coef& cf, int prec_in, int prec_out,
+                       int compute64, int trans, const void* x, void* y, const void* b,
+                       const void* invd, const double* scale, const int* skip, int mask_in,
+                       int dir_rows) {
+    if (compute64) {
+        if (prec_in == 0 && prec_out == 0)
+            fine_dispatch<double, double, double>(s, g, cf.k64, cf.c64, trans, x, y, b, invd,
+                                                  scale, skip, mask_in, dir_rows);
+        else if (prec_in == 1 && prec_out == 0)
+            fine_dispatch<float, double, double>(s, g, cf.k64, cf.c64, trans, x, y, b, invd, scale,
+                                                 skip, mask_in, dir_rows);
+        else
+            fine_dispatch<double, float, double>(s, g, cf.k64, cf.c64, trans, x, y, b, invd, scale,
+                                                 skip, mask_in, dir_rows);
+    } else {
+        fine_dispatch<float, float, float>(s, g, cf.k32, cf.c32, trans, x, y, b, invd, scale, skip,
+                                           mask_in, dir_rows);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Diagonal of the fine operator: per element, A_aa = 2 dt / 9 for every node and
+// B_aa = dx^2 / 9 for the nodes on the element's upper time face.
+__global__ void k_fine_invdiag(FineGeom g, const double* __restrict__ kc,
+                               const double* __restrict__ cc, double dx, double dt,
+                               double* __restrict__ invd64, float* __restrict__ invd32,
+                               uint8_t* __restrict__ mask) {
+    const int nx = g.nx, ny = g.ny, nt = g.nt;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i > nx || j > ny) return;
+    const long long P = (long long)(nx + 1) * (ny + 1);
+    const long long slab = (long long)nx * ny;
+    const bool qv[4] = {i >= 1 && j >= 1, i < nx && j >= 1, i >= 1 && j < ny, i < nx && j < ny};
+    const long long qoff[4] = {(long long)(j - 1) * nx + (i - 1), (long long)(j - 1) * nx + i,
+                               (long long)j * nx + (i - 1), (long long)j * nx + i};
+    const bool patch = on_patch(g.patches, nx, ny, i, j);
+    auto sums = [&](int s, double& ks, double& cs) {
+        const long long base = g.tconst ? 0 : (long long)s * slab;
+        ks = 0;
+        cs = 0;
+        for (int q = 0; q < 4; ++q)
+            if (qv[q]) {
+                ks += kc[base + qoff[q]];
+                cs += g.cuniform ? g.c0 : cc[base + qoff[q]];
+            }
+    };
+    for (int n = 0; n <= nt; ++n) {
+        double kb = 0, cb = 0, ka = 0, ca = 0;
+        if (n >= 1) sums(n - 1, kb, cb);
+        if (n < nt) sums(n, ka, ca);
+        const bool dir = (g.ic_dir && n == 0) || patch;
+        const double d = (2.0 * dt / 9.0) * (kb + ka) + (dx * dx / 9.0) * cb;
+        const double inv = dir ? 1.0 : 1.0 / d;
+        const long long idx = (long long)n * P + (long long)j * (nx + 1) + i;
+        invd64[idx] = inv;
+        if (invd32) invd32[idx] = (float)inv;
+        if (mask) mask[idx] = dir ? 1 : 0;
+    }
+}
+
+void launch_fine_invdiag(hipStream_t s, const FineGeom& g, const Coef& cf, double dx, double dt,
+                         double* invd64, float* invd32, uint8_t* mask) {
+    dim3 grid((g.nx + 1 + 63) / 64, g.ny + 1);
+    hipLaunchKernelGGL(k_fine_invdiag, grid, dim3(64), 0, s, g, cf.k64, cf.c64, dx, dt, invd64,
+                       invd32, mask);
+}
+
+// ---------------------------------------------------------------------------
+// Consistent load of a uniform source: each element adds q0 V_e / 8 to its nodes.
+__global__ void k_load_uniform(FineGeom g, double w, double* __restrict__ f) {
+    const int nx = g.nx, ny = g.ny, nt = g.nt;
+    const long long P = (long long)(nx + 1) * (ny + 1);
+    const long long N = P * (nt + 1);
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < N;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int n = (int)(idx / P);
+        const long long r = idx - n * P;
+        const int j = (int)(r / (nx + 1)), i = (int)(r - (long long)j * (nx + 1));
+        const int cx = (i == 0 || i == nx) ? 1 : 2;
+        const int cy = (j == 0 || j == ny) ? 1 : 2;
+        const int ct = (n == 0 || n == nt) ? 1 : 2;
+        f[idx] = w * (double)(cx * cy * ct);
+    }
+}
+
+void launch_load_uniform(hipStream_t s, const FineGeom& g, double q0, double dx, double dt,
+                         double* f) {
+    const long long N = (long long)(g.nx + 1) * (g.ny + 1) * (g.nt + 1);
+    long long nb = (N + 255) / 256;
+    if (nb > 65535) nb = 65535;
+    hipLaunchKernelGGL(k_load_uniform, dim3((unsigned)nb), dim3(256), 0, s, g,
+                       q0 * dx * dx * dt / 8.0, f);
+}
+
+// Dirichlet lifting vector: the initial condition on the t = 0 plane, zero
+// elsewhere (patch nodes of later levels are T = 0).
+__global__ void k_ic_lift(FineGeom g, const double* __restrict__ ic, double* __restrict__ gv) {
+    const long long P = (long long)(g.nx + 1) * (g.ny + 1);
+    const long long N = P * (g.nt + 1);
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < N;
+         idx += (long long)gridDim.x * blockDim.x)
+        gv[idx] = (idx < P && g.ic_dir) ? ic[idx] : 0.0;
+}
+
+void launch_ic_lift_vector(hipStream_t s, const FineGeom& g, const double* ic, double* gvec) {
+    const long long N = (long long)(g.nx + 1) * (g.ny + 1) * (g.nt + 1);
+    long long nb = (N + 255) / 256;
+    if (nb > 65535) nb = 65535;
+    hipLaunchKernelGGL(k_ic_lift, dim3((unsigned)nb), dim3(256), 0, s, g, ic, gvec);
+}
+
+// f_m = N (f - J g) + g.
+__global__ void k_lift(long long n, const uint8_t* __restrict__ mask, const double* __restrict__ f,
+                       const double* __restrict__ Jg, const double* __restrict__ gv,
+                       double* __restrict__ fm) {
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * blockDim.x)
+        fm[idx] = mask[idx] ? gv[idx] : f[idx] - Jg[idx];
+}
+
+void launch_lift(hipStream_t s, long long n, const uint8_t* mask, const double* f,
+                 const double* Jg, const double* g, double* fm) {
+    long long nb = (n + 255) / 256;
+    if (nb > 65535) nb = 65535;
+    hipLaunchKernelGGL(k_lift, dim3((unsigned)nb), dim3(256), 0, s, n, mask, f, Jg, g, fm);
+}
+
+__global__ void k_mask_vec(long long n, const uint8_t* __restrict__ mask,
+                           const double* __restrict__ in, double* __restrict__ out) {
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * blockDim.x)
+        out[idx] = mask[idx] ? 0.0 : in[idx];
+}
+
+void launch_mask_vec(hipStream_t s, long long n, const uint8_t* mask, const double* in,
+                     double* out) {
+    long long nb = (n + 255) / 256;
+    if (nb > 65535) nb = 65535;
+    hipLaunchKernelGGL(k_mask_vec, dim3((unsigned)nb), dim3(256), 0, s, n, mask, in, out);
+}
+
+// ---------------------------------------------------------------------------
+// Sensitivities (§3.3.3): g_e = -lambda_e^T (k'_e A + C'_e B) s_e.  With
+// A = Mt (x) Kq:  lambda^T A s = dt/6 [2 lb.Kq sb + lb.Kq st + lt.Kq sb + 2 lt.Kq st];
+// with B = U (x) Mq:  lambda^T B s = lt.Mq (st - sb).  A thread owns one
+// element column; a time-constant design sums over slabs in order.
+__device__ __forceinline__ void kq4(const double s[4], double o[4]) {
+    // 6 * Kq s with local order (0,0), (1,0), (0,1), (1,1)
+    o[0] = 4 * s[0] - s[1] - s[2] - 2 * s[3];
+    o[1] = -s[0] + 4 * s[1] - 2 * s[2] - s[3];
+    o[2] = -s[0] - 2 * s[1] + 4 * s[2] - s[3];
+    o[3] = -2 * s[0] - s[1] - s[2] + 4 * s[3];
+}
+__device__ __forceinline__ void mq4(const double s[4], double o[4]) {
+    // 36 / dx^2 * Mq s
+    o[0] = 4 * s[0] + 2 * s[1] + 2 * s[2] + s[3];
+    o[1] = 2 * s[0] + 4 * s[1] + s[2] + 2 * s[3];
+    o[2] = 2 * s[0] + s[1] + 4 * s[2] + 2 * s[3];
+    o[3] = s[0] + 2 * s[1] + 2 * s[2] + 4 * s[3];
+}
+
+__global__ void k_sensitivity(FineGeom g, double dx, double dt, const double* __restrict__ T,
+                              const double* __restrict__ lam, const double* __restrict__ dk,
+                              const double* __restrict__ dc, double* __restrict__ out,
+                              int sum_slabs) {
+    const int nx = g.nx, ny = g.ny, nt = g.nt;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= nx || j >= ny) return;
+    const long long rowp = nx + 1;
+    const long long P = rowp * (ny + 1);
+    const long long slab = (long long)nx * ny;
+    const long long e2 = (long long)j * nx + i;
+    const long long c0 = (long long)j * rowp + i;
+    const long long loc[4] = {c0, c0 + 1, c0 + rowp, c0 + rowp + 1};
+    double acc = 0.0;
+    for (int s = 0; s < nt; ++s) {
+        double sb[4], st_[4], lb[4], lt[4];
+        for (int a = 0; a < 4; ++a) {
+            sb[a] = T[(long long)s * P + loc[a]];
+            st_[a] = T[(long long)(s + 1) * P + loc[a]];
+            lb[a] = lam[(long long)s * P + loc[a]];
+            lt[a] = lam[(long long)(s + 1) * P + loc[a]];
+        }
+        double kb[4], kt[4], md[4], ds[4];
+        kq4(sb, kb);
+        kq4(st_, kt);
+        for (int a = 0; a < 4; ++a) ds[a] = st_[a] - sb[a];
+        mq4(ds, md);
+        double lbkb = 0, lbkt = 0, ltkb = 0, ltkt = 0, ltm = 0;
+        for (int a = 0; a < 4; ++a) {
+            lbkb += lb[a] * kb[a];
+            lbkt += lb[a] * kt[a];
+            ltkb += lt[a] * kb[a];
+            ltkt += lt[a] * kt[a];
+            ltm += lt[a] * md[a];
+        }
+        const double la = (dt / 36.0) * (2 * lbkb + lbkt + ltkb + 2 * ltkt);
+        const double lb_ = (dx * dx / 36.0) * ltm;
+        const long long e = g.tconst ? e2 : (long long)s * slab + e2;
+        const double dcv = g.cuniform ? 0.0 : dc[e];
+        const double ge = -(dk[e] * la + dcv * lb_);
+        if (sum_slabs)
+            acc += ge;
+        else
+            out[(long long)s * slab + e2] = ge;
+    }
+    if (sum_slabs) out[e2] = acc;
+}
+
+void launch_sensitivity(hipStream_t s, const FineGeom& g, double dx, double dt, const double* T,
+                        const double* lam, const double* dk, const double* dc, double* out,
+                        int sum_slabs) {
+    dim3 grid((g.nx + 63) / 64, g.ny);
+    hipLaunchKernelGGL(k_sensitivity, grid, dim3(64), 0, s, g, dx, dt, T, lam, dk, dc, out,
+                       sum_slabs);
+}
+
+// ---------------------------------------------------------------------------
+// Constant-coefficient tensor operator on a full box with natural boundaries:
+//   H = dxx (Mt (x) My (x) Sx + Mt (x) Sy (x) Mx) + dtt St (x) My (x) Mx + Mt (x) My (x) Mx
+// with 1-D assembled linear-element mass M and stiffness S.  It is the nodal
+// Helmholtz operator of the PDE filter (§3.3.2) and, with dxx = dtt = 0, the
+// consistent space-time mass used for a nodal heat source.
+__device__ __forceinline__ void w1d(int i, int n, double h, double m[3], double st[3]) {
+    const bool lo = i > 0, hi = i < n;
+    const int cnt = (int)lo + (int)hi;
+    m[0] = lo ? h / 6.0 : 0.0;
+    m[2] = hi ? h / 6.0 : 0.0;
+    m[1] = cnt * h / 3.0;
+    st[0] = lo ? -1.0 / h : 0.0;
+    st[2] = hi ? -1.0 / h : 0.0;
+    st[1] = cnt / h;
+}
+
+__global__ void k_tensor_op(int nx, int ny, int nt, double dx, double dt, double dxx, double dtt,
+                            const double* __restrict__ x, double* __restrict__ y,
+                            const double* __restrict__ b, const double* __restrict__ invd,
+                            const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const long long rowp = nx + 1;
+    const long long P = rowp * (ny + 1);
+    const long long N = P * (nt + 1);
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < N;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int n = (int)(idx / P);
+        const long long r = idx - n * P;
+        const int j = (int)(r / rowp), i = (int)(r - (long long)j * rowp);
+        double mx[3], sx[3], my[3], sy[3], mt[3], stt[3];
+        w1d(i, nx, dx, mx, sx);
+        w1d(j, ny, dx, my, sy);
+        w1d(n, nt, dt, mt, stt);
+        double acc = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            if (mt[a] == 0.0) continue;
+            for (int c = 0; c < 3; ++c) {
+                if (my[c] == 0.0) continue;
+                const double* xp = x + idx + (long long)(a - 1) * P + (long long)(c - 1) * rowp;
+                for (int d = 0; d < 3; ++d) {
+                    if (mx[d] == 0.0) continue;
+                    const double w = dxx * (mt[a] * my[c] * sx[d] + mt[a] * sy[c] * mx[d]) +
+                                     dtt * stt[a] * my[c] * mx[d] + mt[a] * my[c] * mx[d];
+                    acc += w * xp[d - 1];
+                }
+            }
+        }
+        double v = b ? b[idx] - acc : acc;
+        if (invd) v *= invd[idx];
+        y[idx] = v;
+    }
+}
+
+void launch_tensor_op(hipStream_t s, int nx, int ny, int nt, double dx, double dt, double dxx,
+                      double dtt, const double* x, double* y, const double* b, const double* invd,
+                      const int* skip) {
+    const long long N = (long long)(nx + 1) * (ny + 1) * (nt + 1);
+    long long nb = (N + 255) / 256;
+    if (nb > 65535) nb = 65535;
+    hipLaunchKernelGGL(k_tensor_op, dim3((unsigned)nb), dim3(256), 0, s, nx, ny, nt, dx, dt, dxx,
+                       dtt, x, y, b, invd, skip);
+}
+
+__global__ void k_tensor_invdiag(int nx, int ny, int nt, double dx, double dt, double dxx,
+                                 double dtt, double* __restrict__ invd) {
+    const long long rowp = nx + 1;
+    const long long P = rowp * (ny + 1);
+    const long long N = P * (nt + 1);
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < N;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int n = (int)(idx / P);
+        const long long r = idx - n * P;
+        const int j = (int)(r / rowp), i = (int)(r - (long long)j * rowp);
+        double mx[3], sx[3], my[3], sy[3], mt[3], stt[3];
+        w1d(i, nx, dx, mx, sx);
+        w1d(j, ny, dx, my, sy);
+        w1d(n, nt, dt, mt, stt);
+        const double d = dxx * (mt[1] * my[1] * sx[1] + mt[1] * sy[1] * mx[1]) +
+                         dtt * stt[1] * my[1] * mx[1] + mt[1] * my[1] * mx[1];
+        invd[idx] = 1.0 / d;
+    }
+}
+
+void launch_tensor_invdiag(hipStream_t s, int nx, int ny, int nt, double dx, double dt,
+                           double dxx, double dtt, double* invd) {
+    const long long N = (long long)(nx + 1) * (ny + 1) * (nt + 1);
+    long long nb = (N + 255) / 256;
+    if (nb > 65535) nb = 65535;
+    hipLaunchKernelGGL(k_tensor_invdiag, dim3((unsigned)nb), dim3(256), 0, s, nx, ny, nt, dx, dt,
+                       dxx, dtt, invd);
+}
+
+// Element -> node: nodal[a] = w * sum of the element values around a.
+__global__ void k_elem_to_node(int nx, int ny, int nt, double w, const double* __restrict__ e,
+                               double* __restrict__ nodal) {
+    const long long rowp = nx + 1;
+    const long long P = rowp * (ny + 1);
+    const long long N = P * (nt + 1);
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < N;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int n = (int)(idx / P);
+        const long long r = idx - n * P;
+        const int j = (int)(r / rowp), i = (int)(r - (long long)j * rowp);
+        double acc = 0.0;
+        for (int en = n - 1; en <= n; ++en) {
+            if (en < 0 || en >= nt) continue;
+            for (int ej = j - 1; ej <= j; ++ej) {
+                if (ej < 0 || ej >= ny) continue;
+                for (int ei = i - 1; ei <= i; ++ei) {
+                    if (ei < 0 || ei >= nx) continue;
+                    acc += e[((long long)en * ny + ej) * nx + ei];
+                }
+            }
+        }
+        nodal[idx] = w * acc;
+    }
+}
+
+void launch_elem_to_node(hipStream_t s, int nx, int ny, int nt, double w, const double* e,
+                         double* nodal) {
+    const long long N = (long long)(nx + 1) * (ny + 1) * (nt + 1);
+    long long nb = (N + 255) / 256;
+    if (nb > 65535) nb = 65535;
+    hipLaunchKernelGGL(k_elem_to_node, dim3((unsigned)nb), dim3(256), 0, s, nx, ny, nt, w, e,
+                       nodal);
+}
+
+// Node -> element: mean of the element's 8 nodal values.
+__global__ void k_node_to_elem(int nx, int ny, int nt, const double* __restrict__ nodal,
+                               double* __restrict__ e) {
+    const long long rowp = nx + 1;
+    const long long P = rowp * (ny + 1);
+    const long long NE = (long long)nx * ny * nt;
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < NE;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const long long sl = (long long)nx * ny;
+        const int n = (int)(idx / sl);
+        const long long r = idx - n * sl;
+        const int j = (int)(r / nx), i = (int)(r - (long long)j * nx);
+        const long long c = (long long)n * P + (long long)j * rowp + i;
+        const double s = nodal[c] + nodal[c + 1] + nodal[c + rowp] + nodal[c + rowp + 1] +
+                         nodal[c + P] + nodal[c + P + 1] + nodal[c + P + rowp] +
+                         nodal[c + P + rowp + 1];
+        e[idx] = 0.125 * s;
+    }
+}
+
+void launch_node_to_elem(hipStream_t s, int nx, int ny, int nt, const double* nodal, double* e) {
+    const long long NE = (long long)nx * ny * nt;
+    long long nb = (NE + 255) / 256;
+    if (nb > 65535) nb = 65535;
+    hipLaunchKernelGGL(k_node_to_elem, dim3((unsigned)nb), dim3(256), 0, s, nx, ny, nt, nodal, e);
+}
+
+}  // namespace st

@@ -1,0 +1,674 @@
+// Krylov kernels: classical Gram-Schmidt projections, vector updates, Givens
+// rotations and the least-squares solve of GMRES (Saad & Schultz) and FGMRES
+// (Saad), all with the small scalar work on the device (paper §3.2).
+//
+// Reductions are deterministic: every block reduces its threads in a fixed
+// tree, writes one partial per quantity, and the last block to arrive (an
+// arrival counter) sums the partials in block order and finalises.  The grid
+// size depends only on the vector length, so two runs give bitwise equal sums.
+//
+// Basis vectors are stored unnormalised; KState::scale[d] = 1/||w_d|| turns
+// them into the orthonormal v_d inside the scalar coefficients, so no pass is
+// spent on normalising a vector.
+#include "st_internal.hpp"
+
+namespace st {
+
+static inline unsigned red_grid(long long n) {
+    long long nb = (n + 4LL * VEC_THREADS - 1) / (4LL * VEC_THREADS);
+    if (nb < 1) nb = 1;
+    if (nb > RED_BLOCKS) nb = RED_BLOCKS;
+    return (unsigned)nb;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+template <typename T> __device__ __forceinline__ double ldd(const T* p) { return (double)*p; }
+
+// ---------------------------------------------------------------------------
+// Scalar finalisation (thread 0 of the last block).
+__device__ void kstate_solve_y(KState* ks) {
+    const int k = ks->k;
+    for (int i = k - 1; i >= 0; --i) {
+        double v = ks->g[i];
+        for (int c = i + 1; c < k; ++c) v -= ks->H[i][c] * ks->y[c];
+        const double d = ks->H[i][i];
+        ks->y[i] = d != 0.0 ? v / d : 0.0;
+    }
+    if (ks->scale_update)
+        for (int i = 0; i < k; ++i) ks->y[i] *= ks->scale[i];
+}
+
+__device__ void kstate_finalize(KState* ks, int mode, int j, const double* sums, int nd) {
+    switch (mode) {
+    case FIN_INIT_SELF:
+    case FIN_INIT_REF: {
+        const double beta = sqrt(sums[0]);
+        ks->beta = beta;
+        if (mode == FIN_INIT_SELF) ks->ref = beta;
+        ks->g[0] = beta;
+        ks->scale[0] = beta > 0.0 ? 1.0 / beta : 0.0;
+        ks->k = 0;
+        ks->est = beta;
+        ks->bad = !isfinite(beta);
+        ks->done = (beta == 0.0) || ks->bad || (mode == FIN_INIT_REF && beta <= ks->rtol * ks->ref);
+        break;
+    }
+    case FIN_PROJ1:
+        for (int d = 0; d < nd; ++d) {
+            const double h = sums[d] * ks->scale[d];
+            ks->hcol[d] = h;
+            ks->coef[d] = h * ks->scale[d];
+        }
+        break;
+    case FIN_PROJ2:
+        for (int d = 0; d < nd; ++d) {
+            const double h = sums[d] * ks->scale[d];
+            ks->hcol[d] += h;
+            ks->coef[d] = h * ks->scale[d];
+        }
+        break;
+    case FIN_GIVENS: {
+        // Column j of the Hessenberg matrix is rotated in place in ks->H.
+        const double hn = sqrt(sums[0]);
+        double hnorm2 = hn * hn;
+        for (int i = 0; i <= j; ++i) {
+            const double v = ks->hcol[i];
+            ks->H[i][j] = v;
+            hnorm2 += v * v;
+        }
+        for (int i = 0; i < j; ++i) {
+            const double a = ks->H[i][j], b = ks->H[i + 1][j];
+            ks->H[i][j] = ks->cs[i] * a + ks->sn[i] * b;
+            ks->H[i + 1][j] = -ks->sn[i] * a + ks->cs[i] * b;
+        }
+        const double hj = ks->H[j][j];
+        const double r = hypot(hj, hn);
+        double c = 1.0, sn = 0.0;
+        if (r != 0.0) {
+            c = hj / r;
+            sn = hn / r;
+        }
+        ks->cs[j] = c;
+        ks->sn[j] = sn;
+        ks->H[j][j] = r;
+        ks->g[j + 1] = -sn * ks->g[j];
+        ks->g[j] = c * ks->g[j];
+        ks->scale[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+        ks->k = j + 1;
+        ks->est = fabs(ks->g[j + 1]);
+        const bool bad = !isfinite(ks->est) || !isfinite(hn);
+        const bool conv = ks->est <= ks->rtol * ks->ref;
+        const bool brk = hn <= 1e-14 * sqrt(hnorm2);
+        ks->bad |= bad;
+        if (conv || brk || bad || ks->k >= ks->maxit) {
+            ks->done = 1;
+            kstate_solve_y(ks);
+        }
+        break;
+    }
+    default:
+        break;
+    }
+}
+
+// Block reduction of MAXD accumulators into partials[blockIdx][.], then the
+// last block reduces the partials and finalises.  Returns nothing; must be
+// called by every thread of every block.
+template <int MAXD>
+__device__ void block_finish(double (&acc)[MAXD], int nd, double* __restrict__ partials,
+                             KState* ks, int mode, int j, double* out) {
+    __shared__ double red[VEC_THREADS / 64][MAXD];
+    __shared__ double sums[MAXD];
+    __shared__ int amlast;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 0; d < MAXD; ++d) {
+        if (d < nd) {
+            const double v = wave_sum(acc[d]);
+            if (lane == 0) red[wave][d] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < nd) {
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < VEC_THREADS / 64; ++w) v += red[w][threadIdx.x];
+        partials[(long long)blockIdx.x * MAXD + threadIdx.x] = v;
+    }
+    __threadfence();
+    __syncthreads();
+    unsigned* counter = ks ? &ks->counter : (unsigned*)(partials + (long long)RED_BLOCKS * KMAX + KMAX);
+    if (threadIdx.x == 0) {
+        const unsigned prev = atomicAdd(counter, 1u);
+        amlast = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!amlast) return;
+    __threadfence();
+    const int nb = gridDim.x;
+    for (int d = wave; d < nd; d += VEC_THREADS / 64) {
+        double v = 0.0;
+        for (int b = lane; b < nb; b += 64) v += partials[(long long)b * MAXD + d];
+        v = wave_sum(v);
+        if (lane == 0) sums[d] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (ks) {
+            kstate_finalize(ks, mode, j, sums, nd);
+        } else {
+            for (int d = 0; d < nd; ++d) out[d] = sums[d];
+        }
+        *counter = 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// w = invd .* b (invd optional), ||w||^2 -> FIN_INIT_*.
+template <typename T>
+__global__ __launch_bounds__(VEC_THREADS) void k_scale_norm(long long n, const T* __restrict__ b,
+                                                            const T* __restrict__ invd,
+                                                            T* __restrict__ w,
+                                                            double* __restrict__ partials,
+                                                            KState* ks, int mode) {
+    double acc[1] = {0.0};
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        T v = b[i];
+        if (invd) v *= invd[i];
+        w[i] = v;
+        acc[0] += (double)v * (double)v;
+    }
+    block_finish<1>(acc, 1, partials, ks, mode, 0, nullptr);
+}
+
+__global__ void k_init_state(KState* ks, int maxit, double rtol, int scale_update,
+                             const double* ref) {
+    if (threadIdx.x == 0) {
+        ks->maxit = maxit;
+        ks->rtol = rtol;
+        ks->scale_update = scale_update;
+        ks->done = 0;
+        ks->bad = 0;
+        ks->k = 0;
+        ks->counter = 0u;
+        if (ref) ks->ref = *ref;
+    }
+}
+
+void launch_init_state(hipStream_t s, KState* ks, int maxit, double rtol, int scale_update,
+                       const double* ref) {
+    hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, ks, maxit, rtol, scale_update, ref);
+}
+
+void launch_scale_norm(hipStream_t s, long long n, int prec, const void* b, const void* invd,
+                       void* w, double* partials, KState* ks, int mode, int maxit, double rtol,
+                       int scale_update) {
+    (void)maxit;
+    (void)rtol;
+    (void)scale_update;
+    const unsigned nb = red_grid(n);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_scale_norm<double>, dim3(nb), dim3(VEC_THREADS), 0, s, n,
+                           (const double*)b, (const double*)invd, (double*)w, partials, ks, mode);
+    else
+        hipLaunchKernelGGL(k_scale_norm<float>, dim3(nb), dim3(VEC_THREADS), 0, s, n,
+                           (const float*)b, (const float*)invd, (float*)w, partials, ks, mode);
+}
+
+// ---------------------------------------------------------------------------
+// Multi-dot: h_d = <V_d, w>, d < nd (mode FIN_PROJ1 / FIN_INIT_*).
+template <typename TW, typename TV, int MAXD>
+__global__ __launch_bounds__(VEC_THREADS) void k_mdot(long long n, const TW* __restrict__ w,
+                                                      const TV* __restrict__ V, long long ldv,
+                                                      int nd, double* __restrict__ partials,
+                                                      KState* ks, int mode, int j) {
+    if (ks && ks->done) return;
+    double acc[MAXD];
+#pragma unroll
+    for (int d = 0; d < MAXD; ++d) acc[d] = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double wv = (double)w[i];
+#pragma unroll
+        for (int d = 0; d < MAXD; ++d)
+            if (d < nd) acc[d] += (double)V[(long long)d * ldv + i] * wv;
+    }
+    block_finish<MAXD>(acc, nd, partials, ks, mode, j, nullptr);
+}
+
+// w -= sum_d coef_d V_d, then either ||w||^2 (FIN_GIVENS) or the
+// re-orthogonalisation projections <V_d, w> (FIN_PROJ2).
+template <typename TW, typename TV, int MAXD>
+__global__ __launch_bounds__(VEC_THREADS) void k_maxpy(long long n, TW* __restrict__ w,
+                                                       const TV* __restrict__ V, long long ldv,
+                                                       int nd, double* __restrict__ partials,
+                                                       KState* ks, int mode, int j) {
+    if (ks->done) return;
+    __shared__ double c[MAXD];
+    if (threadIdx.x < MAXD) c[threadIdx.x] = (int)threadIdx.x < nd ? ks->coef[threadIdx.x] : 0.0;
+    __syncthreads();
+    double acc[MAXD];
+#pragma unroll
+    for (int d = 0; d < MAXD; ++d) acc[d] = 0.0;
+    const bool redot = mode == FIN_PROJ2;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        double wv = (double)w[i];
+#pragma unroll
+        for (int d = 0; d < MAXD; ++d)
+            if (d < nd) wv -= c[d] * (double)V[(long long)d * ldv + i];
+        const TW wo = (TW)wv;
+        w[i] = wo;
+        const double wr = (double)wo;
+        if (redot) {
+#pragma unroll
+            for (int d = 0; d < MAXD; ++d)
+                if (d < nd) acc[d] += (double)V[(long long)d * ldv + i] * wr;
+        } else {
+            acc[0] += wr * wr;
+        }
+    }
+    block_finish<MAXD>(acc, redot ? nd : 1, partials, ks, mode, j, nullptr);
+}
+
+template <int MAXD>
+static void mdot_dispatch(hipStream_t s, long long n, int pw, int pv, const void* w,
+                          const void* V, long long ldv, int nd, double* partials, KState* ks,
+                          int mode, int j) {
+    const unsigned nb = red_grid(n);
+    if (pw == 0 && pv == 0)
+        hipLaunchKernelGGL((k_mdot<double, double, MAXD>), dim3(nb), dim3(VEC_THREADS), 0, s, n,
+                           (const double*)w, (const double*)V, ldv, nd, partials, ks, mode, j);
+    else if (pw == 1 && pv == 1)
+        hipLaunchKernelGGL((k_mdot<float, float, MAXD>), dim3(nb), dim3(VEC_THREADS), 0, s, n,
+                           (const float*)w, (const float*)V, ldv, nd, partials, ks, mode, j);
+    else if (pw == 0 && pv == 1)
+        hipLaunchKernelGGL((k_mdot<double, float, MAXD>), dim3(nb), dim3(VEC_THREADS), 0, s, n,
+                           (const double*)w, (const float*)V, ldv, nd, partials, ks, mode, j);
+    else
+        hipLaunchKernelGGL((k_mdot<float, double, MAXD>), dim3(nb), dim3(VEC_THREADS), 0, s, n,
+                           (const float*)w, (const double*)V, ldv, nd, partials, ks, mode, j);
+}
+
+void launch_mdot(hipStream_t s, long long n, int prec_w, int prec_v, const void* w,
+                 const void* V, long long ldv, int nd, double* partials, KState* ks, int mode,
+                 int j, int maxd) {
+    if (maxd <= 1)
+        mdot_dispatch<1>(s, n, prec_w, prec_v, w, V, ldv, nd, partials, ks, mode, j);
+    else if (maxd <= SMAX)
+        mdot_dispatch<SMAX>(s, n, prec_w, prec_v, w, V, ldv, nd, partials, ks, mode, j);
+    else
+        mdot_dispatch<KMAX>(s, n, prec_w, prec_v, w, V, ldv, nd, partials, ks, mode, j);
+}
+
+template <int MAXD>
+static void maxpy_dispatch(hipStream_t s, long long n, int pw, int pv, void* w, const void* V,
+                           long long ldv, int nd, double* partials, KState* ks, int mode, int j) {
+    const unsigned nb = red_grid(n);
+    if (pw == 0 && pv == 0)
+        hipLaunchKernelGGL((k_maxpy<double, double, MAXD>), dim3(nb), dim3(VEC_THREADS), 0, s, n,
+                           (double*)w, (const double*)V, ldv, nd, partials, ks, mode, j);
+    else
+        hipLaunchKernelGGL((k_maxpy<float, float, MAXD>), dim3(nb), dim3(VEC_THREADS), 0, s, n,
+                           (float*)w, (const float*)V, ldv, nd, partials, ks, mode, j);
+}
+
+void launch_maxpy(hipStream_t s, long long n, int prec_w, int prec_v, void* w, const void* V,
+                  long long ldv, int nd, double* partials, KState* ks, int mode, int j, int maxd) {
+    if (maxd <= SMAX)
+        maxpy_dispatch<SMAX>(s, n, prec_w, prec_v, w, V, ldv, nd, partials, ks, mode, j);
+    else
+        maxpy_dispatch<KMAX>(s, n, prec_w, prec_v, w, V, ldv, nd, partials, ks, mode, j);
+}
+
+// x = (zero ? 0 : x) + sum_{d < k} y_d V_d.
+template <typename TX, typename TV>
+__global__ __launch_bounds__(VEC_THREADS) void k_update(long long n, TX* __restrict__ x,
+                                                        const TV* __restrict__ V, long long ldv,
+                                                        const KState* __restrict__ ks,
+                                                        int zero_x0) {
+    const int k = ks->k;
+    if (k == 0 && !zero_x0) return;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        double v = zero_x0 ? 0.0 : (double)x[i];
+        for (int d = 0; d < k; ++d) v += ks->y[d] * (double)V[(long long)d * ldv + i];
+        x[i] = (TX)v;
+    }
+}
+
+void launch_update(hipStream_t s, long long n, int prec_x, int prec_v, void* x, const void* V,
+                   long long ldv, KState* ks, int zero_x0, int maxd) {
+    (void)maxd;
+    long long nb = (n + VEC_THREADS - 1) / VEC_THREADS;
+    if (nb > 65535) nb = 65535;
+    if (prec_x == 0 && prec_v == 0)
+        hipLaunchKernelGGL((k_update<double, double>), dim3((unsigned)nb), dim3(VEC_THREADS), 0, s,
+                           n, (double*)x, (const double*)V, ldv, ks, zero_x0);
+    else if (prec_x == 0 && prec_v == 1)
+        hipLaunchKernelGGL((k_update<double, float>), dim3((unsigned)nb), dim3(VEC_THREADS), 0, s,
+                           n, (double*)x, (const float*)V, ldv, ks, zero_x0);
+    else
+        hipLaunchKernelGGL((k_update<float, float>), dim3((unsigned)nb), dim3(VEC_THREADS), 0, s,
+                           n, (float*)x, (const float*)V, ldv, ks, zero_x0);
+}
+
+// Plain dot product into out[0] (deterministic).
+__global__ __launch_bounds__(VEC_THREADS) void k_dot(long long n, const double* __restrict__ a,
+                                                     const double* __restrict__ b,
+                                                     double* __restrict__ partials,
+                                                     double* __restrict__ out) {
+    double acc[1] = {0.0};
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        acc[0] += a[i] * b[i];
+    block_finish<1>(acc, 1, partials, nullptr, FIN_SUM, 0, out);
+}
+
+void launch_dot(hipStream_t s, long long n, const double* a, const double* b, double* partials,
+                double* out) {
+    hipLaunchKernelGGL(k_dot, dim3(red_grid(n)), dim3(VEC_THREADS), 0, s, n, a, b, partials, out);
+}
+
+// ---------------------------------------------------------------------------
+// Coarsest level: Jacobi-preconditioned GMRES(restart), at most maxit
+// iterations, stopping at rtol times the initial preconditioned residual, in
+// FP64, in one workgroup (§3.2: the coarse grid solver).
+constexpr int CT = 1024;
+
+__device__ __forceinline__ double block_sum_1(double v, double* sh) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < CT / 64; ++w) t += sh[w];
+        sh[CT / 64] = t;
+    }
+    __syncthreads();
+    return sh[CT / 64];
+}
+
+template <typename TIO>
+__global__ __launch_bounds__(CT) void k_coarse_gmres(
+    int nx, int ny, int nt, int nplanes, const double* __restrict__ st,
+    const int* __restrict__ pmap, const double* __restrict__ invd, const TIO* __restrict__ bio,
+    TIO* __restrict__ xio, double* __restrict__ V, double* __restrict__ work, int maxit,
+    int restart, double rtol, int zero_x0, int trans) {
+    const long long row = nx + 1, P = row * (ny + 1), n = P * (nt + 1);
+    const long long DS = P * nplanes;
+    double* x = work;
+    double* w = work + n;
+    __shared__ double H[KMAX + 1][KMAX];
+    __shared__ double cs[KMAX], sn[KMAX], g[KMAX + 1], y[KMAX], h[KMAX + 1];
+    __shared__ double sh[CT / 64 + 1];
+    __shared__ int flag;
+    const int tid = threadIdx.x;
+
+    auto apply = [&](const double* in, long long idx) -> double {
+        const int nn0 = (int)(idx / P);
+        const long long r = idx - nn0 * P;
+        const int j = (int)(r / row), i = (int)(r - (long long)j * row);
+        double acc = 0.0;
+        for (int dn = -1; dn <= 1; ++dn) {
+            const int nn = nn0 + dn;
+            if (nn < 0 || nn > nt) continue;
+            for (int dj = -1; dj <= 1; ++dj) {
+                const int jj = j + dj;
+                if (jj < 0 || jj > ny) continue;
+                for (int di = -1; di <= 1; ++di) {
+                    const int ii = i + di;
+                    if (ii < 0 || ii > nx) continue;
+                    const int d = (dn + 1) * 9 + (dj + 1) * 3 + (di + 1);
+                    const long long nb = (long long)nn * P + (long long)jj * row + ii;
+                    const double a = trans ? st[(long long)(26 - d) * DS + (long long)pmap[nn] * P +
+                                                (long long)jj * row + ii]
+                                           : st[(long long)d * DS + (long long)pmap[nn0] * P + r];
+                    acc += a * in[nb];
+                }
+            }
+        }
+        return acc;
+    };
+
+    for (long long i = tid; i < n; i += CT) x[i] = zero_x0 ? 0.0 : (double)xio[i];
+    __syncthreads();
+    // r0 = D^-1 (b - A x) into V[0]
+    double loc = 0.0;
+    for (long long i = tid; i < n; i += CT) {
+        const double v = invd[i] * ((double)bio[i] - (zero_x0 ? 0.0 : apply(x, i)));
+        V[i] = v;
+        loc += v * v;
+    }
+    double beta = sqrt(block_sum_1(loc, sh));
+    const double ref = beta;
+    int its = 0;
+    bool finished = !(beta > 0.0) || !isfinite(beta);
+    while (!finished) {
+        for (long long i = tid; i < n; i += CT) V[i] *= 1.0 / beta;
+        if (tid < KMAX + 1) g[tid] = 0.0;
+        __syncthreads();
+        if (tid == 0) g[0] = beta;
+        int k = 0;
+        bool stop = false;
+        for (int jcol = 0; jcol < restart && !stop; ++jcol) {
+            const double* vj = V + (long long)jcol * n;
+            __syncthreads();
+            for (long long i = tid; i < n; i += CT) w[i] = invd[i] * apply(vj, i);
+            __syncthreads();
+            // projections h_d = <v_d, w>, d <= jcol: 32 threads per d
+            {
+                const int d = tid >> 5, q = tid & 31;
+                double a = 0.0;
+                if (d <= jcol)
+                    for (long long i = q; i < n; i += 32) a += V[(long long)d * n + i] * w[i];
+#pragma unroll
+                for (int o = 16; o > 0; o >>= 1) a += __shfl_down(a, o, 32);
+                if (q == 0 && d <= jcol) h[d] = a;
+            }
+            __syncthreads();
+            loc = 0.0;
+            for (long long i = tid; i < n; i += CT) {
+                double v = w[i];
+                for (int d = 0; d <= jcol; ++d) v -= h[d] * V[(long long)d * n + i];
+                w[i] = v;
+                loc += v * v;
+            }
+            const double hn = sqrt(block_sum_1(loc, sh));
+            if (tid == 0) {
+                // rotate column jcol in place in shared H
+                double hn2 = hn * hn;
+                for (int i = 0; i <= jcol; ++i) {
+                    H[i][jcol] = h[i];
+                    hn2 += h[i] * h[i];
+                }
+                for (int i = 0; i < jcol; ++i) {
+                    const double a = H[i][jcol], bb = H[i + 1][jcol];
+                    H[i][jcol] = cs[i] * a + sn[i] * bb;
+                    H[i + 1][jcol] = -sn[i] * a + cs[i] * bb;
+                }
+                const double hj = H[jcol][jcol];
+                const double r = hypot(hj, hn);
+                double c = 1.0, s_ = 0.0;
+                if (r != 0.0) {
+                    c = hj / r;
+                    s_ = hn / r;
+                }
+                cs[jcol] = c;
+                sn[jcol] = s_;
+                H[jcol][jcol] = r;
+                g[jcol + 1] = -s_ * g[jcol];
+                g[jcol] = c * g[jcol];
+                const double est = fabs(g[jcol + 1]);
+                int f = 0;
+                if (est <= rtol * ref) f = 1;
+                if (hn <= 1e-14 * sqrt(hn2) || !isfinite(est)) f = 2;
+                if (its + 1 >= maxit) f |= 4;
+                flag = f;
+            }
+            __syncthreads();
+            ++its;
+            k = jcol + 1;
+            const int f = flag;
+            if (f) {
+                stop = true;
+                if (f & 3) finished = true;
+                if (f & 4) finished = true;
+            } else if (jcol + 1 < restart) {
+                for (long long i = tid; i < n; i += CT) V[(long long)(jcol + 1) * n + i] = w[i] / hn;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int i = k - 1; i >= 0; --i) {
+                double v = g[i];
+                for (int c = i + 1; c < k; ++c) v -= H[i][c] * y[c];
+                y[i] = H[i][i] != 0.0 ? v / H[i][i] : 0.0;
+            }
+        }
+        __syncthreads();
+        for (long long i = tid; i < n; i += CT) {
+            double v = x[i];
+            for (int d = 0; d < k; ++d) v += y[d] * V[(long long)d * n + i];
+            x[i] = v;
+        }
+        __syncthreads();
+        if (finished || its >= maxit) break;
+        loc = 0.0;
+        for (long long i = tid; i < n; i += CT) {
+            const double v = invd[i] * ((double)bio[i] - apply(x, i));
+            V[i] = v;
+            loc += v * v;
+        }
+        beta = sqrt(block_sum_1(loc, sh));
+        if (!(beta > 0.0) || !isfinite(beta)) break;
+    }
+    __syncthreads();
+    for (long long i = tid; i < n; i += CT) xio[i] = (TIO)x[i];
+}
+
+void launch_coarse_solve(hipStream_t s, const Level& L, int prec_io, int trans, const void* b,
+                         void* x, double* V, double* work, int maxit, int restart, double rtol,
+                         int zero_x0) {
+    if (prec_io == 0)
+        hipLaunchKernelGGL(k_coarse_gmres<double>, dim3(1), dim3(CT), 0, s, L.nx, L.ny, L.nt,
+                           L.nplanes, L.st64, L.plane_map, L.invd64, (const double*)b, (double*)x,
+                           V, work, maxit, restart, rtol, zero_x0, trans);
+    else
+        hipLaunchKernelGGL(k_coarse_gmres<float>, dim3(1), dim3(CT), 0, s, L.nx, L.ny, L.nt,
+                           L.nplanes, L.st64, L.plane_map, L.invd64, (const float*)b, (float*)x, V,
+                           work, maxit, restart, rtol, zero_x0, trans);
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi-preconditioned conjugate gradients for the filter system, scalars on
+// the device.  scal: [0] rz, [1] alpha, [2] beta, [3] rr, [4] rz_new.
+__global__ __launch_bounds__(VEC_THREADS) void k_cg_pq(long long n, const double* __restrict__ p,
+                                                       const double* __restrict__ q,
+                                                       double* __restrict__ partials,
+                                                       double* __restrict__ scal) {
+    double acc[1] = {0.0};
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        acc[0] += p[i] * q[i];
+    block_finish<1>(acc, 1, partials, nullptr, FIN_SUM, 0, scal + 5);
+}
+
+__global__ __launch_bounds__(VEC_THREADS) void k_cg_update(
+    long long n, double* __restrict__ x, double* __restrict__ r, double* __restrict__ z,
+    const double* __restrict__ p, const double* __restrict__ q, const double* __restrict__ invd,
+    double* __restrict__ partials, double* __restrict__ scal) {
+    const double alpha = scal[0] / scal[5];
+    double acc[2] = {0.0, 0.0};
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        x[i] += alpha * p[i];
+        const double rv = r[i] - alpha * q[i];
+        r[i] = rv;
+        const double zv = invd[i] * rv;
+        z[i] = zv;
+        acc[0] += rv * zv;
+        acc[1] += rv * rv;
+    }
+    block_finish<2>(acc, 2, partials, nullptr, FIN_SUM, 0, scal + 6);
+}
+
+__global__ void k_cg_p(long long n, const double* __restrict__ z, double* __restrict__ p,
+                       double* __restrict__ scal, int first) {
+    const double beta = first ? 0.0 : scal[6] / scal[0];
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = z[i] + beta * p[i];
+    // rz <- rz_new after every thread has read the old value: done by the host
+    // through step 3 (below) on the next launch.
+}
+
+// r = b, z = invd .* b, p = z; sums r.z, r.r -> scal[6], scal[7].
+__global__ __launch_bounds__(VEC_THREADS) void k_cg_init(long long n, const double* __restrict__ b,
+                                                         double* __restrict__ r,
+                                                         double* __restrict__ z,
+                                                         double* __restrict__ p,
+                                                         const double* __restrict__ invd,
+                                                         double* __restrict__ partials,
+                                                         double* __restrict__ scal) {
+    double acc[2] = {0.0, 0.0};
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double rv = b[i];
+        const double zv = invd[i] * rv;
+        r[i] = rv;
+        z[i] = zv;
+        p[i] = zv;
+        acc[0] += rv * zv;
+        acc[1] += rv * rv;
+    }
+    block_finish<2>(acc, 2, partials, nullptr, FIN_SUM, 0, scal + 6);
+}
+
+__global__ void k_cg_roll(double* scal) {
+    if (threadIdx.x == 0) {
+        scal[0] = scal[6];
+        scal[3] = scal[7];
+    }
+}
+
+void launch_cg_step(hipStream_t s, int step, long long n, double* x, double* r, double* z,
+                    double* p, const double* q, const double* invd, double* partials,
+                    double* scal, const int* skip) {
+    (void)skip;
+    const unsigned nb = red_grid(n);
+    long long nb2 = (n + VEC_THREADS - 1) / VEC_THREADS;
+    if (nb2 > 65535) nb2 = 65535;
+    switch (step) {
+    case 0:   // p . q
+        hipLaunchKernelGGL(k_cg_pq, dim3(nb), dim3(VEC_THREADS), 0, s, n, p, q, partials, scal);
+        break;
+    case 1:   // x, r, z updates and r.z, r.r
+        hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(VEC_THREADS), 0, s, n, x, r, z, p, q, invd,
+                           partials, scal);
+        break;
+    case 2:   // p = z + beta p
+        hipLaunchKernelGGL(k_cg_p, dim3((unsigned)nb2), dim3(VEC_THREADS), 0, s, n, z, p, scal, 0);
+        break;
+    case 3:   // p = z (first iteration)
+        hipLaunchKernelGGL(k_cg_p, dim3((unsigned)nb2), dim3(VEC_THREADS), 0, s, n, z, p, scal, 1);
+        break;
+    case 4:   // roll scalars
+        hipLaunchKernelGGL(k_cg_roll, dim3(1), dim3(64), 0, s, scal);
+        break;
+    case 5:   // init from b (= q argument): r = b, z = p = invd .* b
+        hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(VEC_THREADS), 0, s, n, q, r, z, p, invd,
+                           partials, scal);
+        break;
+    }
+}
+
+}  // namespace st

@@ -1,0 +1,547 @@
+// Coarse-level kernels of the space-time multigrid hierarchy (paper §3.2):
+// 27-point stencil application and its transpose, masked trilinear restriction
+// (P_m^T) and prolongation (P_m) for space and time semi-coarsening (§3.2.1),
+// coarse Dirichlet masks, and the pieces of the Galerkin construction
+// A_{l+1} = P_m^T A_l P_m by probing with 27 colours.
+//
+// Stencil layout: st[d][plane][j][i], d = (dn+1)*9 + (dj+1)*3 + (di+1) holds
+// A(node, node + (di, dj, dn)); plane = plane_map[n] so that time levels with
+// identical rows share storage.
+#include "st_internal.hpp"
+
+namespace st {
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+    return __uint_as_float(((unsigned)h) << 16);
+}
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    unsigned u = __float_as_uint(f);
+    const unsigned lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;   // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+template <typename S> __device__ __forceinline__ float ld_st(const S* p);
+template <> __device__ __forceinline__ float ld_st<float>(const float* p) { return *p; }
+template <> __device__ __forceinline__ float ld_st<uint16_t>(const uint16_t* p) {
+    return bf16_to_f32(*p);
+}
+
+static inline unsigned grid_for(long long n, int threads = 256, long long cap = 65535) {
+    long long nb = (n + threads - 1) / threads;
+    if (nb < 1) nb = 1;
+    if (nb > cap) nb = cap;
+    return (unsigned)nb;
+}
+
+// ---------------------------------------------------------------------------
+// y = A x (or A^T x) with the same epilogue as the fine apply:
+//   v = A x;  if b: v = b - v;  if invd: v *= invd;  v *= scale.
+template <typename T, typename S, typename TC, bool TRANS>
+__global__ __launch_bounds__(256) void k_stencil_apply(
+    int nx, int ny, int nt, int nplanes, const S* __restrict__ st, const int* __restrict__ pmap,
+    const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ b,
+    const T* __restrict__ invd, const double* __restrict__ scale, const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const long long rowp = nx + 1;
+    const long long P = rowp * (ny + 1);
+    const long long N = P * (nt + 1);
+    const long long DS = P * nplanes;   // stride between stencil entries
+    const TC sc = scale ? (TC)(*scale) : (TC)1;
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < N;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int n = (int)(idx / P);
+        const long long r = idx - n * P;
+        const int j = (int)(r / rowp), i = (int)(r - (long long)j * rowp);
+        TC acc = 0;
+#pragma unroll
+        for (int dn = -1; dn <= 1; ++dn) {
+            const int nn = n + dn;
+            if (nn < 0 || nn > nt) continue;
+            const long long pl = TRANS ? (long long)pmap[nn] * P : (long long)pmap[n] * P;
+#pragma unroll
+            for (int dj = -1; dj <= 1; ++dj) {
+                const int jj = j + dj;
+                if (jj < 0 || jj > ny) continue;
+#pragma unroll
+                for (int di = -1; di <= 1; ++di) {
+                    const int ii = i + di;
+                    if (ii < 0 || ii > nx) continue;
+                    const int d = (dn + 1) * 9 + (dj + 1) * 3 + (di + 1);
+                    const long long nb = (long long)nn * P + (long long)jj * rowp + ii;
+                    TC a;
+                    if (TRANS)
+                        a = (TC)st[(long long)(26 - d) * DS + pl + (long long)jj * rowp + ii];
+                    else
+                        a = (TC)st[(long long)d * DS + pl + r];
+                    acc += a * (TC)x[nb];
+                }
+            }
+        }
+        TC v = acc;
+        if (b) v = (TC)b[idx] - v;
+        if (invd) v *= (TC)invd[idx];
+        y[idx] = (T)(v * sc);
+    }
+}
+
+// BF16 storage variant (FP32 arithmetic).
+template <bool TRANS>
+__global__ __launch_bounds__(256) void k_stencil_apply_bf16(
+    int nx, int ny, int nt, int nplanes, const uint16_t* __restrict__ st,
+    const int* __restrict__ pmap, const float* __restrict__ x, float* __restrict__ y,
+    const float* __restrict__ b, const float* __restrict__ invd, const double* __restrict__ scale,
+    const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const long long rowp = nx + 1;
+    const long long P = rowp * (ny + 1);
+    const long long N = P * (nt + 1);
+    const long long DS = P * nplanes;
+    const float sc = scale ? (float)(*scale) : 1.0f;
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < N;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int n = (int)(idx / P);
+        const long long r = idx - n * P;
+        const int j = (int)(r / rowp), i = (int)(r - (long long)j * rowp);
+        float acc = 0.0f;
+#pragma unroll
+        for (int dn = -1; dn <= 1; ++dn) {
+            const int nn = n + dn;
+            if (nn < 0 || nn > nt) continue;
+            const long long pl = TRANS ? (long long)pmap[nn] * P : (long long)pmap[n] * P;
+#pragma unroll
+            for (int dj = -1; dj <= 1; ++dj) {
+                const int jj = j + dj;
+                if (jj < 0 || jj > ny) continue;
+#pragma unroll
+                for (int di = -1; di <= 1; ++di) {
+                    const int ii = i + di;
+                    if (ii < 0 || ii > nx) continue;
+                    const int d = (dn + 1) * 9 + (dj + 1) * 3 + (di + 1);
+                    const long long nb = (long long)nn * P + (long long)jj * rowp + ii;
+                    float a;
+                    if (TRANS)
+                        a = bf16_to_f32(st[(long long)(26 - d) * DS + pl + (long long)jj * rowp + ii]);
+                    else
+                        a = bf16_to_f32(st[(long long)d * DS + pl + r]);
+                    acc += a * x[nb];
+                }
+            }
+        }
+        float v = acc;
+        if (b) v = b[idx] - v;
+        if (invd) v *= invd[idx];
+        y[idx] = v * sc;
+    }
+}
+
+void launch_stencil_apply(hipStream_t s, const Level& L, int prec, int trans, const void* x,
+                          void* y, const void* b, const void* invd, const double* scale,
+                          const int* skip) {
+    const unsigned nb = grid_for(L.nn);
+    if (prec == 0) {
+        auto* xx = (const double*)x;
+        auto* yy = (double*)y;
+        auto* bb = (const double*)b;
+        auto* dd = (const double*)invd;
+        if (trans)
+            hipLaunchKernelGGL((k_stencil_apply<double, double, double, true>), dim3(nb), dim3(256),
+                               0, s, L.nx, L.ny, L.nt, L.nplanes, L.st64, L.plane_map, xx, yy, bb,
+                               dd, scale, skip);
+        else
+            hipLaunchKernelGGL((k_stencil_apply<double, double, double, false>), dim3(nb),
+                               dim3(256), 0, s, L.nx, L.ny, L.nt, L.nplanes, L.st64, L.plane_map,
+                               xx, yy, bb, dd, scale, skip);
+    } else {
+        auto* xx = (const float*)x;
+        auto* yy = (float*)y;
+        auto* bb = (const float*)b;
+        auto* dd = (const float*)invd;
+        if (L.sprec == 2) {
+            if (trans)
+                hipLaunchKernelGGL(k_stencil_apply_bf16<true>, dim3(nb), dim3(256), 0, s, L.nx,
+                                   L.ny, L.nt, L.nplanes, L.st16, L.plane_map, xx, yy, bb, dd,
+                                   scale, skip);
+            else
+                hipLaunchKernelGGL(k_stencil_apply_bf16<false>, dim3(nb), dim3(256), 0, s, L.nx,
+                                   L.ny, L.nt, L.nplanes, L.st16, L.plane_map, xx, yy, bb, dd,
+                                   scale, skip);
+        } else {
+            if (trans)
+                hipLaunchKernelGGL((k_stencil_apply<float, float, float, true>), dim3(nb),
+                                   dim3(256), 0, s, L.nx, L.ny, L.nt, L.nplanes, L.st32,
+                                   L.plane_map, xx, yy, bb, dd, scale, skip);
+            else
+                hipLaunchKernelGGL((k_stencil_apply<float, float, float, false>), dim3(nb),
+                                   dim3(256), 0, s, L.nx, L.ny, L.nt, L.nplanes, L.st32,
+                                   L.plane_map, xx, yy, bb, dd, scale, skip);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Restriction b_c = P_m^T r_f = P^T N_f r_f.  Space: coarse (I, J, n) gathers
+// fine (2I+a, 2J+c, n), a, c in {-1, 0, 1}, weight w(a) w(c) with w(0) = 1,
+// w(+-1) = 1/2.  Time: coarse (i, j, N) gathers fine (i, j, 2N+a).
+template <typename T>
+__global__ void k_restrict(int how, int nxf, int nyf, int ntf, int nxc, int nyc, int ntc,
+                           const uint8_t* __restrict__ maskf, const T* __restrict__ rf,
+                           T* __restrict__ bc) {
+    const long long rowc = nxc + 1, Pc = rowc * (nyc + 1);
+    const long long Nc = Pc * (ntc + 1);
+    const long long rowf = nxf + 1, Pf = rowf * (nyf + 1);
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < Nc;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int n = (int)(idx / Pc);
+        const long long r = idx - n * Pc;
+        const int J = (int)(r / rowc), I = (int)(r - (long long)J * rowc);
+        double acc = 0.0;
+        if (how == 1) {
+            for (int c = -1; c <= 1; ++c) {
+                const int fj = 2 * J + c;
+                if (fj < 0 || fj > nyf) continue;
+                const double wc = c == 0 ? 1.0 : 0.5;
+                for (int a = -1; a <= 1; ++a) {
+                    const int fi = 2 * I + a;
+                    if (fi < 0 || fi > nxf) continue;
+                    const long long f = (long long)n * Pf + (long long)fj * rowf + fi;
+                    if (maskf[f]) continue;
+                    acc += wc * (a == 0 ? 1.0 : 0.5) * (double)rf[f];
+                }
+            }
+        } else {
+            for (int a = -1; a <= 1; ++a) {
+                const int fn = 2 * n + a;
+                if (fn < 0 || fn > ntf) continue;
+                const long long f = (long long)fn * Pf + r;
+                if (maskf[f]) continue;
+                acc += (a == 0 ? 1.0 : 0.5) * (double)rf[f];
+            }
+        }
+        bc[idx] = (T)acc;
+    }
+}
+
+void launch_restrict(hipStream_t s, const Level& F, const Level& C, int prec, const void* rf,
+                     void* bc) {
+    const unsigned nb = grid_for(C.nn);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_restrict<double>, dim3(nb), dim3(256), 0, s, C.how, F.nx, F.ny, F.nt,
+                           C.nx, C.ny, C.nt, F.mask, (const double*)rf, (double*)bc);
+    else
+        hipLaunchKernelGGL(k_restrict<float>, dim3(nb), dim3(256), 0, s, C.how, F.nx, F.ny, F.nt,
+                           C.nx, C.ny, C.nt, F.mask, (const float*)rf, (float*)bc);
+}
+
+// Prolongation x_f (+)= P_m e_c: zero at fine Dirichlet nodes.
+template <typename T>
+__global__ void k_prolong(int how, int nxf, int nyf, int ntf, int nxc, int nyc, int ntc,
+                          const uint8_t* __restrict__ maskf, const T* __restrict__ ec,
+                          T* __restrict__ xf, int accumulate) {
+    const long long rowf = nxf + 1, Pf = rowf * (nyf + 1);
+    const long long Nf = Pf * (ntf + 1);
+    const long long rowc = nxc + 1, Pc = rowc * (nyc + 1);
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < Nf;
+         idx += (long long)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        if (!maskf[idx]) {
+            const int n = (int)(idx / Pf);
+            const long long r = idx - n * Pf;
+            const int j = (int)(r / rowf), i = (int)(r - (long long)j * rowf);
+            if (how == 1) {
+                const int i0 = i >> 1, j0 = j >> 1;
+                const bool io = i & 1, jo = j & 1;
+                const long long base = (long long)n * Pc;
+                if (!io && !jo) {
+                    v = (double)ec[base + (long long)j0 * rowc + i0];
+                } else if (io && !jo) {
+                    v = 0.5 * ((double)ec[base + (long long)j0 * rowc + i0] +
+                               (double)ec[base + (long long)j0 * rowc + i0 + 1]);
+                } else if (!io && jo) {
+                    v = 0.5 * ((double)ec[base + (long long)j0 * rowc + i0] +
+                               (double)ec[base + (long long)(j0 + 1) * rowc + i0]);
+                } else {
+                    v = 0.25 * ((double)ec[base + (long long)j0 * rowc + i0] +
+                                (double)ec[base + (long long)j0 * rowc + i0 + 1] +
+                                (double)ec[base + (long long)(j0 + 1) * rowc + i0] +
+                                (double)ec[base + (long long)(j0 + 1) * rowc + i0 + 1]);
+                }
+            } else {
+                const int n0 = n >> 1;
+                if (!(n & 1))
+                    v = (double)ec[(long long)n0 * Pc + r];
+                else
+                    v = 0.5 * ((double)ec[(long long)n0 * Pc + r] +
+                               (double)ec[(long long)(n0 + 1) * Pc + r]);
+            }
+        }
+        if (accumulate)
+            xf[idx] = (T)((double)xf[idx] + v);
+        else
+            xf[idx] = (T)v;
+    }
+}
+
+void launch_prolong(hipStream_t s, const Level& F, const Level& C, int prec, const void* ec,
+                    void* xf, int accumulate) {
+    const unsigned nb = grid_for(F.nn);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_prolong<double>, dim3(nb), dim3(256), 0, s, C.how, F.nx, F.ny, F.nt,
+                           C.nx, C.ny, C.nt, F.mask, (const double*)ec, (double*)xf, accumulate);
+    else
+        hipLaunchKernelGGL(k_prolong<float>, dim3(nb), dim3(256), 0, s, C.how, F.nx, F.ny, F.nt,
+                           C.nx, C.ny, C.nt, F.mask, (const float*)ec, (float*)xf, accumulate);
+}
+
+// Coarse Dirichlet mask: a coarse node is Dirichlet when every fine node in the
+// support of its prolongation column is Dirichlet (its P_m column is zero).
+__global__ void k_coarse_mask(int how, int nxf, int nyf, int ntf, int nxc, int nyc, int ntc,
+                              const uint8_t* __restrict__ maskf, uint8_t* __restrict__ maskc) {
+    const long long rowc = nxc + 1, Pc = rowc * (nyc + 1);
+    const long long Nc = Pc * (ntc + 1);
+    const long long rowf = nxf + 1, Pf = rowf * (nyf + 1);
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < Nc;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int n = (int)(idx / Pc);
+        const long long r = idx - n * Pc;
+        const int J = (int)(r / rowc), I = (int)(r - (long long)J * rowc);
+        bool any_free = false;
+        if (how == 1) {
+            for (int c = -1; c <= 1; ++c)
+                for (int a = -1; a <= 1; ++a) {
+                    const int fj = 2 * J + c, fi = 2 * I + a;
+                    if (fj < 0 || fj > nyf || fi < 0 || fi > nxf) continue;
+                    any_free |= !maskf[(long long)n * Pf + (long long)fj * rowf + fi];
+                }
+        } else {
+            for (int a = -1; a <= 1; ++a) {
+                const int fn = 2 * n + a;
+                if (fn < 0 || fn > ntf) continue;
+                any_free |= !maskf[(long long)fn * Pf + r];
+            }
+        }
+        maskc[idx] = any_free ? 0 : 1;
+    }
+}
+
+void launch_coarse_mask(hipStream_t s, const Level& F, const Level& C) {
+    hipLaunchKernelGGL(k_coarse_mask, dim3(grid_for(C.nn)), dim3(256), 0, s, C.how, F.nx, F.ny,
+                       F.nt, C.nx, C.ny, C.nt, F.mask, C.mask);
+}
+
+// ---------------------------------------------------------------------------
+// Galerkin by probing.  Colour c = (cn, cj, ci) in {0,1,2}^3 marks the coarse
+// nodes with (n mod 3, j mod 3, i mod 3) = c.  Two nodes of one colour are at
+// least 3 apart in some direction, so within the 3x3x3 stencil of any row at
+// most one of them appears: y = P_m^T A P_m e_c read at row C is the entry of
+// the unique offset d that lands on colour c.
+__global__ void k_probe_fill(int nx, int ny, int nt, int color, const uint8_t* __restrict__ mask,
+                             double* __restrict__ e) {
+    const long long row = nx + 1, P = row * (ny + 1), N = P * (nt + 1);
+    const int ci = color % 3, cj = (color / 3) % 3, cn = color / 9;
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < N;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int n = (int)(idx / P);
+        const long long r = idx - n * P;
+        const int j = (int)(r / row), i = (int)(r - (long long)j * row);
+        e[idx] = (i % 3 == ci && j % 3 == cj && n % 3 == cn && !(mask && mask[idx])) ? 1.0 : 0.0;
+    }
+}
+
+void launch_probe_fill(hipStream_t s, const Level& C, int color, double* e) {
+    hipLaunchKernelGGL(k_probe_fill, dim3(grid_for(C.nn)), dim3(256), 0, s, C.nx, C.ny, C.nt,
+                       color, C.mask, e);
+}
+
+__device__ __forceinline__ int off_to_colour(int v, int c) {
+    // offset d in {-1, 0, 1} with (v + d) mod 3 == c
+    const int d = ((c - v % 3) % 3 + 3) % 3;   // 0, 1, 2
+    return d == 2 ? -1 : d;
+}
+
+// Writes the full (uncompressed, nplanes = nt+1) stencil entry of colour c.
+__global__ void k_probe_extract(int nx, int ny, int nt, int color, const double* __restrict__ yc,
+                                double* __restrict__ st) {
+    const long long row = nx + 1, P = row * (ny + 1), N = P * (nt + 1);
+    const int ci = color % 3, cj = (color / 3) % 3, cn = color / 9;
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < N;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int n = (int)(idx / P);
+        const long long r = idx - n * P;
+        const int j = (int)(r / row), i = (int)(r - (long long)j * row);
+        const int di = off_to_colour(i, ci), dj = off_to_colour(j, cj), dn = off_to_colour(n, cn);
+        const bool inside = i + di >= 0 && i + di <= nx && j + dj >= 0 && j + dj <= ny &&
+                            n + dn >= 0 && n + dn <= nt;
+        const int d = (dn + 1) * 9 + (dj + 1) * 3 + (di + 1);
+        st[(long long)d * N + idx] = inside ? yc[idx] : 0.0;
+    }
+}
+
+void launch_probe_extract(hipStream_t s, const Level& C, int color, const double* yc, double* st) {
+    hipLaunchKernelGGL(k_probe_extract, dim3(grid_for(C.nn)), dim3(256), 0, s, C.nx, C.ny, C.nt,
+                       color, yc, st);
+}
+
+// Identity rows on coarse Dirichlet nodes (their probed rows are zero).
+__global__ void k_identity_rows(long long N, const uint8_t* __restrict__ mask,
+                                double* __restrict__ st) {
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < N;
+         idx += (long long)gridDim.x * blockDim.x) {
+        if (!mask[idx]) continue;
+        for (int d = 0; d < 27; ++d) st[(long long)d * N + idx] = d == 13 ? 1.0 : 0.0;
+    }
+}
+
+void launch_identity_rows(hipStream_t s, const Level& C, double* st) {
+    hipLaunchKernelGGL(k_identity_rows, dim3(grid_for(C.nn)), dim3(256), 0, s, C.nn, C.mask, st);
+}
+
+// neq[n] = 1 when time level n of the uncompressed stencil differs (bitwise)
+// from time level n-1.
+__global__ void k_plane_equal(int nx, int ny, int nt, const double* __restrict__ st,
+                              int* __restrict__ neq) {
+    const long long P = (long long)(nx + 1) * (ny + 1), N = P * (nt + 1);
+    const int n = blockIdx.y + 1;
+    bool diff = false;
+    for (long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x; r < P;
+         r += (long long)gridDim.x * blockDim.x) {
+        for (int d = 0; d < 27; ++d) {
+            const double a = st[(long long)d * N + (long long)n * P + r];
+            const double b = st[(long long)d * N + (long long)(n - 1) * P + r];
+            diff |= __double_as_longlong(a) != __double_as_longlong(b);
+        }
+    }
+    if (__any(diff) && (threadIdx.x % 64) == 0) atomicOr(&neq[n], 1);
+}
+
+void launch_plane_equal(hipStream_t s, const Level& C, const double* st, int* neq) {
+    if (C.nt < 1) return;
+    const long long P = (long long)(C.nx + 1) * (C.ny + 1);
+    unsigned gx = grid_for(P, 256, 64);
+    hipLaunchKernelGGL(k_plane_equal, dim3(gx, C.nt), dim3(256), 0, s, C.nx, C.ny, C.nt, st, neq);
+}
+
+// Copy one contiguous block of P values (one stencil entry of one time level).
+__global__ void k_plane_move(long long P, const double* __restrict__ in, double* __restrict__ out) {
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < P;
+         t += (long long)gridDim.x * blockDim.x)
+        out[t] = in[t];
+}
+
+// In-place compaction: the distinct planes are moved one entry d at a time in
+// increasing d, so no source is overwritten before it is read (the compressed
+// position of (d, p) never exceeds its uncompressed position).
+void launch_plane_compact(hipStream_t s, const Level& C, double* st, const int* src_plane,
+                          int ndistinct) {
+    const long long P = (long long)(C.nx + 1) * (C.ny + 1);
+    const int nold = C.nt + 1;
+    for (int d = 0; d < 27; ++d)
+        for (int p = 0; p < ndistinct; ++p) {
+            const long long from = (long long)d * nold * P + (long long)src_plane[p] * P;
+            const long long to = (long long)d * ndistinct * P + (long long)p * P;
+            if (from == to) continue;
+            hipLaunchKernelGGL(k_plane_move, dim3(grid_for(P)), dim3(256), 0, s, P, st + from,
+                               st + to);
+        }
+}
+
+// Expand a compressed stencil to [27][nt+1][ny+1][nx+1].
+__global__ void k_stencil_expand(int nx, int ny, int nt, int nplanes, const double* __restrict__ st,
+                                 const int* __restrict__ pmap, double* __restrict__ out) {
+    const long long P = (long long)(nx + 1) * (ny + 1), N = P * (nt + 1);
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < 27 * N;
+         t += (long long)gridDim.x * blockDim.x) {
+        const int d = (int)(t / N);
+        const long long idx = t - (long long)d * N;
+        const int n = (int)(idx / P);
+        const long long r = idx - (long long)n * P;
+        out[t] = st[(long long)d * nplanes * P + (long long)pmap[n] * P + r];
+    }
+}
+
+void launch_stencil_expand(hipStream_t s, const Level& L, double* out) {
+    hipLaunchKernelGGL(k_stencil_expand, dim3(grid_for(27 * L.nn)), dim3(256), 0, s, L.nx, L.ny,
+                       L.nt, L.nplanes, L.st64, L.plane_map, out);
+}
+
+// Inverse diagonal from the centre entry (d = 13).
+__global__ void k_stencil_invdiag(int nx, int ny, int nt, int nplanes,
+                                  const double* __restrict__ st, const int* __restrict__ pmap,
+                                  double* __restrict__ invd64, float* __restrict__ invd32) {
+    const long long row = nx + 1, P = row * (ny + 1), N = P * (nt + 1);
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < N;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int n = (int)(idx / P);
+        const long long r = idx - n * P;
+        const double d = st[(long long)13 * nplanes * P + (long long)pmap[n] * P + r];
+        const double v = 1.0 / d;
+        invd64[idx] = v;
+        if (invd32) invd32[idx] = (float)v;
+    }
+}
+
+void launch_stencil_invdiag(hipStream_t s, const Level& L, double* invd64, float* invd32) {
+    hipLaunchKernelGGL(k_stencil_invdiag, dim3(grid_for(L.nn)), dim3(256), 0, s, L.nx, L.ny, L.nt,
+                       L.nplanes, L.st64, L.plane_map, invd64, invd32);
+}
+
+__global__ void k_stencil_cast(long long n, const double* __restrict__ in, float* __restrict__ o32,
+                               uint16_t* __restrict__ o16) {
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n;
+         t += (long long)gridDim.x * blockDim.x) {
+        const float f = (float)in[t];
+        if (o32) o32[t] = f;
+        if (o16) o16[t] = f32_to_bf16(f);
+    }
+}
+
+void launch_stencil_cast(hipStream_t s, const Level& L, float* st32, uint16_t* st16) {
+    const long long n = 27LL * L.nplanes * (L.nx + 1) * (L.ny + 1);
+    hipLaunchKernelGGL(k_stencil_cast, dim3(grid_for(n)), dim3(256), 0, s, n, L.st64, st32, st16);
+}
+
+// ---------------------------------------------------------------------------
+template <typename A, typename B>
+__global__ void k_cast(long long n, const A* __restrict__ in, B* __restrict__ out,
+                       const double* __restrict__ scale) {
+    const double sc = scale ? *scale : 1.0;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n;
+         t += (long long)gridDim.x * blockDim.x)
+        out[t] = (B)((double)in[t] * sc);
+}
+
+void launch_cast(hipStream_t s, long long n, int from, int to, const void* in, void* out,
+                 const double* scale) {
+    const unsigned nb = grid_for(n);
+    if (from == 0 && to == 0)
+        hipLaunchKernelGGL((k_cast<double, double>), dim3(nb), dim3(256), 0, s, n,
+                           (const double*)in, (double*)out, scale);
+    else if (from == 0 && to == 1)
+        hipLaunchKernelGGL((k_cast<double, float>), dim3(nb), dim3(256), 0, s, n,
+                           (const double*)in, (float*)out, scale);
+    else if (from == 1 && to == 0)
+        hipLaunchKernelGGL((k_cast<float, double>), dim3(nb), dim3(256), 0, s, n,
+                           (const float*)in, (double*)out, scale);
+    else
+        hipLaunchKernelGGL((k_cast<float, float>), dim3(nb), dim3(256), 0, s, n,
+                           (const float*)in, (float*)out, scale);
+}
+
+template <typename T>
+__global__ void k_fill(long long n, T* __restrict__ p, T v) {
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n;
+         t += (long long)gridDim.x * blockDim.x)
+        p[t] = v;
+}
+
+void launch_fill(hipStream_t s, long long n, int prec, void* p, double v) {
+    const unsigned nb = grid_for(n);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_fill<double>, dim3(nb), dim3(256), 0, s, n, (double*)p, v);
+    else if (prec == 1)
+        hipLaunchKernelGGL(k_fill<float>, dim3(nb), dim3(256), 0, s, n, (float*)p, (float)v);
+    else
+        hipLaunchKernelGGL(k_fill<int>, dim3(nb), dim3(256), 0, s, n, (int*)p, (int)v);
+}
+
+}  // namespace st

@@ -1,0 +1,1050 @@
+// Host side of the space-time solver: Algorithm 1 hierarchy, workspace
+// carving, Galerkin coarse operators, the Jacobi-GMRES smoother, the V-cycle,
+// FGMRES, adjoint solves, the PDE filter and the C ABI of st_api.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstddef>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "st_internal.hpp"
+
+using namespace st;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+struct TimedRec {
+    int cls;
+    int64_t bytes;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct st_handle {
+    hipStream_t stream = nullptr;
+    st_grid grid{};
+    st_material mat{};
+    st_opts opts{};
+    int rho_tv = 0;
+    int cuniform = 1;
+    double c0 = 1.0;
+    FineGeom fg{};
+    int nlev = 0;
+    Level lev[ST_MAX_LEVELS];
+    long long n0 = 0;          // fine nodes
+    long long ne = 0;          // coefficient elements (design layout)
+    long long nde = 0;         // design entries
+    // fine level data
+    double* rho = nullptr;     // design copy
+    double* rho_phys = nullptr;
+    double *k64 = nullptr, *c64 = nullptr, *dk = nullptr, *dc = nullptr;
+    float *k32 = nullptr, *c32 = nullptr;
+    double *f_full = nullptr, *f_m = nullptr;
+    double* ic = nullptr;      // copy of the initial condition [ny+1][nx+1]
+    double* src = nullptr;     // copy of the nodal source
+    double* adj_rhs = nullptr; // masked adjoint right-hand side
+    double* gtmp = nullptr;    // unfiltered sensitivities (filter problems)
+    double q0 = 1.0;
+    bool have_ic = false, have_src = false;
+    // outer Krylov
+    double* V = nullptr;       // (m+1) x n0 FP64
+    void* Z = nullptr;         // m x n0 (FP32 mixed / FP64 plain)
+    KState* ks_outer = nullptr;
+    double* coarseV = nullptr;
+    double* coarseWork = nullptr;
+    double* partials = nullptr;
+    double* dscal = nullptr;   // device scalars
+    int* neq = nullptr;        // plane comparison flags
+    // filter
+    int fnt = 0;
+    long long fnn = 0;
+    double *flt_invd = nullptr, *flt_x = nullptr, *flt_r = nullptr, *flt_z = nullptr,
+           *flt_p = nullptr, *flt_q = nullptr, *flt_b = nullptr;
+    // host
+    double* hbuf = nullptr;    // pinned staging
+    bool timing = false;
+    std::vector<TimedRec> trecs;
+    std::vector<hipEvent_t> evpool;
+    size_t evused = 0;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    int setup_done = 0;
+};
+
+namespace {
+
+#define HIPCHK(x)                                                     \
+    do {                                                              \
+        hipError_t e_ = (x);                                          \
+        if (e_ != hipSuccess) {                                       \
+            fprintf(stderr, "st: HIP error %s at %s:%d\n", hipGetErrorString(e_), __FILE__, \
+                    __LINE__);                                        \
+            return ST_ERR_HIP;                                        \
+        }                                                             \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Workspace carving: the same routine sizes (base == nullptr) and assigns.
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + ALIGN - 1) / ALIGN * ALIGN;
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+// Algorithm 1 (§3.2.1): lambda = D_eff dt / dx^2; below lambda_crit coarsen in
+// time, otherwise in space; when the chosen direction cannot be halved try the
+// other; stop at max_levels or once a level has <= max_coarse_nodes nodes.
+struct LevelDims {
+    int nx, ny, nt, how;
+    double dx, dt;
+};
+
+std::vector<LevelDims> build_hierarchy(const st_grid& g, const st_material& m, const st_opts& o) {
+    std::vector<LevelDims> L;
+    L.push_back({g.nx, g.ny, g.nt, 0, g.dx, g.dt});
+    const double D = std::sqrt(m.k_con * m.k_ins / (m.c_con * m.c_ins));
+    const int maxl = std::max(1, std::min(o.max_levels, (int)ST_MAX_LEVELS));
+    while ((int)L.size() < maxl) {
+        const LevelDims c = L.back();
+        const long long nodes = (long long)(c.nx + 1) * (c.ny + 1) * (c.nt + 1);
+        if (nodes <= o.max_coarse_nodes) break;
+        const double lam = D * c.dt / (c.dx * c.dx);
+        const bool want_time = lam < o.lambda_crit;
+        const bool can_s = c.nx % 2 == 0 && c.ny % 2 == 0 && c.nx >= 2 && c.ny >= 2;
+        const bool can_t = c.nt % 2 == 0 && c.nt >= 2;
+        int how = 0;
+        if (want_time) how = can_t ? 2 : (can_s ? 1 : 0);
+        else how = can_s ? 1 : (can_t ? 2 : 0);
+        if (!how) break;
+        if (how == 1) L.push_back({c.nx / 2, c.ny / 2, c.nt, 1, 2 * c.dx, c.dt});
+        else L.push_back({c.nx, c.ny, c.nt / 2, 2, c.dx, 2 * c.dt});
+    }
+    return L;
+}
+
+int patch_range(int n_along, double dx, double centre, double hw, int* lo, int* hi) {
+    int first = -1, last = -1;
+    for (int k = 0; k <= n_along; ++k) {
+        if (std::fabs(k * dx - centre) <= hw + 1e-12) {
+            if (first < 0) first = k;
+            last = k;
+        }
+    }
+    *lo = first;
+    *hi = last;
+    return first >= 0;
+}
+
+size_t vbytes(int prec) { return prec == 0 ? 8 : 4; }
+
+// Assign every buffer (or just size them when h->ws == nullptr).
+size_t carve(st_handle* h, char* base) {
+    Carver c{base};
+    const st_opts& o = h->opts;
+    const int m = o.restart;
+    const int si = o.smooth_its;
+    const bool mixed = o.precision == ST_MIXED;
+    h->rho = c.take<double>(h->nde);
+    h->rho_phys = o.filter_r > 0 ? c.take<double>(h->nde) : h->rho;
+    h->k64 = c.take<double>(h->ne);
+    h->dk = c.take<double>(h->ne);
+    if (!h->cuniform) {
+        h->c64 = c.take<double>(h->ne);
+        h->dc = c.take<double>(h->ne);
+    } else {
+        h->c64 = nullptr;
+        h->dc = nullptr;
+    }
+    h->k32 = mixed ? c.take<float>(h->ne) : nullptr;
+    h->c32 = (mixed && !h->cuniform) ? c.take<float>(h->ne) : nullptr;
+    h->f_full = c.take<double>(h->n0);
+    h->f_m = c.take<double>(h->n0);
+    h->ic = c.take<double>((size_t)(h->grid.nx + 1) * (h->grid.ny + 1));
+    h->src = c.take<double>(h->n0);
+    h->adj_rhs = c.take<double>(h->n0);
+    h->gtmp = o.filter_r > 0 ? c.take<double>(h->nde) : nullptr;
+    h->V = c.take<double>((size_t)(m + 1) * h->n0);
+    h->Z = mixed ? (void*)c.take<float>((size_t)m * h->n0) : (void*)c.take<double>((size_t)m * h->n0);
+    h->ks_outer = c.take<KState>(1);
+    h->partials = c.take<double>((size_t)RED_BLOCKS * KMAX + 2 * KMAX);
+    h->dscal = c.take<double>(64);
+    int maxnt = 0;
+    for (int l = 0; l < h->nlev; ++l) maxnt = std::max(maxnt, h->lev[l].nt);
+    h->neq = c.take<int>(maxnt + 2);
+    for (int l = 0; l < h->nlev; ++l) {
+        Level& L = h->lev[l];
+        const long long P = (long long)(L.nx + 1) * (L.ny + 1);
+        const size_t vb = vbytes(L.vprec);
+        L.mask = c.take<uint8_t>(L.nn);
+        L.invd64 = c.take<double>(L.nn);
+        L.invd32 = mixed ? c.take<float>(L.nn) : nullptr;
+        L.plane_map = c.take<int>(L.nt + 1);
+        if (l > 0) {
+            L.st64 = c.take<double>((size_t)27 * P * (L.nt + 1));
+            L.st32 = (mixed && L.sprec == 1) ? c.take<float>((size_t)27 * P * (L.nt + 1)) : nullptr;
+            L.st16 = (mixed && L.sprec == 2) ? c.take<uint16_t>((size_t)27 * P * (L.nt + 1)) : nullptr;
+        }
+        const bool coarsest = l == h->nlev - 1;
+        L.x = (l > 0) ? (void*)c.take<char>(L.nn * vb) : nullptr;
+        L.b = c.take<char>(L.nn * vb);
+        L.r = coarsest ? nullptr : (void*)c.take<char>(L.nn * vb);
+        L.V = coarsest ? nullptr : (void*)c.take<char>((size_t)(si + 1) * L.nn * vb);
+        L.ks = coarsest ? nullptr : c.take<KState>(1);
+    }
+    const Level& Lc = h->lev[h->nlev - 1];
+    h->coarseV = c.take<double>((size_t)(o.coarse_restart + 1) * Lc.nn);
+    h->coarseWork = c.take<double>((size_t)2 * Lc.nn);
+    if (o.filter_r > 0) {
+        h->fnt = h->rho_tv ? h->grid.nt : 1;
+        h->fnn = (long long)(h->grid.nx + 1) * (h->grid.ny + 1) * (h->fnt + 1);
+        h->flt_invd = c.take<double>(h->fnn);
+        h->flt_x = c.take<double>(h->fnn);
+        h->flt_r = c.take<double>(h->fnn);
+        h->flt_z = c.take<double>(h->fnn);
+        h->flt_p = c.take<double>(h->fnn);
+        h->flt_q = c.take<double>(h->fnn);
+        h->flt_b = c.take<double>(h->fnn);
+    }
+    return (c.off + ALIGN - 1) / ALIGN * ALIGN + ALIGN;
+}
+
+st_status validate(const st_grid* g, const st_material* m, const st_opts* o) {
+    if (!g || !m || !o) return ST_ERR_ARG;
+    if (g->nx < 1 || g->ny < 1 || g->nt < 1) return ST_ERR_ARG;
+    if (!(g->dx > 0) || !(g->dt > 0)) return ST_ERR_ARG;
+    if (!(m->k_ins > 0) || !(m->k_con > 0) || !(m->c_ins > 0) || !(m->c_con > 0)) return ST_ERR_ARG;
+    if (o->precision != ST_FP64 && o->precision != ST_MIXED) return ST_ERR_ARG;
+    if (o->restart < 4 || o->restart > KMAX - 1) return ST_ERR_ARG;
+    if (o->smooth_its < 1 || o->smooth_its > SMAX - 1) return ST_ERR_ARG;
+    if (o->coarse_restart < 1 || o->coarse_restart > KMAX - 1) return ST_ERR_ARG;
+    if (o->coarse_max_it < 1 || o->max_it < 1) return ST_ERR_ARG;
+    if (!(o->rtol >= 0) || !(o->smooth_rtol >= 0) || !(o->coarse_rtol >= 0)) return ST_ERR_ARG;
+    if (!(o->filter_r >= 0)) return ST_ERR_ARG;
+    return ST_OK;
+}
+
+void make_levels(st_handle* h) {
+    auto dims = build_hierarchy(h->grid, h->mat, h->opts);
+    h->nlev = (int)dims.size();
+    const bool mixed = h->opts.precision == ST_MIXED;
+    for (int l = 0; l < h->nlev; ++l) {
+        Level& L = h->lev[l];
+        L = Level();
+        L.nx = dims[l].nx;
+        L.ny = dims[l].ny;
+        L.nt = dims[l].nt;
+        L.dx = dims[l].dx;
+        L.dt = dims[l].dt;
+        L.how = dims[l].how;
+        L.nn = (long long)(L.nx + 1) * (L.ny + 1) * (L.nt + 1);
+        L.nplanes = L.nt + 1;
+        L.vprec = mixed ? 1 : 0;
+        L.sprec = 0;
+        if (mixed && l > 0)
+            L.sprec = (h->opts.bf16_from_level > 0 && l >= h->opts.bf16_from_level) ? 2 : 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kernel timing (ST_FLAG_TIME_KERNELS).
+hipEvent_t next_event(st_handle* h) {
+    if (h->evused == h->evpool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        h->evpool.push_back(e);
+    }
+    return h->evpool[h->evused++];
+}
+
+struct Timed {
+    st_handle* h;
+    int cls;
+    int64_t bytes;
+    hipEvent_t a = nullptr;
+    Timed(st_handle* h_, int cls_, int64_t bytes_) : h(h_), cls(cls_), bytes(bytes_) {
+        if (h->timing) {
+            a = next_event(h);
+            if (a) (void)hipEventRecord(a, h->stream);
+        }
+    }
+    ~Timed() {
+        if (h->timing && a) {
+            hipEvent_t b = next_event(h);
+            if (b) {
+                (void)hipEventRecord(b, h->stream);
+                h->trecs.push_back({cls, bytes, a, b});
+            }
+        }
+    }
+};
+
+void collect_timing(st_handle* h, st_info* info) {
+    if (!h->timing) return;
+    (void)hipStreamSynchronize(h->stream);
+    if (info) {
+        for (int c = 0; c < ST_NUM_KCLASS; ++c) {
+            info->kclass_ms[c] = 0;
+            info->kclass_launches[c] = 0;
+            info->kclass_bytes[c] = 0;
+        }
+    }
+    for (auto& r : h->trecs) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, r.a, r.b);
+        if (info && r.cls >= 0 && r.cls < ST_NUM_KCLASS) {
+            info->kclass_ms[r.cls] += ms;
+            info->kclass_launches[r.cls] += 1;
+            info->kclass_bytes[r.cls] += r.bytes;
+        }
+    }
+    h->trecs.clear();
+    h->evused = 0;
+}
+
+enum { KC_FINE64 = 0, KC_FINEV = 1, KC_STENCIL = 2, KC_DOT = 3, KC_AXPY = 4, KC_TRANSFER = 5,
+       KC_COARSE = 6, KC_MISC = 7 };
+
+// ---------------------------------------------------------------------------
+// Operator applications on a level.  Level 0 is matrix-free; coarse levels
+// use their Galerkin stencil.  prec: storage/arithmetic precision (0 FP64,
+// 1 the level's V-cycle precision when mixed).
+void level_apply(st_handle* h, int l, int prec, int trans, const void* x, void* y, const void* b,
+                 const void* invd, const double* scale, const int* skip) {
+    Level& L = h->lev[l];
+    if (l == 0) {
+        Coef cf{h->k64, h->c64, h->k32, h->c32};
+        const int v = prec;
+        Timed t(h, v == 0 ? KC_FINE64 : KC_FINEV,
+                (int64_t)L.nn * (int64_t)(2 * vbytes(v) + (b ? vbytes(v) : 0) + (invd ? vbytes(v) : 0)));
+        launch_fine_apply(h->stream, h->fg, cf, v, v, v == 0, trans, x, y, b, invd, scale, skip, 1, 1);
+    } else {
+        const int sb = prec == 0 ? 8 : (L.sprec == 2 ? 2 : 4);
+        Timed t(h, KC_STENCIL,
+                (int64_t)L.nn * (int64_t)(2 * vbytes(prec) + (b ? vbytes(prec) : 0) +
+                                          (invd ? vbytes(prec) : 0)) +
+                    (int64_t)27 * sb * (L.nx + 1) * (L.ny + 1) * L.nplanes);
+        launch_stencil_apply(h->stream, L, prec, trans, x, y, b, invd, scale, skip);
+    }
+}
+
+const void* level_invd(st_handle* h, int l, int prec) {
+    return prec == 0 ? (const void*)h->lev[l].invd64 : (const void*)h->lev[l].invd32;
+}
+
+// One Jacobi-GMRES smoothing (Saad & Schultz; left Jacobi, CGS, no restart):
+// x = x0 + V_k y_k, x0 = 0 when zero_x0.  All scalar work on the device.
+void smooth(st_handle* h, int l, int prec, int trans, const void* b, void* x, int zero_x0, int its,
+            double rtol, void* Vbuf, KState* ks) {
+    Level& L = h->lev[l];
+    hipStream_t s = h->stream;
+    const long long n = L.nn;
+    const size_t vb = vbytes(prec);
+    char* V = (char*)Vbuf;
+    auto Vj = [&](int j) { return (void*)(V + (size_t)j * n * vb); };
+    const void* invd = level_invd(h, l, prec);
+    launch_init_state(s, ks, its, rtol, 1, nullptr);
+    if (zero_x0) {
+        Timed t(h, KC_DOT, n * (int64_t)(3 * vb));
+        launch_scale_norm(s, n, prec, b, invd, Vj(0), h->partials, ks, FIN_INIT_SELF, its, rtol, 1);
+    } else {
+        level_apply(h, l, prec, trans, x, Vj(0), b, invd, nullptr, nullptr);
+        Timed t(h, KC_DOT, n * (int64_t)vb);
+        launch_mdot(s, n, prec, prec, Vj(0), Vj(0), n, 1, h->partials, ks, FIN_INIT_SELF, 0, 1);
+    }
+    for (int j = 0; j < its; ++j) {
+        level_apply(h, l, prec, trans, Vj(j), Vj(j + 1), nullptr, invd, &ks->scale[j], &ks->done);
+        {
+            Timed t(h, KC_DOT, n * (int64_t)vb * (j + 2));
+            launch_mdot(s, n, prec, prec, Vj(j + 1), V, n, j + 1, h->partials, ks, FIN_PROJ1, j, SMAX);
+        }
+        {
+            Timed t(h, KC_AXPY, n * (int64_t)vb * (j + 3));
+            launch_maxpy(s, n, prec, prec, Vj(j + 1), V, n, j + 1, h->partials, ks, FIN_GIVENS, j, SMAX);
+        }
+    }
+    Timed t(h, KC_AXPY, n * (int64_t)vb * (its + 2));
+    launch_update(s, n, prec, prec, x, V, n, ks, zero_x0, SMAX);
+}
+
+// Classical V-cycle (§3.2): pre-smoothing from zero, residual, restriction,
+// recursion, prolongation, post-smoothing; Jacobi-GMRES on the coarsest level.
+void vcycle(st_handle* h, int l, const void* b, void* x, int trans) {
+    Level& L = h->lev[l];
+    const st_opts& o = h->opts;
+    const int p = L.vprec;
+    hipStream_t s = h->stream;
+    if (l == h->nlev - 1) {
+        Timed t(h, KC_COARSE, 0);
+        launch_coarse_solve(s, L, p, trans, b, x, h->coarseV, h->coarseWork, o.coarse_max_it,
+                            o.coarse_restart, o.coarse_rtol, 1);
+        return;
+    }
+    smooth(h, l, p, trans, b, x, 1, o.smooth_its, o.smooth_rtol, L.V, L.ks);
+    level_apply(h, l, p, trans, x, L.r, b, nullptr, nullptr, nullptr);
+    Level& C = h->lev[l + 1];
+    {
+        Timed t(h, KC_TRANSFER, (int64_t)L.nn * (vbytes(p) + 1) + C.nn * vbytes(p));
+        launch_restrict(s, L, C, p, L.r, C.b);
+    }
+    vcycle(h, l + 1, C.b, C.x, trans);
+    {
+        Timed t(h, KC_TRANSFER, (int64_t)L.nn * (2 * vbytes(p) + 1) + C.nn * vbytes(p));
+        launch_prolong(s, L, C, p, C.x, x, 1);
+    }
+    smooth(h, l, p, trans, b, x, 0, o.smooth_its, o.smooth_rtol, L.V, L.ks);
+}
+
+// ---------------------------------------------------------------------------
+// Galerkin coarse operator of level l+1 by probing: for each of the 27
+// colours, y = P_m^T A_l P_m e_c, and the entries land in the uncompressed
+// stencil of level l+1.  Temporaries come from the FGMRES basis, which is
+// idle during setup.
+void galerkin_level(st_handle* h, int l) {
+    Level& F = h->lev[l];
+    Level& C = h->lev[l + 1];
+    hipStream_t s = h->stream;
+    double* xf = h->V;
+    double* yf = h->V + F.nn;
+    double* ec = h->V + 2 * F.nn;
+    double* yc = ec + C.nn;
+    C.nplanes = C.nt + 1;   // uncompressed while probing
+    for (int color = 0; color < 27; ++color) {
+        launch_probe_fill(s, C, color, ec);
+        launch_prolong(s, F, C, 0, ec, xf, 0);
+        level_apply(h, l, 0, 0, xf, yf, nullptr, nullptr, nullptr, nullptr);
+        launch_restrict(s, F, C, 0, yf, yc);
+        launch_probe_extract(s, C, color, yc, C.st64);
+    }
+    launch_identity_rows(s, C, C.st64);
+}
+
+// Merge runs of bitwise-identical time levels of a level's stencil.
+st_status dedup_planes(st_handle* h, int l) {
+    Level& L = h->lev[l];
+    hipStream_t s = h->stream;
+    std::vector<int> map(L.nt + 1, 0), src;
+    if (!(h->opts.flags & ST_FLAG_NO_PLANE_DEDUP) && L.nt >= 1) {
+        launch_fill(s, L.nt + 2, 2, h->neq, 0.0);
+        launch_plane_equal(s, L, L.st64, h->neq);
+        std::vector<int> neq(L.nt + 1, 0);
+        HIPCHK(hipMemcpyAsync(neq.data(), h->neq, sizeof(int) * (L.nt + 1), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        src.push_back(0);
+        for (int n = 1; n <= L.nt; ++n) {
+            if (neq[n]) src.push_back(n);
+            map[n] = (int)src.size() - 1;
+        }
+    } else {
+        for (int n = 0; n <= L.nt; ++n) {
+            map[n] = n;
+            src.push_back(n);
+        }
+    }
+    const int nd = (int)src.size();
+    if (nd < L.nt + 1) launch_plane_compact(s, L, L.st64, src.data(), nd);
+    L.nplanes = nd;
+    HIPCHK(hipMemcpyAsync(L.plane_map, map.data(), sizeof(int) * (L.nt + 1), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// PDE filter (§3.3.2): F g = (1/8) E^T H^{-1} (V/8) E g with the nodal
+// Helmholtz operator H = K_d + M (natural boundaries), solved by
+// Jacobi-preconditioned CG to a relative residual of 1e-13.  F is symmetric, so
+// the same routine sends sensitivities back through the filter.
+st_status filter_apply(st_handle* h, const double* in, double* out) {
+    hipStream_t s = h->stream;
+    const st_grid& g = h->grid;
+    const double rx = h->opts.filter_r * g.dx, rt = h->opts.filter_r * g.dt;
+    const double dxx = rx * rx / 12.0, dtt = rt * rt / 12.0;
+    const int nx = g.nx, ny = g.ny, nt = h->fnt;
+    const long long n = h->fnn;
+    double* scal = h->dscal + 16;
+    launch_elem_to_node(s, nx, ny, nt, g.dx * g.dx * g.dt / 8.0, in, h->flt_b);
+    launch_fill(s, n, 0, h->flt_x, 0.0);
+    launch_cg_step(s, 5, n, h->flt_x, h->flt_r, h->flt_z, h->flt_p, h->flt_b, h->flt_invd,
+                   h->partials, scal, nullptr);
+    launch_cg_step(s, 4, n, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, scal, nullptr);
+    HIPCHK(hipMemcpyAsync(h->hbuf, scal + 3, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double rr0 = h->hbuf[0];
+    const double tol2 = 1e-26 * rr0;
+    for (int it = 0; it < 2000 && rr0 > 0; ++it) {
+        launch_tensor_op(s, nx, ny, nt, g.dx, g.dt, dxx, dtt, h->flt_p, h->flt_q, nullptr, nullptr,
+                         nullptr);
+        launch_cg_step(s, 0, n, h->flt_x, h->flt_r, h->flt_z, h->flt_p, h->flt_q, h->flt_invd,
+                       h->partials, scal, nullptr);
+        launch_cg_step(s, 1, n, h->flt_x, h->flt_r, h->flt_z, h->flt_p, h->flt_q, h->flt_invd,
+                       h->partials, scal, nullptr);
+        launch_cg_step(s, 2, n, h->flt_x, h->flt_r, h->flt_z, h->flt_p, h->flt_q, h->flt_invd,
+                       h->partials, scal, nullptr);
+        launch_cg_step(s, 4, n, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, scal,
+                       nullptr);
+        if (it % 4 == 3) {
+            HIPCHK(hipMemcpyAsync(h->hbuf, scal + 3, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (!(h->hbuf[0] == h->hbuf[0])) return ST_ERR_BREAKDOWN;
+            if (h->hbuf[0] <= tol2) break;
+        }
+    }
+    launch_node_to_elem(s, nx, ny, nt, h->flt_x, out);
+    return ST_OK;
+}
+
+// SIMP coefficients, fine diagonal and mask, Galerkin hierarchy: every
+// density-dependent quantity.
+st_status build_operators(st_handle* h) {
+    hipStream_t s = h->stream;
+    const st_grid& g = h->grid;
+    st_status rc;
+    if (h->opts.filter_r > 0) {
+        rc = filter_apply(h, h->rho, h->rho_phys);
+        if (rc != ST_OK) return rc;
+    }
+    launch_simp(s, h->ne, h->rho_phys, &h->mat, h->k64, h->c64, h->dk, h->dc, h->k32, h->c32,
+                h->cuniform);
+    Coef cf{h->k64, h->c64, h->k32, h->c32};
+    Level& L0 = h->lev[0];
+    launch_fine_invdiag(s, h->fg, cf, g.dx, g.dt, L0.invd64, L0.invd32, L0.mask);
+    std::vector<int> ident(L0.nt + 1);
+    for (int n = 0; n <= L0.nt; ++n) ident[n] = n;
+    HIPCHK(hipMemcpyAsync(L0.plane_map, ident.data(), sizeof(int) * ident.size(), hipMemcpyHostToDevice, s));
+    for (int l = 0; l + 1 < h->nlev; ++l) {
+        Level& C = h->lev[l + 1];
+        launch_coarse_mask(s, h->lev[l], C);
+        galerkin_level(h, l);
+        rc = dedup_planes(h, l + 1);
+        if (rc != ST_OK) return rc;
+        launch_stencil_invdiag(s, C, C.invd64, C.invd32);
+        if (C.st32 || C.st16) launch_stencil_cast(s, C, C.st32, C.st16);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    return ST_OK;
+}
+
+// Consistent load, Dirichlet lifting f_m = N (f - J g) + g and ||f_m||.
+st_status build_rhs(st_handle* h, bool have_src, bool have_ic) {
+    hipStream_t s = h->stream;
+    const st_grid& g = h->grid;
+    if (have_src)
+        launch_tensor_op(s, g.nx, g.ny, g.nt, g.dx, g.dt, 0.0, 0.0, h->src, h->f_full, nullptr,
+                         nullptr, nullptr);
+    else
+        launch_load_uniform(s, h->fg, h->q0, g.dx, g.dt, h->f_full);
+    double* gv = h->V;
+    double* Jg = h->V + h->n0;
+    if (have_ic) {
+        launch_ic_lift_vector(s, h->fg, h->ic, gv);
+        Coef cf{h->k64, h->c64, h->k32, h->c32};
+        launch_fine_apply(s, h->fg, cf, 0, 0, 1, 0, gv, Jg, nullptr, nullptr, nullptr, nullptr, 0, 0);
+    } else {
+        launch_fill(s, h->n0, 0, gv, 0.0);
+        launch_fill(s, h->n0, 0, Jg, 0.0);
+    }
+    launch_lift(s, h->n0, h->lev[0].mask, h->f_full, Jg, gv, h->f_m);
+    launch_dot(s, h->n0, h->f_m, h->f_m, h->partials, h->dscal + 0);
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    return ST_OK;
+}
+
+// FGMRES(m), right-preconditioned by one V-cycle (§3.2), CGS with one
+// re-orthogonalisation, FP64 basis; one host read per iteration.
+st_status fgmres(st_handle* h, const double* f, const double* fnorm_dev, double* x, int trans,
+                 st_info* info) {
+    hipStream_t s = h->stream;
+    const st_opts& o = h->opts;
+    const long long n = h->n0;
+    const int m = o.restart;
+    const int zp = h->lev[0].vprec;
+    const size_t zb = vbytes(zp);
+    KState* ks = h->ks_outer;
+    auto Vj = [&](int j) { return h->V + (size_t)j * n; };
+    auto Zj = [&](int j) { return (void*)((char*)h->Z + (size_t)j * n * zb); };
+    HIPCHK(hipMemcpyAsync(h->hbuf, fnorm_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double fnorm = std::sqrt(h->hbuf[0]);
+    double* fref = h->dscal + 8;   // ||f||_2, reference of the relative tolerance
+    h->hbuf[1] = fnorm;
+    HIPCHK(hipMemcpyAsync(fref, &h->hbuf[1], sizeof(double), hipMemcpyHostToDevice, s));
+    int its = 0, restarts = 0;
+    double est = 0, truer = 0;
+    bool converged = false, bad = false;
+    if (info) info->n_hist = 0;
+    while (true) {
+        const int mc = std::min(m, o.max_it - its);
+        launch_init_state(s, ks, std::max(mc, 1), o.rtol, 0, fref);
+        // r0 = f - J x
+        {
+            Coef cf{h->k64, h->c64, h->k32, h->c32};
+            Timed t(h, KC_FINE64, n * 24);
+            launch_fine_apply(s, h->fg, cf, 0, 0, 1, trans, x, Vj(0), f, nullptr, nullptr, nullptr, 1, 1);
+        }
+        launch_mdot(s, n, 0, 0, Vj(0), Vj(0), n, 1, h->partials, ks, FIN_INIT_REF, 0, 1);
+        HIPCHK(hipMemcpyAsync(h->hbuf, &ks->est, 4 * sizeof(double) + 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        {
+            const int* iv = (const int*)(h->hbuf + 2);
+            truer = fnorm > 0 ? h->hbuf[0] / fnorm : h->hbuf[0];
+            est = truer;
+            if (iv[3] || !(h->hbuf[0] == h->hbuf[0])) { bad = true; break; }
+            if (h->hbuf[0] <= o.rtol * fnorm) { converged = true; break; }
+        }
+        if (its >= o.max_it) break;
+        int k = 0;
+        for (int j = 0; j < mc; ++j) {
+            {
+                Timed t(h, KC_MISC, n * (8 + zb));
+                launch_cast(s, n, 0, zp, Vj(j), h->lev[0].b, &ks->scale[j]);
+            }
+            vcycle(h, 0, h->lev[0].b, Zj(j), trans);
+            {
+                Coef cf{h->k64, h->c64, h->k32, h->c32};
+                Timed t(h, KC_FINE64, n * (8 + zb));
+                launch_fine_apply(s, h->fg, cf, zp, 0, 1, trans, Zj(j), Vj(j + 1), nullptr, nullptr,
+                                  nullptr, nullptr, 1, 1);
+            }
+            {
+                Timed t(h, KC_DOT, n * 8 * (j + 2));
+                launch_mdot(s, n, 0, 0, Vj(j + 1), h->V, n, j + 1, h->partials, ks, FIN_PROJ1, j, KMAX);
+            }
+            {
+                Timed t(h, KC_AXPY, n * 8 * (2 * j + 4));
+                launch_maxpy(s, n, 0, 0, Vj(j + 1), h->V, n, j + 1, h->partials, ks, FIN_PROJ2, j, KMAX);
+            }
+            {
+                Timed t(h, KC_AXPY, n * 8 * (j + 3));
+                launch_maxpy(s, n, 0, 0, Vj(j + 1), h->V, n, j + 1, h->partials, ks, FIN_GIVENS, j, KMAX);
+            }
+            HIPCHK(hipMemcpyAsync(h->hbuf, &ks->est, 4 * sizeof(double) + 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            ++its;
+            k = j + 1;
+            est = h->hbuf[0] / (fnorm > 0 ? fnorm : 1.0);
+            if (info && info->n_hist < ST_MAX_HIST) info->res_hist[info->n_hist++] = est;
+            const int* iv = (const int*)(h->hbuf + 2);   // k, done, maxit, bad
+            if (iv[3]) { bad = true; break; }
+            if (iv[1]) break;
+        }
+        if (bad) break;
+        (void)k;
+        {
+            Timed t(h, KC_AXPY, n * (16 + zb * m));
+            launch_update(s, n, 0, zp, x, h->Z, n, ks, 0, KMAX);
+        }
+        // true residual
+        {
+            Coef cf{h->k64, h->c64, h->k32, h->c32};
+            launch_fine_apply(s, h->fg, cf, 0, 0, 1, trans, x, Vj(0), f, nullptr, nullptr, nullptr, 1, 1);
+        }
+        launch_dot(s, n, Vj(0), Vj(0), h->partials, h->dscal + 9);
+        HIPCHK(hipMemcpyAsync(h->hbuf, h->dscal + 9, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        truer = std::sqrt(h->hbuf[0]) / (fnorm > 0 ? fnorm : 1.0);
+        if (!(truer == truer)) { bad = true; break; }
+        if (truer <= o.rtol) { converged = true; break; }
+        if (its >= o.max_it) break;
+        ++restarts;
+    }
+    HIPCHK(hipGetLastError());
+    if (info) {
+        info->iterations = its;
+        info->restarts = restarts;
+        info->rel_res_est = est;
+        info->true_rel_res = truer;
+        info->rhs_norm = fnorm;
+    }
+    if (bad) return ST_ERR_BREAKDOWN;
+    return converged ? ST_OK : ST_NOT_CONVERGED;
+}
+
+void fill_hierarchy(const st_handle* h, st_info* info) {
+    info->levels = h->nlev;
+    for (int l = 0; l < h->nlev; ++l) {
+        info->level_dims[l][0] = h->lev[l].nx;
+        info->level_dims[l][1] = h->lev[l].ny;
+        info->level_dims[l][2] = h->lev[l].nt;
+        info->level_planes[l] = h->lev[l].nplanes;
+    }
+}
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+extern "C" {
+
+void st_opts_default(st_opts* o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->precision = ST_FP64;
+    o->bf16_from_level = 0;
+    o->restart = 30;
+    o->rtol = 1e-8;
+    o->max_it = 1000;
+    o->smooth_its = 10;
+    o->smooth_rtol = 1e-6;
+    o->coarse_max_it = 200;
+    o->coarse_rtol = 1e-6;
+    o->coarse_restart = 30;
+    o->lambda_crit = 0.5;
+    o->max_levels = ST_MAX_LEVELS;
+    o->max_coarse_nodes = 4096;
+    o->filter_r = 0.0;
+    o->flags = 0;
+}
+
+const char* st_status_string(st_status s) {
+    switch (s) {
+    case ST_OK: return "ok";
+    case ST_NOT_CONVERGED: return "not converged";
+    case ST_ERR_ARG: return "invalid argument";
+    case ST_ERR_OOM: return "workspace too small";
+    case ST_ERR_HIP: return "HIP runtime error";
+    case ST_ERR_BREAKDOWN: return "breakdown (NaN/Inf)";
+    case ST_ERR_STATE: return "invalid state";
+    }
+    return "unknown";
+}
+
+st_status st_footprint_bytes(const st_grid* grid, const st_material* mat, const st_opts* opts,
+                             int32_t rho_time_varying, size_t* bytes) {
+    if (!bytes) return ST_ERR_ARG;
+    st_status rc = validate(grid, mat, opts);
+    if (rc != ST_OK) return rc;
+    st_handle* h = new (std::nothrow) st_handle();
+    if (!h) return ST_ERR_OOM;
+    h->grid = *grid;
+    h->mat = *mat;
+    h->opts = *opts;
+    h->rho_tv = rho_time_varying ? 1 : 0;
+    h->cuniform = mat->c_con == mat->c_ins;
+    h->n0 = (long long)(grid->nx + 1) * (grid->ny + 1) * (grid->nt + 1);
+    h->nde = (long long)(h->rho_tv ? grid->nt : 1) * grid->ny * grid->nx;
+    h->ne = h->nde;
+    make_levels(h);
+    *bytes = carve(h, nullptr);
+    delete h;
+    return ST_OK;
+}
+
+st_status st_setup(const st_grid* grid, const st_material* mat, const double* rho_dev,
+                   int32_t rho_time_varying, const double* ic_dev, const double* source_dev,
+                   double q0, const st_patch* patches, int32_t n_patches, const st_opts* opts,
+                   void* workspace_dev, size_t workspace_bytes, void* hip_stream,
+                   st_handle** out) {
+    if (!out || !rho_dev || !workspace_dev) return ST_ERR_ARG;
+    *out = nullptr;
+    st_status rc = validate(grid, mat, opts);
+    if (rc != ST_OK) return rc;
+    if (n_patches < 0 || n_patches > ST_MAX_PATCHES || (n_patches > 0 && !patches)) return ST_ERR_ARG;
+    if (!(q0 == q0)) return ST_ERR_ARG;
+    st_handle* h = new (std::nothrow) st_handle();
+    if (!h) return ST_ERR_OOM;
+    h->stream = (hipStream_t)hip_stream;
+    h->grid = *grid;
+    h->mat = *mat;
+    h->opts = *opts;
+    h->rho_tv = rho_time_varying ? 1 : 0;
+    h->cuniform = mat->c_con == mat->c_ins;
+    h->c0 = mat->c_ins;
+    h->q0 = q0;
+    h->n0 = (long long)(grid->nx + 1) * (grid->ny + 1) * (grid->nt + 1);
+    h->nde = (long long)(h->rho_tv ? grid->nt : 1) * grid->ny * grid->nx;
+    h->ne = h->nde;
+    FineGeom& g = h->fg;
+    g.nx = grid->nx;
+    g.ny = grid->ny;
+    g.nt = grid->nt;
+    g.dt6 = grid->dt / 36.0;
+    g.mw = grid->dx * grid->dx / 36.0;
+    g.tconst = h->rho_tv ? 0 : 1;
+    g.cuniform = h->cuniform;
+    g.c0 = h->c0;
+    g.ic_dir = 1;
+    g.patches.n = 0;
+    for (int q = 0; q < n_patches; ++q) {
+        const st_patch& P = patches[q];
+        if (P.edge < 0 || P.edge > 3 || !(P.half_width >= 0)) {
+            delete h;
+            return ST_ERR_ARG;
+        }
+        const int along = (P.edge <= 1) ? grid->ny : grid->nx;
+        int lo, hi;
+        if (!patch_range(along, grid->dx, P.centre, P.half_width, &lo, &hi)) continue;
+        const int k = g.patches.n++;
+        g.patches.edge[k] = P.edge;
+        g.patches.lo[k] = lo;
+        g.patches.hi[k] = hi;
+    }
+    make_levels(h);
+    const size_t need = carve(h, nullptr);
+    char* base = (char*)(((uintptr_t)workspace_dev + ALIGN - 1) / ALIGN * ALIGN);
+    if (workspace_bytes < need || (size_t)(base - (char*)workspace_dev) + (need - ALIGN) > workspace_bytes) {
+        delete h;
+        return ST_ERR_OOM;
+    }
+    carve(h, base);
+    h->ws = (char*)workspace_dev;
+    h->ws_bytes = workspace_bytes;
+    h->timing = (opts->flags & ST_FLAG_TIME_KERNELS) != 0;
+    if (hipHostMalloc((void**)&h->hbuf, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        delete h;
+        return ST_ERR_HIP;
+    }
+    hipStream_t s = h->stream;
+    launch_fill(s, (long long)RED_BLOCKS * KMAX + 2 * KMAX, 0, h->partials, 0.0);
+    launch_fill(s, 64, 0, h->dscal, 0.0);
+    launch_fill(s, (long long)(sizeof(KState) / sizeof(int)), 2, h->ks_outer, 0.0);
+    for (int l = 0; l < h->nlev; ++l)
+        if (h->lev[l].ks) launch_fill(s, (long long)(sizeof(KState) / sizeof(int)), 2, h->lev[l].ks, 0.0);
+    hipError_t e = hipMemcpyAsync(h->rho, rho_dev, sizeof(double) * h->nde, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && ic_dev) {
+        e = hipMemcpyAsync(h->ic, ic_dev, sizeof(double) * (grid->nx + 1) * (grid->ny + 1),
+                           hipMemcpyDeviceToDevice, s);
+        h->have_ic = true;
+    }
+    if (e == hipSuccess && source_dev) {
+        e = hipMemcpyAsync(h->src, source_dev, sizeof(double) * h->n0, hipMemcpyDeviceToDevice, s);
+        h->have_src = true;
+    }
+    if (e != hipSuccess) {
+        st_destroy(h);
+        return ST_ERR_HIP;
+    }
+    if (opts->filter_r > 0) {
+        const double rx = opts->filter_r * grid->dx, rt = opts->filter_r * grid->dt;
+        launch_tensor_invdiag(s, grid->nx, grid->ny, h->fnt, grid->dx, grid->dt, rx * rx / 12.0,
+                              rt * rt / 12.0, h->flt_invd);
+    }
+    const double t0 = now_s();
+    rc = build_operators(h);
+    if (rc == ST_OK) rc = build_rhs(h, h->have_src, h->have_ic);
+    if (rc != ST_OK) {
+        st_destroy(h);
+        return rc;
+    }
+    (void)t0;
+    h->setup_done = 1;
+    *out = h;
+    return ST_OK;
+}
+
+st_status st_update_density(st_handle* h, const double* rho_dev) {
+    if (!h || !rho_dev) return ST_ERR_ARG;
+    if (!h->setup_done) return ST_ERR_STATE;
+    HIPCHK(hipMemcpyAsync(h->rho, rho_dev, sizeof(double) * h->nde, hipMemcpyDeviceToDevice, h->stream));
+    st_status rc = build_operators(h);
+    if (rc == ST_OK) rc = build_rhs(h, h->have_src, h->have_ic);
+    return rc;
+}
+
+st_status st_solve(st_handle* h, double* T_dev, st_info* info) {
+    if (!h || !T_dev) return ST_ERR_ARG;
+    if (!h->setup_done) return ST_ERR_STATE;
+    if (info) memset(info, 0, sizeof(*info));
+    const double t0 = now_s();
+    st_status rc = fgmres(h, h->f_m, h->dscal + 0, T_dev, 0, info);
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return ST_ERR_HIP;
+    const double t1 = now_s();
+    if (info) {
+        info->t_solve_s = t1 - t0;
+        fill_hierarchy(h, info);
+    }
+    collect_timing(h, info);
+    return rc;
+}
+
+st_status st_adjoint_solve(st_handle* h, const double* g_dev, double* lambda_dev, st_info* info) {
+    if (!h || !g_dev || !lambda_dev) return ST_ERR_ARG;
+    if (!h->setup_done) return ST_ERR_STATE;
+    if (info) memset(info, 0, sizeof(*info));
+    hipStream_t s = h->stream;
+    const double t0 = now_s();
+    launch_mask_vec(s, h->n0, h->lev[0].mask, g_dev, h->adj_rhs);
+    launch_dot(s, h->n0, h->adj_rhs, h->adj_rhs, h->partials, h->dscal + 1);
+    st_status rc = fgmres(h, h->adj_rhs, h->dscal + 1, lambda_dev, 1, info);
+    if (hipStreamSynchronize(s) != hipSuccess) return ST_ERR_HIP;
+    if (info) {
+        info->t_solve_s = now_s() - t0;
+        fill_hierarchy(h, info);
+    }
+    collect_timing(h, info);
+    return rc;
+}
+
+st_status st_sensitivity(st_handle* h, const double* T_dev, const double* lambda_dev,
+                         double* dJdrho_dev) {
+    if (!h || !T_dev || !lambda_dev || !dJdrho_dev) return ST_ERR_ARG;
+    if (!h->setup_done) return ST_ERR_STATE;
+    hipStream_t s = h->stream;
+    double* dst = h->opts.filter_r > 0 ? h->gtmp : dJdrho_dev;
+    launch_sensitivity(s, h->fg, h->grid.dx, h->grid.dt, T_dev, lambda_dev, h->dk, h->dc, dst,
+                       h->rho_tv ? 0 : 1);
+    if (h->opts.filter_r > 0) {
+        st_status rc = filter_apply(h, h->gtmp, dJdrho_dev);
+        if (rc != ST_OK) return rc;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    return ST_OK;
+}
+
+st_status st_objective(st_handle* h, const double* T_dev, double* J_host) {
+    if (!h || !T_dev || !J_host) return ST_ERR_ARG;
+    hipStream_t s = h->stream;
+    launch_dot(s, h->n0, h->f_full, T_dev, h->partials, h->dscal + 2);
+    HIPCHK(hipMemcpyAsync(h->hbuf, h->dscal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *J_host = h->hbuf[0];
+    return ST_OK;
+}
+
+st_status st_load_vector(st_handle* h, double* f_dev) {
+    if (!h || !f_dev) return ST_ERR_ARG;
+    HIPCHK(hipMemcpyAsync(f_dev, h->f_full, sizeof(double) * h->n0, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return ST_OK;
+}
+
+st_status st_filter(st_handle* h, const double* in_dev, double* out_dev) {
+    if (!h || !in_dev || !out_dev) return ST_ERR_ARG;
+    if (!(h->opts.filter_r > 0)) return ST_ERR_STATE;
+    st_status rc = filter_apply(h, in_dev, out_dev);
+    if (rc != ST_OK) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return ST_OK;
+}
+
+st_status st_hierarchy(st_handle* h, st_info* info) {
+    if (!h || !info) return ST_ERR_ARG;
+    fill_hierarchy(h, info);
+    return ST_OK;
+}
+
+void st_destroy(st_handle* h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (auto e : h->evpool) (void)hipEventDestroy(e);
+    if (h->hbuf) (void)hipHostFree(h->hbuf);
+    delete h;
+}
+
+// ---- test entry points ----------------------------------------------------
+
+st_status st_debug_apply(st_handle* h, int32_t level, int32_t transpose, int32_t prec,
+                         const double* x_dev, double* y_dev) {
+    if (!h || !x_dev || !y_dev || level < 0 || level >= h->nlev) return ST_ERR_ARG;
+    Level& L = h->lev[level];
+    hipStream_t s = h->stream;
+    if (prec == ST_FP64) {
+        level_apply(h, level, 0, transpose, x_dev, y_dev, nullptr, nullptr, nullptr, nullptr);
+    } else {
+        if (h->opts.precision != ST_MIXED) return ST_ERR_STATE;
+        void* tin = L.b;
+        void* tout = L.r ? L.r : (void*)h->coarseWork;
+        launch_cast(s, L.nn, 0, 1, x_dev, tin, nullptr);
+        level_apply(h, level, 1, transpose, tin, tout, nullptr, nullptr, nullptr, nullptr);
+        launch_cast(s, L.nn, 1, 0, tout, y_dev, nullptr);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    return ST_OK;
+}
+
+st_status st_debug_stencil(st_handle* h, int32_t level, double* out_dev) {
+    if (!h || !out_dev || level < 0 || level >= h->nlev) return ST_ERR_ARG;
+    Level& L = h->lev[level];
+    hipStream_t s = h->stream;
+    if (level == 0) {
+        double* e = h->V;
+        double* y = h->V + L.nn;
+        Level probe = L;
+        probe.mask = nullptr;   // probe every node: identity rows show up as such
+        for (int color = 0; color < 27; ++color) {
+            launch_probe_fill(s, probe, color, e);
+            level_apply(h, 0, 0, 0, e, y, nullptr, nullptr, nullptr, nullptr);
+            launch_probe_extract(s, L, color, y, out_dev);
+        }
+    } else {
+        launch_stencil_expand(s, L, out_dev);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    return ST_OK;
+}
+
+st_status st_debug_diag(st_handle* h, int32_t level, double* invdiag_dev, uint8_t* mask_dev) {
+    if (!h || level < 0 || level >= h->nlev) return ST_ERR_ARG;
+    Level& L = h->lev[level];
+    if (invdiag_dev)
+        HIPCHK(hipMemcpyAsync(invdiag_dev, L.invd64, sizeof(double) * L.nn, hipMemcpyDeviceToDevice, h->stream));
+    if (mask_dev)
+        HIPCHK(hipMemcpyAsync(mask_dev, L.mask, L.nn, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return ST_OK;
+}
+
+st_status st_debug_transfer(st_handle* h, int32_t level, int32_t prolong, const double* in_dev,
+                            double* out_dev) {
+    if (!h || !in_dev || !out_dev || level < 0 || level + 1 >= h->nlev) return ST_ERR_ARG;
+    if (prolong)
+        launch_prolong(h->stream, h->lev[level], h->lev[level + 1], 0, in_dev, out_dev, 0);
+    else
+        launch_restrict(h->stream, h->lev[level], h->lev[level + 1], 0, in_dev, out_dev);
+    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipGetLastError());
+    return ST_OK;
+}
+
+st_status st_debug_smooth(st_handle* h, int32_t level, int32_t transpose, const double* b_dev,
+                          double* x_dev, int32_t zero_x0, int32_t its, double rtol) {
+    if (!h || !b_dev || !x_dev || level < 0 || level >= h->nlev) return ST_ERR_ARG;
+    if (its < 1 || its > SMAX - 1 || its > h->opts.restart) return ST_ERR_ARG;
+    smooth(h, level, 0, transpose, b_dev, x_dev, zero_x0, its, rtol, h->V, h->ks_outer);
+    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipGetLastError());
+    return ST_OK;
+}
+
+st_status st_debug_vcycle(st_handle* h, int32_t transpose, const double* b_dev, double* x_dev) {
+    if (!h || !b_dev || !x_dev) return ST_ERR_ARG;
+    hipStream_t s = h->stream;
+    const int p = h->lev[0].vprec;
+    launch_cast(s, h->n0, 0, p, b_dev, h->lev[0].b, nullptr);
+    vcycle(h, 0, h->lev[0].b, h->Z, transpose);
+    launch_cast(s, h->n0, p, 0, h->Z, x_dev, nullptr);
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    return ST_OK;
+}
+
+st_status st_abi_sizes(size_t* out, int32_t n) {
+    if (!out || n < 0) return ST_ERR_ARG;
+    const size_t v[7] = {sizeof(st_grid), sizeof(st_material), sizeof(st_patch), sizeof(st_opts),
+                         sizeof(st_info), offsetof(st_opts, flags), offsetof(st_info, kclass_ms)};
+    for (int i = 0; i < n && i < 7; ++i) out[i] = v[i];
+    return ST_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,177 @@
+// Internal declarations of the space-time solver library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <vector>
+#include <string>
+
+#include "st_api.h"
+
+namespace st {
+
+// ---------------------------------------------------------------------------
+// Small fixed limits.
+constexpr int KMAX = 32;          // largest Krylov basis (FGMRES / coarse restart)
+constexpr int SMAX = 16;          // largest smoother basis
+constexpr int RED_BLOCKS = 1024;  // most blocks of a grid-stride reduction kernel
+constexpr int VEC_THREADS = 256;
+
+// Device-resident state of one GMRES / FGMRES cycle.  Every small scalar step
+// (projections, Givens rotations, the least-squares solve, convergence test)
+// runs on the device so that a whole smoothing needs no host round trip.
+struct KState {
+    double H[KMAX + 1][KMAX];   // rotated Hessenberg (upper triangular part = R)
+    double cs[KMAX], sn[KMAX];
+    double g[KMAX + 1];         // rotated right-hand side beta e1
+    double scale[KMAX + 1];     // 1 / ||w_d|| of the (unnormalised) basis vector d
+    double hcol[KMAX + 1];      // projections of the current column (scaled)
+    double coef[KMAX + 1];      // maxpy coefficients for the unnormalised basis
+    double y[KMAX];             // update coefficients
+    double ref;                 // reference norm of the relative tolerance
+    double rtol;
+    double est;                 // |g_k|: residual estimate after k steps
+    double beta;                // initial residual norm of this cycle
+    int k;                      // completed iterations this cycle
+    int done;                   // 1 = converged / breakdown / maxit reached
+    int maxit;                  // iterations allowed this cycle
+    int bad;                    // NaN or Inf seen
+    unsigned counter;           // arrival counter of the last-block reduction
+    int scale_update;           // 1: y_d multiplied by scale_d (unnormalised basis)
+    int pad[2];
+};
+
+// Finalisation modes of the fused reduction kernels.
+enum FinMode {
+    FIN_INIT_SELF = 0,   // beta = sqrt(sum); ref = beta
+    FIN_INIT_REF = 1,    // beta = sqrt(sum); ref unchanged (set by host)
+    FIN_PROJ1 = 2,       // first CGS projections h_d
+    FIN_PROJ2 = 3,       // re-orthogonalisation projections (CGS2)
+    FIN_GIVENS = 4,      // norm of the new vector, Givens update, convergence test
+    FIN_SUM = 5          // plain sums to out[]
+};
+
+// T = 0 patches translated to index ranges.
+struct PatchSet {
+    int n;
+    int edge[ST_MAX_PATCHES];
+    int lo[ST_MAX_PATCHES];
+    int hi[ST_MAX_PATCHES];
+};
+
+struct FineGeom {
+    int nx, ny, nt;       // elements
+    double dt6;           // dt / 6 times 1/6 of the 2-D stiffness (= dt / 36)
+    double mw;            // dx^2 / 36
+    int tconst;           // coefficient arrays have a single slab
+    int cuniform;         // capacity uniform (value c0, no C array)
+    double c0;
+    int ic_dir;           // the t = 0 plane is Dirichlet
+    PatchSet patches;
+};
+
+// Level of the multigrid hierarchy (host view of device buffers).
+struct Level {
+    int nx, ny, nt;
+    long long nn;           // nodes
+    double dx, dt;
+    int how;                // 0 finest, 1 space-coarsened, 2 time-coarsened
+    int nplanes;            // distinct stencil time levels
+    int vprec;              // 0 = FP64 vectors, 1 = FP32 vectors in the V-cycle
+    int sprec;              // stencil storage: 0 FP64, 1 FP32, 2 BF16
+    uint8_t* mask = nullptr;       // [nn] 1 = Dirichlet
+    int* plane_map = nullptr;      // [nt+1] -> distinct plane
+    double* st64 = nullptr;        // [27][nplanes][ny+1][nx+1]
+    float* st32 = nullptr;
+    uint16_t* st16 = nullptr;
+    double* invd64 = nullptr;
+    float* invd32 = nullptr;
+    void* x = nullptr;             // V-cycle vectors (vprec)
+    void* b = nullptr;
+    void* r = nullptr;
+    void* V = nullptr;             // smoother basis [SMAX+1][nn]
+    KState* ks = nullptr;
+};
+
+struct Workspace;  // memory carving
+
+}  // namespace st
+
+// Kernel launchers (defined in the .hip files).
+namespace st {
+struct Coef {
+    const double* k64; const double* c64;   // element coefficients (FP64)
+    const float* k32; const float* c32;     // FP32 copies
+};
+void launch_simp(hipStream_t s, long long ne, const double* rho, const st_material* m,
+                 double* k, double* c, double* dk, double* dc, float* k32, float* c32, int cuniform);
+void launch_fine_apply(hipStream_t s, const FineGeom& g, const Coef& cf, int prec_in, int prec_out,
+                       int compute64, int trans, const void* x, void* y, const void* b,
+                       const void* invd, const double* scale, const int* skip, int mask_in,
+                       int dir_rows);
+void launch_fine_invdiag(hipStream_t s, const FineGeom& g, const Coef& cf, double dx, double dt,
+                         double* invd64, float* invd32, uint8_t* mask);
+void launch_stencil_apply(hipStream_t s, const Level& L, int prec, int trans, const void* x,
+                          void* y, const void* b, const void* invd, const double* scale,
+                          const int* skip);
+void launch_restrict(hipStream_t s, const Level& F, const Level& C, int prec, const void* rf,
+                     void* bc);
+void launch_prolong(hipStream_t s, const Level& F, const Level& C, int prec, const void* ec,
+                    void* xf, int accumulate);
+void launch_coarse_mask(hipStream_t s, const Level& F, const Level& C);
+void launch_probe_fill(hipStream_t s, const Level& C, int color, double* e);
+void launch_probe_extract(hipStream_t s, const Level& C, int color, const double* yc, double* st);
+void launch_identity_rows(hipStream_t s, const Level& C, double* st);
+void launch_plane_equal(hipStream_t s, const Level& C, const double* st, int* neq);
+void launch_plane_compact(hipStream_t s, const Level& C, double* st, const int* src_plane,
+                          int ndistinct);
+void launch_stencil_invdiag(hipStream_t s, const Level& L, double* invd64, float* invd32);
+void launch_stencil_expand(hipStream_t s, const Level& L, double* out);
+void launch_stencil_cast(hipStream_t s, const Level& L, float* st32, uint16_t* st16);
+void launch_cast(hipStream_t s, long long n, int from, int to, const void* in, void* out,
+                 const double* scale);
+void launch_fill(hipStream_t s, long long n, int prec, void* p, double v);
+
+// Krylov kernels.
+void launch_scale_norm(hipStream_t s, long long n, int prec, const void* b, const void* invd,
+                       void* w, double* partials, KState* ks, int mode, int maxit, double rtol,
+                       int scale_update);
+void launch_mdot(hipStream_t s, long long n, int prec_w, int prec_v, const void* w,
+                 const void* V, long long ldv, int nd, double* partials, KState* ks, int mode,
+                 int j, int maxd);
+void launch_maxpy(hipStream_t s, long long n, int prec_w, int prec_v, void* w, const void* V,
+                  long long ldv, int nd, double* partials, KState* ks, int mode, int j, int maxd);
+void launch_update(hipStream_t s, long long n, int prec_x, int prec_v, void* x, const void* V,
+                   long long ldv, KState* ks, int zero_x0, int maxd);
+void launch_init_state(hipStream_t s, KState* ks, int maxit, double rtol, int scale_update,
+                       const double* ref);
+void launch_dot(hipStream_t s, long long n, const double* a, const double* b, double* partials,
+                double* out);
+void launch_coarse_solve(hipStream_t s, const Level& L, int prec_io, int trans, const void* b,
+                         void* x, double* V, double* work, int maxit, int restart, double rtol,
+                         int zero_x0);
+
+// Right-hand side, objective, sensitivities, filter.
+void launch_load_uniform(hipStream_t s, const FineGeom& g, double q0, double dx, double dt,
+                         double* f);
+void launch_tensor_op(hipStream_t s, int nx, int ny, int nt, double dx, double dt, double dxx,
+                      double dtt, const double* x, double* y, const double* b, const double* invd,
+                      const int* skip);
+void launch_tensor_invdiag(hipStream_t s, int nx, int ny, int nt, double dx, double dt,
+                           double dxx, double dtt, double* invd);
+void launch_lift(hipStream_t s, long long n, const uint8_t* mask, const double* f,
+                 const double* Jg, const double* g, double* fm);
+void launch_mask_vec(hipStream_t s, long long n, const uint8_t* mask, const double* in,
+                     double* out);
+void launch_elem_to_node(hipStream_t s, int nx, int ny, int nt, double w, const double* e,
+                         double* nodal);
+void launch_node_to_elem(hipStream_t s, int nx, int ny, int nt, const double* nodal, double* e);
+void launch_sensitivity(hipStream_t s, const FineGeom& g, double dx, double dt, const double* T,
+                        const double* lam, const double* dk, const double* dc, double* out,
+                        int sum_slabs);
+void launch_ic_lift_vector(hipStream_t s, const FineGeom& g, const double* ic, double* gvec);
+void launch_cg_step(hipStream_t s, int step, long long n, double* x, double* r, double* z,
+                    double* p, const double* q, const double* invd, double* partials,
+                    double* scal, const int* skip);
+}  // namespace st

@@ -1,0 +1,143 @@
+"""GPU parity of the single operators against the FP64 oracle (element by
+element): fine matrix-free apply and transpose, diagonal, Galerkin stencils of
+every level, masks, transfers, coarse applies, FP32 variants, one smoothing and
+one V-cycle."""
+import numpy as np
+import pytest
+
+from oracle.krylov import gmres_jacobi, VCycle
+from oracle.multigrid import stencil_of
+from tests._cases import Case, rel, maxrel
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(3, 2, 2, False), (3, 2, 2, True), (8, 6, 5, True), (12, 12, 8, False),
+          (32, 32, 32, False), (16, 16, 16, True)]
+
+
+def _t(x):
+    import torch
+    return torch.tensor(np.asarray(x, dtype=np.float64), device="cuda")
+
+
+@pytest.fixture(scope="module")
+def torch_cuda(require_gpu):
+    import torch
+    return torch
+
+
+@pytest.mark.parametrize("nx,ny,nt,tv", SHAPES)
+def test_fine_apply_and_transpose(torch_cuda, nx, ny, nt, tv):
+    c = Case(nx, ny, nt, tv=tv, seed=nx + nt, patches=((0, 0.5 * ny / max(nx, ny), 0.3),))
+    p = c.problem(max_coarse_nodes=10 ** 9)
+    rng = np.random.default_rng(1)
+    shp = (nt + 1, ny + 1, nx + 1)
+    for trans in (False, True):
+        x = rng.standard_normal(shp)
+        y = p.debug_apply(0, _t(x), transpose=trans).cpu().numpy()
+        ref = (c.Jm.T if trans else c.Jm) @ x.ravel()
+        assert maxrel(y, ref) < 1e-13, (trans, maxrel(y, ref))
+    p.close()
+
+
+@pytest.mark.parametrize("nx,ny,nt,tv", SHAPES)
+def test_fine_diagonal_mask_and_stencil(torch_cuda, nx, ny, nt, tv):
+    c = Case(nx, ny, nt, tv=tv, seed=3, patches=((0, 0.5 * ny / max(nx, ny), 0.3), (3, 0.4, 0.2)))
+    p = c.problem(max_coarse_nodes=10 ** 9)
+    invd, m = p.debug_diag(0)
+    assert np.array_equal(m.cpu().numpy().astype(bool).ravel(), c.mask.ravel())
+    assert maxrel(invd.cpu().numpy(), 1.0 / c.Jm.diagonal()) < 1e-14
+    st = p.debug_stencil(0).cpu().numpy()
+    ref = stencil_of(c.Jm, c.levels[0])
+    assert maxrel(st, ref) < 1e-13
+    p.close()
+
+
+@pytest.mark.parametrize("nx,ny,nt,tv", [(16, 16, 16, False), (16, 16, 16, True), (16, 12, 8, True),
+                                         (32, 32, 32, False)])
+def test_galerkin_hierarchy(torch_cuda, nx, ny, nt, tv):
+    """Every coarse level: mask, stencil (P_m^T A P_m with identity rows),
+    inverse diagonal; and the transfers on every level pair."""
+    c = Case(nx, ny, nt, tv=tv, seed=5, max_coarse_nodes=200)
+    p = c.problem(max_coarse_nodes=200)
+    dims, planes = p.hierarchy()
+    assert [(L["nx"], L["ny"], L["nt"]) for L in c.levels] == [tuple(d) for d in dims]
+    A, masks, Pm = c.ops
+    rng = np.random.default_rng(2)
+    for l in range(1, len(dims)):
+        invd, m = p.debug_diag(l)
+        assert np.array_equal(m.cpu().numpy().astype(bool).ravel(), masks[l]), l
+        st = p.debug_stencil(l).cpu().numpy()
+        ref = stencil_of(A[l], c.levels[l])
+        assert maxrel(st, ref) < 1e-13, (l, maxrel(st, ref))
+        assert maxrel(invd.cpu().numpy(), 1.0 / A[l].diagonal()) < 1e-13
+        if not tv:
+            assert planes[l] <= 8, planes
+        # transfers
+        xc = rng.standard_normal(A[l].shape[0])
+        xf = rng.standard_normal(A[l - 1].shape[0])
+        pro = p.debug_transfer(l - 1, _t(xc).reshape(p.level_shape(l)), prolong=True).cpu().numpy()
+        res = p.debug_transfer(l - 1, _t(xf).reshape(p.level_shape(l - 1)), prolong=False).cpu().numpy()
+        assert maxrel(pro, Pm[l - 1] @ xc) < 1e-15
+        assert maxrel(res, Pm[l - 1].T @ xf) < 1e-14
+        # coarse apply and transpose
+        for trans in (False, True):
+            y = p.debug_apply(l, _t(xc).reshape(p.level_shape(l)), transpose=trans).cpu().numpy()
+            ref = (A[l].T if trans else A[l]) @ xc
+            assert maxrel(y, ref) < 1e-13, (l, trans)
+    p.close()
+
+
+@pytest.mark.parametrize("tv", [False, True])
+def test_mixed_precision_applies(torch_cuda, tv):
+    """FP32 level operators (mixed precision) against the FP64 oracle: 1e-5."""
+    c = Case(16, 16, 16, tv=tv, seed=7, max_coarse_nodes=200)
+    p = c.problem(max_coarse_nodes=200, precision="mixed")
+    A, masks, Pm = c.ops
+    rng = np.random.default_rng(3)
+    for l in range(len(c.levels)):
+        x = rng.standard_normal(A[l].shape[0])
+        for trans in (False, True):
+            y = p.debug_apply(l, _t(x).reshape(p.level_shape(l)), transpose=trans, mixed=True)
+            ref = (A[l].T if trans else A[l]) @ x
+            assert rel(y.cpu().numpy(), ref) < 1e-5, (l, trans, rel(y.cpu().numpy(), ref))
+    p.close()
+
+
+@pytest.mark.parametrize("level", [0, 1, 2])
+def test_smoother_matches_oracle_gmres(torch_cuda, level):
+    """One Jacobi-GMRES smoothing (10 iterations, CGS, left Jacobi) on a level,
+    from zero and from a given x0, forward and transposed."""
+    c = Case(16, 16, 16, tv=True, seed=9, max_coarse_nodes=200)
+    p = c.problem(max_coarse_nodes=200)
+    A, masks, Pm = c.ops
+    rng = np.random.default_rng(4)
+    b = rng.standard_normal(A[level].shape[0])
+    b[masks[level]] = 0.0
+    x0 = rng.standard_normal(A[level].shape[0]) * 0.1
+    shp = p.level_shape(level)
+    for trans in (False, True):
+        Al = A[level].T.tocsr() if trans else A[level]
+        xg = p.debug_smooth(level, _t(b).reshape(shp), None, 10, 1e-6, trans).cpu().numpy()
+        xo, _, _ = gmres_jacobi(Al, b, None, 10, 1e-6)
+        assert rel(xg, xo) < 1e-10, (trans, rel(xg, xo))
+        xg = p.debug_smooth(level, _t(b).reshape(shp), _t(x0).reshape(shp), 10, 1e-6, trans).cpu().numpy()
+        xo, _, _ = gmres_jacobi(Al, b, x0, 10, 1e-6)
+        assert rel(xg, xo) < 1e-10, (trans, rel(xg, xo))
+    p.close()
+
+
+@pytest.mark.parametrize("tv", [False, True])
+def test_vcycle_matches_oracle(torch_cuda, tv):
+    c = Case(16, 16, 16, tv=tv, seed=11, max_coarse_nodes=200)
+    p = c.problem(max_coarse_nodes=200)
+    A, masks, Pm = c.ops
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(A[0].shape[0])
+    b[masks[0]] = 0.0
+    for trans in (False, True):
+        At = [a.T.tocsr() for a in A] if trans else A
+        xo = VCycle(At, Pm)(b)
+        xg = p.debug_vcycle(_t(b).reshape(p.level_shape(0)), transpose=trans).cpu().numpy()
+        assert rel(xg, xo) < 1e-9, (trans, rel(xg, xo))
+    p.close()

@@ -1,0 +1,72 @@
+"""GPU parity of complete solves against the FP64 oracle, plus closed forms
+that hold at any size."""
+import numpy as np
+import pytest
+
+from oracle.solve import solve_direct, solve_adjoint_direct
+from tests._cases import Case, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda(require_gpu):
+    import torch
+    return torch
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_small_workload_parity(torch_cuda, precision):
+    """32^2 x 32, time-constant uniform-random density, left-edge patch: the
+    solution in parity mode (rtol 1e-12) matches the direct solve to 1e-10."""
+    from paper_2508_09589_amd.inputs import uniform_density
+    c = Case(32, 32, 32, rho=uniform_density(32, seed=0))
+    p = c.problem(precision=precision, rtol=1e-12)
+    T, info = p.solve()
+    s = solve_direct(c.Jm, c.fm)
+    assert info.true_rel_res <= 1e-12
+    assert rel(T.cpu().numpy(), s) <= 1e-10, rel(T.cpu().numpy(), s)
+    assert info.levels == 4
+    p.close()
+
+
+@pytest.mark.parametrize("nx,ny,nt,tv", [(24, 16, 12, True), (20, 28, 16, False), (1, 1, 1, False),
+                                         (2, 2, 1, True)])
+def test_ragged_and_tiny_grids(torch_cuda, nx, ny, nt, tv):
+    c = Case(nx, ny, nt, tv=tv, seed=nx * ny + nt,
+             patches=((0, 0.5 * ny / max(nx, ny), 0.2), (2, 0.3, 0.3)))
+    p = c.problem(rtol=1e-12)
+    T, info = p.solve()
+    s = solve_direct(c.Jm, c.fm)
+    assert rel(T.cpu().numpy(), s) <= 1e-10, (rel(T.cpu().numpy(), s), info.iterations)
+    p.close()
+
+
+def test_adjoint_parity(torch_cuda):
+    c = Case(24, 24, 16, tv=True, seed=21)
+    p = c.problem(rtol=1e-12)
+    f = p.load_vector()
+    assert rel(f.cpu().numpy(), c.f) < 1e-15
+    lam, info = p.adjoint(f)
+    ref = solve_adjoint_direct(c.Jm, c.f, c.mask)
+    assert rel(lam.cpu().numpy(), ref) <= 1e-10
+    p.close()
+
+
+@pytest.mark.parametrize("n,nt,tv", [(64, 64, True), (128, 64, False)])
+def test_sink_free_closed_form(torch_cuda, n, nt, tv):
+    """No patch, C = 1, Q = q0: T = n q0 dt (n < nt), (nt - 1/2) q0 dt at nt,
+    for any conductivity field -- checked without the oracle."""
+    import torch
+    from paper_2508_09589_amd import Problem
+    from paper_2508_09589_amd.inputs import smooth_density
+    rho = smooth_density(n, n, nt, seed=3) if tv else np.random.default_rng(3).uniform(1e-3, 1, (n, n))
+    q0 = 1.0
+    p = Problem(n, n, nt, torch.tensor(rho), patches=(), q0=q0, rtol=1e-12)
+    T, info = p.solve()
+    dt = 1.0 / nt
+    expect = np.arange(nt + 1) * q0 * dt
+    expect[-1] = (nt - 0.5) * q0 * dt
+    err = np.max(np.abs(T.cpu().numpy() - expect[:, None, None])) / expect.max()
+    assert err < 1e-10, err
+    p.close()
