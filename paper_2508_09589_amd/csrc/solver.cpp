@@ -193,10 +193,12 @@ size_t carve(st_handle* h, char* base) {
         L.invd64 = c.take<double>(L.nn);
         L.invd32 = mixed ? c.take<float>(L.nn) : nullptr;
         L.plane_map = c.take<int>(L.nt + 1);
-        if (l > 0) {
+        if (l > 0 || h->nlev == 1) {
+            // coarse levels hold Galerkin stencils; a one-level hierarchy
+            // needs the fine stencil for its coarsest-level solve
             L.st64 = c.take<double>((size_t)27 * P * (L.nt + 1));
-            L.st32 = (mixed && L.sprec == 1) ? c.take<float>((size_t)27 * P * (L.nt + 1)) : nullptr;
-            L.st16 = (mixed && L.sprec == 2) ? c.take<uint16_t>((size_t)27 * P * (L.nt + 1)) : nullptr;
+            L.st32 = (mixed && L.sprec == 1 && l > 0) ? c.take<float>((size_t)27 * P * (L.nt + 1)) : nullptr;
+            L.st16 = (mixed && L.sprec == 2 && l > 0) ? c.take<uint16_t>((size_t)27 * P * (L.nt + 1)) : nullptr;
         }
         const bool coarsest = l == h->nlev - 1;
         L.x = (l > 0) ? (void*)c.take<char>(L.nn * vb) : nullptr;
@@ -388,6 +390,7 @@ void vcycle(st_handle* h, int l, const void* b, void* x, int trans) {
     const int p = L.vprec;
     hipStream_t s = h->stream;
     if (l == h->nlev - 1) {
+        if (!L.st64) return;   // unreachable: setup builds a stencil for the coarsest level
         Timed t(h, KC_COARSE, 0);
         launch_coarse_solve(s, L, p, trans, b, x, h->coarseV, h->coarseWork, o.coarse_max_it,
                             o.coarse_restart, o.coarse_rtol, 1);
@@ -524,6 +527,23 @@ st_status build_operators(st_handle* h) {
     std::vector<int> ident(L0.nt + 1);
     for (int n = 0; n <= L0.nt; ++n) ident[n] = n;
     HIPCHK(hipMemcpyAsync(L0.plane_map, ident.data(), sizeof(int) * ident.size(), hipMemcpyHostToDevice, s));
+    if (h->nlev == 1) {
+        // One level: the coarsest-level solver works on the fine operator,
+        // materialised by probing (every node probed, so Dirichlet rows come
+        // out as identity rows).
+        double* e = h->V;
+        double* y = h->V + L0.nn;
+        Level probe = L0;
+        probe.mask = nullptr;
+        L0.nplanes = L0.nt + 1;
+        for (int color = 0; color < 27; ++color) {
+            launch_probe_fill(s, probe, color, e);
+            level_apply(h, 0, 0, 0, e, y, nullptr, nullptr, nullptr, nullptr);
+            launch_probe_extract(s, L0, color, y, L0.st64);
+        }
+        rc = dedup_planes(h, 0);
+        if (rc != ST_OK) return rc;
+    }
     for (int l = 0; l + 1 < h->nlev; ++l) {
         Level& C = h->lev[l + 1];
         launch_coarse_mask(s, h->lev[l], C);

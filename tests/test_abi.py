@@ -1,0 +1,88 @@
+"""The C-ABI library loads and exports every symbol include/st_api.h declares;
+struct layouts agree with the Python binding; host-side logic (defaults,
+footprints, argument validation) works without a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2508_09589_amd import _lib as L
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "st_api.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(st_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = L.load()
+    names = _declared()
+    assert "st_setup" in names and "st_solve" in names and "st_adjoint_solve" in names
+    assert "st_sensitivity" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L._SIGS), set(names) ^ set(L._SIGS)
+
+
+def test_struct_layouts_match():
+    lib = L.load()
+    out = (C.c_size_t * 7)()
+    assert lib.st_abi_sizes(out, 7) == 0
+    py = [C.sizeof(L.st_grid), C.sizeof(L.st_material), C.sizeof(L.st_patch),
+          C.sizeof(L.st_opts), C.sizeof(L.st_info), L.st_opts.flags.offset,
+          L.st_info.kclass_ms.offset]
+    assert list(out) == py
+
+
+def test_defaults_are_the_papers_parameters():
+    o = L.default_opts()
+    # §3.2: smoothing <= 10 its at rtol 1e-6, coarse <= 200 its at rtol 1e-6,
+    # lambda_crit 0.5 (§3.2.1); outer rtol 1e-8 for this solver.
+    assert (o.smooth_its, o.smooth_rtol, o.coarse_max_it, o.coarse_rtol) == (10, 1e-6, 200, 1e-6)
+    assert o.lambda_crit == 0.5 and o.rtol == 1e-8 and o.restart == 30
+    assert o.precision == L.ST_FP64
+
+
+def _fp(nx, ny, nt, tv, **kw):
+    lib = L.load()
+    g = L.st_grid(nx, ny, nt, 1.0 / max(nx, ny, 1), 1.0 / max(nt, 1))
+    m = L.st_material(1e-3, 1.0, 3.0, 1.0, 1.0, 1.0)
+    o = L.default_opts()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    b = C.c_size_t(0)
+    rc = lib.st_footprint_bytes(C.byref(g), C.byref(m), C.byref(o), tv, C.byref(b))
+    return rc, b.value
+
+
+def test_footprints_fit_one_gpu():
+    rc, b = _fp(512, 512, 1024, 0, precision=L.ST_MIXED, restart=20)
+    assert rc == 0 and b < 200e9, b
+    rc, b64 = _fp(512, 512, 1024, 0, precision=L.ST_FP64, restart=20)
+    assert rc == 0 and b < b64 < 280e9, (b, b64)
+    rc, b = _fp(256, 256, 256, 1, precision=L.ST_MIXED)
+    assert rc == 0 and b < 20e9
+
+
+@pytest.mark.parametrize("bad", [dict(nx=0), dict(nt=0), dict(restart=2), dict(restart=40),
+                                 dict(smooth_its=0), dict(smooth_its=20), dict(precision=7)])
+def test_invalid_arguments_rejected_on_host(bad):
+    nx, ny, nt = bad.pop("nx", 8), 8, bad.pop("nt", 8)
+    rc, _ = _fp(nx, ny, nt, 0, **bad)
+    assert rc == L.ST_ERR_ARG
+
+
+def test_setup_rejects_null_pointers_without_gpu():
+    lib = L.load()
+    g = L.st_grid(4, 4, 4, 0.25, 0.25)
+    m = L.st_material(1e-3, 1.0, 3.0, 1.0, 1.0, 1.0)
+    o = L.default_opts()
+    h = C.c_void_p()
+    rc = lib.st_setup(C.byref(g), C.byref(m), None, 0, None, None, 1.0, None, 0, C.byref(o),
+                      None, 0, None, C.byref(h))
+    assert rc == L.ST_ERR_ARG
+    assert L.status_string(L.ST_NOT_CONVERGED) == "not converged"
