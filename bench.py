@@ -1,0 +1,166 @@
+"""Benchmark: space-time DOFs solved per second to a 1e-8 relative residual.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large]
+                    [--precision mixed|fp64] [--no-cpu-baseline] [--compare-fp64]
+
+A step is one complete st_solve (FGMRES + space-time multigrid V-cycles, from
+a zero initial guess) of the workload; the design, hierarchy and right-hand
+side are resident in HBM before the timed region starts (setup is reported
+separately).  DOFs = all (nx+1)(ny+1)(nt+1) nodes, Dirichlet nodes included.
+
+Prints one JSON line with the throughput, the roofline of the dominant kernel
+class (algorithmic bytes / GPU time from HIP events recorded around each of
+its launches on the solver's stream during the timed steps) and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+
+
+def workload_problem(name, precision, time_kernels, bf16_from_level=0):
+    import torch
+    from paper_2508_09589_amd import Problem
+    from paper_2508_09589_amd.inputs import WORKLOADS, workload_density
+    w = WORKLOADS[name]
+    rho = workload_density(name)
+    restart = 20 if name == "large" else 30
+    t0 = time.perf_counter()
+    p = Problem(w["nx"], w["ny"], w["nt"], torch.tensor(rho), precision=precision, restart=restart,
+                rtol=1e-8, time_kernels=time_kernels, bf16_from_level=bf16_from_level)
+    torch.cuda.synchronize()
+    return p, time.perf_counter() - t0, restart
+
+
+def cpu_baseline(name):
+    """The FP64 oracle (block Gauss-Seidel in time with exact 2-D sparse LU
+    blocks) on the first few time slabs of the same grid, same dt, to the same
+    1e-8 relative residual.  Single-threaded (SuperLU)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle.assemble import load_vector
+    from oracle.grid import Grid, dirichlet_mask
+    from oracle.solve import BlockTimeSystem
+    from paper_2508_09589_amd.inputs import WORKLOADS, workload_density
+    w = WORKLOADS[name]
+    rho = workload_density(name)
+    slabs = {"large": 4, "medium": 8, "grad": 16, "small": 32}[name]
+    k = 1e-3 + (1 - 1e-3) * rho ** 3
+    if k.ndim == 3:
+        k = k[:slabs]
+    g = Grid(w["nx"], w["ny"], slabs, 1.0 / w["nx"], 1.0 / w["nt"])
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        mask = dirichlet_mask(g, [(0, 0.5, 0.05)])
+        f = load_vector(g, 1.0)
+        bs = BlockTimeSystem(g, k, np.ones_like(k), mask)
+        s, sweeps, rel = bs.gauss_seidel(bs.masked_rhs(f), tol=1e-8)
+        dt = time.perf_counter() - t0
+    return {"value": g.n_nodes / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {slabs} of {w['nt']} time slabs of the {w['nx']}x{w['ny']} grid "
+                      f"({g.n_nodes} nodes), block Gauss-Seidel in time with SuperLU blocks, "
+                      f"{sweeps} sweeps to rel. residual {rel:.1e}, {dt:.1f} s",
+            "seconds": dt}
+
+
+def run(args):
+    import torch
+    from paper_2508_09589_amd.solver import info_dict
+    from paper_2508_09589_amd import _lib as L
+
+    p, t_setup, restart = workload_problem(args.workload, args.precision, True,
+                                           args.bf16_from_level)
+    n_nodes = p.n_nodes
+    # Warm-up solves time every kernel class to find the dominant one.
+    warm = []
+    for _ in range(max(args.warmup, 1)):
+        T, info = p.solve()
+        warm.append(info_dict(info))
+    kern = warm[-1]["kernels"]
+    dom = max(kern, key=lambda c: kern[c]["ms"])
+    dom_idx = L.KCLASS_NAMES.index(dom)
+    # Timed steps record events only around launches of the dominant class.
+    p.set_flags(L.ST_FLAG_TIME_KERNELS | (1 << (8 + dom_idx)))
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        T, info = p.solve()
+        infos.append(info_dict(info))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    value = n_nodes * args.steps / elapsed
+    ms = sum(i["kernels"].get(dom, {}).get("ms", 0.0) for i in infos)
+    launches = sum(i["kernels"].get(dom, {}).get("launches", 0) for i in infos)
+    nbytes = sum(i["kernels"].get(dom, {}).get("bytes", 0) for i in infos)
+    achieved = (nbytes / (ms * 1e-3)) / 1e9 if ms > 0 else 0.0
+    last = infos[-1]
+    out = {
+        "metric": "space-time DOFs solved/s to 1e-8 rel. residual; operator-apply HBM GB/s",
+        "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": [p.nx, p.ny, p.nt], "dofs": n_nodes,
+                   "precision": args.precision, "fgmres_restart": restart, "rtol": 1e-8,
+                   "levels": last["levels"], "iterations": last["iterations"],
+                   "true_rel_res": last["true_rel_res"], "setup_s": t_setup,
+                   "bf16_from_level": args.bf16_from_level},
+        "roofline": {"bound": "hbm", "kernel_class": dom, "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "launches": launches,
+                     "avg_launch_ms": ms / launches if launches else None,
+                     "bytes_per_launch": nbytes / launches if launches else None},
+        "kernel_classes_warmup_ms": {c: round(v["ms"], 3) for c, v in kern.items()},
+    }
+    p.close()
+    del T
+    torch.cuda.empty_cache()
+    if args.compare_fp64 and args.precision != "fp64":
+        q, ts, _ = workload_problem(args.workload, "fp64", False)
+        Tq, iq = q.solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Tq, iq = q.solve()
+        torch.cuda.synchronize()
+        dtq = time.perf_counter() - t0
+        out["fp64_compare"] = {"value": n_nodes / dtq, "unit": "DOF/s",
+                               "iterations": iq.iterations, "true_rel_res": iq.true_rel_res,
+                               "setup_s": ts}
+        q.close()
+        del Tq
+        torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="large", choices=["small", "medium", "large", "grad"])
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--bf16-from-level", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--compare-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU time-slab sharding is a design only)", file=sys.stderr)
+        sys.exit(2)
+    print(json.dumps(run(args)), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -56,7 +56,8 @@ enum { ST_EDGE_X1_LO = 0, ST_EDGE_X1_HI = 1, ST_EDGE_X2_LO = 2, ST_EDGE_X2_HI = 
 
 /* Option flags. */
 enum {
-    ST_FLAG_TIME_KERNELS = 1,   /* record per-kernel-class GPU times in st_info   */
+    ST_FLAG_TIME_KERNELS = 1,   /* record per-kernel-class GPU times in st_info;
+                                   bits 8.. of flags select classes (0 = all)     */
     ST_FLAG_NO_PLANE_DEDUP = 2  /* keep every time level of coarse stencils       */
 };
 
@@ -109,9 +110,12 @@ typedef struct {
     double t_setup_s, t_solve_s;
     int32_t n_hist;
     double res_hist[ST_MAX_HIST];           /* residual estimate per iteration   */
-    /* ST_FLAG_TIME_KERNELS: GPU milliseconds and launch counts per class:
-       0 fine apply FP64, 1 fine apply V-cycle precision, 2 stencil apply,
-       3 multi-dot, 4 axpy/update, 5 transfers, 6 coarse solve, 7 casts/misc  */
+    /* ST_FLAG_TIME_KERNELS: GPU milliseconds, launch counts and algorithmic
+       bytes per class: 0 fine apply FP64, 1 fine apply in the V-cycle
+       precision, 2 coarse stencil apply, 3 level-0 smoother multi-dot,
+       4 level-0 smoother maxpy+norm, 5 restriction/prolongation, 6 coarsest
+       solve, 7 casts, 8/9 multi-dot/maxpy on coarse levels, 10 FGMRES
+       orthogonalisation, 11 solution updates                                 */
     double kclass_ms[ST_NUM_KCLASS];
     int64_t kclass_launches[ST_NUM_KCLASS];
     int64_t kclass_bytes[ST_NUM_KCLASS];    /* algorithmic bytes moved           */
@@ -176,6 +180,10 @@ st_status st_load_vector(st_handle* h, double* f_dev);
 /* Apply the density filter F (§3.3.2) to an element field of the design's
  * layout.  ST_ERR_STATE when the problem has no filter. */
 st_status st_filter(st_handle* h, const double* in_dev, double* out_dev);
+
+/* Replace the option flags (ST_FLAG_TIME_KERNELS and its class mask) of a
+ * built problem; the other options are fixed at setup. */
+st_status st_set_flags(st_handle* h, int32_t flags);
 
 /* Fill the hierarchy fields of *info (levels, dims, distinct planes). */
 st_status st_hierarchy(st_handle* h, st_info* info);

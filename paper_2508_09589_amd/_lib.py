@@ -14,8 +14,9 @@ ST_EDGE_X1_LO, ST_EDGE_X1_HI, ST_EDGE_X2_LO, ST_EDGE_X2_HI = 0, 1, 2, 3
 ST_FLAG_TIME_KERNELS, ST_FLAG_NO_PLANE_DEDUP = 1, 2
 ST_MAX_LEVELS, ST_MAX_PATCHES, ST_MAX_HIST, ST_NUM_KCLASS = 32, 4, 1024, 12
 
-KCLASS_NAMES = ["fine_apply_fp64", "fine_apply_vcycle", "stencil_apply", "multi_dot",
-                "axpy_update", "transfer", "coarse_solve", "misc", "c8", "c9", "c10", "c11"]
+KCLASS_NAMES = ["fine_apply_fp64", "fine_apply_vcycle", "stencil_apply", "smooth_mdot_l0",
+                "smooth_maxpy_l0", "transfer", "coarse_solve", "cast", "smooth_mdot_coarse",
+                "smooth_maxpy_coarse", "fgmres_orth", "update"]
 
 
 class st_grid(C.Structure):
@@ -70,6 +71,7 @@ _SIGS = {
     "st_load_vector": (C.c_int, [_P, _P]),
     "st_filter": (C.c_int, [_P, _P, _P]),
     "st_hierarchy": (C.c_int, [_P, C.POINTER(st_info)]),
+    "st_set_flags": (C.c_int, [_P, C.c_int32]),
     "st_destroy": (None, [_P]),
     "st_debug_apply": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P]),
     "st_debug_stencil": (C.c_int, [_P, C.c_int32, _P]),

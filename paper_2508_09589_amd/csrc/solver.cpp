@@ -278,13 +278,14 @@ struct Timed {
     int64_t bytes;
     hipEvent_t a = nullptr;
     Timed(st_handle* h_, int cls_, int64_t bytes_) : h(h_), cls(cls_), bytes(bytes_) {
-        if (h->timing) {
+        const unsigned sel = (unsigned)h->opts.flags >> 8;
+        if (h->timing && (sel == 0 || ((sel >> cls) & 1u))) {
             a = next_event(h);
             if (a) (void)hipEventRecord(a, h->stream);
         }
     }
     ~Timed() {
-        if (h->timing && a) {
+        if (a) {
             hipEvent_t b = next_event(h);
             if (b) {
                 (void)hipEventRecord(b, h->stream);
@@ -317,8 +318,9 @@ void collect_timing(st_handle* h, st_info* info) {
     h->evused = 0;
 }
 
+// Kernel classes of ST_FLAG_TIME_KERNELS (st_info.kclass_*).
 enum { KC_FINE64 = 0, KC_FINEV = 1, KC_STENCIL = 2, KC_DOT = 3, KC_AXPY = 4, KC_TRANSFER = 5,
-       KC_COARSE = 6, KC_MISC = 7 };
+       KC_COARSE = 6, KC_MISC = 7, KC_DOT_C = 8, KC_AXPY_C = 9, KC_OUTER = 10, KC_UPDATE = 11 };
 
 // ---------------------------------------------------------------------------
 // Operator applications on a level.  Level 0 is matrix-free; coarse levels
@@ -359,26 +361,27 @@ void smooth(st_handle* h, int l, int prec, int trans, const void* b, void* x, in
     auto Vj = [&](int j) { return (void*)(V + (size_t)j * n * vb); };
     const void* invd = level_invd(h, l, prec);
     launch_init_state(s, ks, its, rtol, 1, nullptr);
+    const int kd = l == 0 ? KC_DOT : KC_DOT_C, ka = l == 0 ? KC_AXPY : KC_AXPY_C;
     if (zero_x0) {
-        Timed t(h, KC_DOT, n * (int64_t)(3 * vb));
+        Timed t(h, kd, n * (int64_t)(3 * vb));
         launch_scale_norm(s, n, prec, b, invd, Vj(0), h->partials, ks, FIN_INIT_SELF, its, rtol, 1);
     } else {
         level_apply(h, l, prec, trans, x, Vj(0), b, invd, nullptr, nullptr);
-        Timed t(h, KC_DOT, n * (int64_t)vb);
+        Timed t(h, kd, n * (int64_t)vb);
         launch_mdot(s, n, prec, prec, Vj(0), Vj(0), n, 1, h->partials, ks, FIN_INIT_SELF, 0, 1);
     }
     for (int j = 0; j < its; ++j) {
         level_apply(h, l, prec, trans, Vj(j), Vj(j + 1), nullptr, invd, &ks->scale[j], &ks->done);
         {
-            Timed t(h, KC_DOT, n * (int64_t)vb * (j + 2));
+            Timed t(h, kd, n * (int64_t)vb * (j + 2));
             launch_mdot(s, n, prec, prec, Vj(j + 1), V, n, j + 1, h->partials, ks, FIN_PROJ1, j, SMAX);
         }
         {
-            Timed t(h, KC_AXPY, n * (int64_t)vb * (j + 3));
+            Timed t(h, ka, n * (int64_t)vb * (j + 3));
             launch_maxpy(s, n, prec, prec, Vj(j + 1), V, n, j + 1, h->partials, ks, FIN_GIVENS, j, SMAX);
         }
     }
-    Timed t(h, KC_AXPY, n * (int64_t)vb * (its + 2));
+    Timed t(h, KC_UPDATE, n * (int64_t)vb * (its + 2));
     launch_update(s, n, prec, prec, x, V, n, ks, zero_x0, SMAX);
 }
 
@@ -641,15 +644,15 @@ st_status fgmres(st_handle* h, const double* f, const double* fnorm_dev, double*
                                   nullptr, nullptr, 1, 1);
             }
             {
-                Timed t(h, KC_DOT, n * 8 * (j + 2));
+                Timed t(h, KC_OUTER, n * 8 * (j + 2));
                 launch_mdot(s, n, 0, 0, Vj(j + 1), h->V, n, j + 1, h->partials, ks, FIN_PROJ1, j, KMAX);
             }
             {
-                Timed t(h, KC_AXPY, n * 8 * (2 * j + 4));
+                Timed t(h, KC_OUTER, n * 8 * (j + 3));
                 launch_maxpy(s, n, 0, 0, Vj(j + 1), h->V, n, j + 1, h->partials, ks, FIN_PROJ2, j, KMAX);
             }
             {
-                Timed t(h, KC_AXPY, n * 8 * (j + 3));
+                Timed t(h, KC_OUTER, n * 8 * (j + 3));
                 launch_maxpy(s, n, 0, 0, Vj(j + 1), h->V, n, j + 1, h->partials, ks, FIN_GIVENS, j, KMAX);
             }
             HIPCHK(hipMemcpyAsync(h->hbuf, &ks->est, 4 * sizeof(double) + 4 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -665,7 +668,7 @@ st_status fgmres(st_handle* h, const double* f, const double* fnorm_dev, double*
         if (bad) break;
         (void)k;
         {
-            Timed t(h, KC_AXPY, n * (16 + zb * m));
+            Timed t(h, KC_UPDATE, n * (16 + zb * m));
             launch_update(s, n, 0, zp, x, h->Z, n, ks, 0, KMAX);
         }
         // true residual
@@ -953,6 +956,14 @@ st_status st_filter(st_handle* h, const double* in_dev, double* out_dev) {
     st_status rc = filter_apply(h, in_dev, out_dev);
     if (rc != ST_OK) return rc;
     HIPCHK(hipStreamSynchronize(h->stream));
+    return ST_OK;
+}
+
+st_status st_set_flags(st_handle* h, int32_t flags) {
+    if (!h) return ST_ERR_ARG;
+    const int keep = h->opts.flags & ST_FLAG_NO_PLANE_DEDUP;
+    h->opts.flags = (flags & ~ST_FLAG_NO_PLANE_DEDUP) | keep;
+    h->timing = (flags & ST_FLAG_TIME_KERNELS) != 0;
     return ST_OK;
 }
 

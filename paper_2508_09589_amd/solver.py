@@ -132,6 +132,9 @@ class Problem:
         rho = _dev_f64(rho, self.device).reshape(self.design_shape)
         L.check("st_update_density", self.lib.st_update_density(self.h, _ptr(rho)))
 
+    def set_flags(self, flags):
+        L.check("st_set_flags", self.lib.st_set_flags(self.h, int(flags)))
+
     def hierarchy(self):
         info = L.st_info()
         L.check("st_hierarchy", self.lib.st_hierarchy(self.h, C.byref(info)))
@@ -190,6 +193,7 @@ class Problem:
         if getattr(self, "h", None):
             self.lib.st_destroy(self.h)
             self.h = None
+        self.workspace = None
 
     def __del__(self):
         try:
