@@ -26,7 +26,11 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 
 
-def workload_problem(name, precision, time_kernels, bf16_from_level=0):
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload_problem(name, precision, time_kernels, bf16_from_level=0, max_it=1000):
     import torch
     from paper_2508_09589_amd import Problem
     from paper_2508_09589_amd.inputs import WORKLOADS, workload_density
@@ -35,8 +39,11 @@ def workload_problem(name, precision, time_kernels, bf16_from_level=0):
     restart = 20 if name == "large" else 30
     t0 = time.perf_counter()
     p = Problem(w["nx"], w["ny"], w["nt"], torch.tensor(rho), precision=precision, restart=restart,
-                rtol=1e-8, time_kernels=time_kernels, bf16_from_level=bf16_from_level)
+                rtol=1e-8, time_kernels=time_kernels, bf16_from_level=bf16_from_level,
+                max_it=max_it)
     torch.cuda.synchronize()
+    log(f"{name} {precision}: setup {time.perf_counter() - t0:.2f} s, {p.n_nodes} nodes, "
+        f"levels {p.hierarchy()[0]}")
     return p, time.perf_counter() - t0, restart
 
 
@@ -77,13 +84,16 @@ def run(args):
     from paper_2508_09589_amd import _lib as L
 
     p, t_setup, restart = workload_problem(args.workload, args.precision, True,
-                                           args.bf16_from_level)
+                                           args.bf16_from_level, args.max_it)
     n_nodes = p.n_nodes
     # Warm-up solves time every kernel class to find the dominant one.
     warm = []
     for _ in range(max(args.warmup, 1)):
-        T, info = p.solve()
+        t0 = time.perf_counter()
+        T, info = p.solve(allow_not_converged=True)
         warm.append(info_dict(info))
+        log(f"warm-up solve: {info.iterations} its, true rel res {info.true_rel_res:.2e}, "
+            f"{time.perf_counter() - t0:.2f} s (all kernel classes timed)")
     kern = warm[-1]["kernels"]
     dom = max(kern, key=lambda c: kern[c]["ms"])
     dom_idx = L.KCLASS_NAMES.index(dom)
@@ -92,9 +102,10 @@ def run(args):
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         T, info = p.solve()
         infos.append(info_dict(info))
+        log(f"step {k}: {info.iterations} its, {info.t_solve_s:.3f} s")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
@@ -126,7 +137,7 @@ def run(args):
     del T
     torch.cuda.empty_cache()
     if args.compare_fp64 and args.precision != "fp64":
-        q, ts, _ = workload_problem(args.workload, "fp64", False)
+        q, ts, _ = workload_problem(args.workload, "fp64", False, 0, args.max_it)
         Tq, iq = q.solve()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -140,6 +151,7 @@ def run(args):
         del Tq
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
+        log("CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(args.workload)
     return out
 
@@ -154,6 +166,7 @@ def main():
     ap.add_argument("--bf16-from-level", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare-fp64", action="store_true")
+    ap.add_argument("--max-it", type=int, default=400)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
