@@ -14,6 +14,14 @@
 
 namespace st {
 
+// Blocks of the vectorised reductions: four elements per thread per step.
+static inline unsigned red_grid4(long long n) {
+    long long nb = (n + 8LL * VEC_THREADS - 1) / (8LL * VEC_THREADS);
+    if (nb < 1) nb = 1;
+    if (nb > RED_BLOCKS) nb = RED_BLOCKS;
+    return (unsigned)nb;
+}
+
 static inline unsigned red_grid(long long n) {
     long long nb = (n + 4LL * VEC_THREADS - 1) / (4LL * VEC_THREADS);
     if (nb < 1) nb = 1;
@@ -28,6 +36,30 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 template <typename T> __device__ __forceinline__ double ldd(const T* p) { return (double)*p; }
+
+// ---------------------------------------------------------------------------
+// Vectorised variants: four consecutive elements per thread per step (one
+// 16-byte load for FP32, two for FP64), all pointers aligned to 4 elements and
+// the basis stride a multiple of 4; the host picks them only when that holds.
+template <typename T> struct V4;
+template <> struct V4<float> { using type = float4; };
+template <> struct V4<double> { using type = double4; };
+
+template <typename T>
+__device__ __forceinline__ void ld4(const T* p, double o[4]) {
+    const typename V4<T>::type v = *reinterpret_cast<const typename V4<T>::type*>(p);
+    o[0] = (double)v.x; o[1] = (double)v.y; o[2] = (double)v.z; o[3] = (double)v.w;
+}
+template <typename T>
+__device__ __forceinline__ void st4(T* p, const double o[4]) {
+    typename V4<T>::type v;
+    v.x = (T)o[0]; v.y = (T)o[1]; v.z = (T)o[2]; v.w = (T)o[3];
+    *reinterpret_cast<typename V4<T>::type*>(p) = v;
+}
+
+static inline bool al4(const void* p, size_t esz) {
+    return ((uintptr_t)p % (4 * esz)) == 0;
+}
 
 // ---------------------------------------------------------------------------
 // Scalar finalisation (thread 0 of the last block).
@@ -187,6 +219,34 @@ __global__ __launch_bounds__(VEC_THREADS) void k_scale_norm(long long n, const T
     block_finish<1>(acc, 1, partials, ks, mode, 0, nullptr);
 }
 
+template <typename T>
+__global__ __launch_bounds__(VEC_THREADS) void k_scale_norm4(long long n, const T* __restrict__ b,
+                                                             const T* __restrict__ invd,
+                                                             T* __restrict__ w,
+                                                             double* __restrict__ partials,
+                                                             KState* ks, int mode) {
+    double acc[1] = {0.0};
+    const long long n4 = n >> 2;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n4; q += stride) {
+        typename V4<T>::type bv = *reinterpret_cast<const typename V4<T>::type*>(b + 4 * q);
+        if (invd) {
+            const typename V4<T>::type dv = *reinterpret_cast<const typename V4<T>::type*>(invd + 4 * q);
+            bv.x *= dv.x; bv.y *= dv.y; bv.z *= dv.z; bv.w *= dv.w;
+        }
+        *reinterpret_cast<typename V4<T>::type*>(w + 4 * q) = bv;
+        acc[0] += (double)bv.x * (double)bv.x + (double)bv.y * (double)bv.y +
+                  (double)bv.z * (double)bv.z + (double)bv.w * (double)bv.w;
+    }
+    for (long long i = 4 * n4 + blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += stride) {
+        T v = b[i];
+        if (invd) v *= invd[i];
+        w[i] = v;
+        acc[0] += (double)v * (double)v;
+    }
+    block_finish<1>(acc, 1, partials, ks, mode, 0, nullptr);
+}
+
 __global__ void k_init_state(KState* ks, int maxit, double rtol, int scale_update,
                              const double* ref) {
     if (threadIdx.x == 0) {
@@ -213,6 +273,17 @@ void launch_scale_norm(hipStream_t s, long long n, int prec, const void* b, cons
     (void)rtol;
     (void)scale_update;
     const unsigned nb = red_grid(n);
+    const size_t es = prec ? 4 : 8;
+    if (al4(b, es) && al4(w, es) && (!invd || al4(invd, es))) {
+        const unsigned nb4 = red_grid4(n);
+        if (prec == 0)
+            hipLaunchKernelGGL(k_scale_norm4<double>, dim3(nb4), dim3(VEC_THREADS), 0, s, n,
+                               (const double*)b, (const double*)invd, (double*)w, partials, ks, mode);
+        else
+            hipLaunchKernelGGL(k_scale_norm4<float>, dim3(nb4), dim3(VEC_THREADS), 0, s, n,
+                               (const float*)b, (const float*)invd, (float*)w, partials, ks, mode);
+        return;
+    }
     if (prec == 0)
         hipLaunchKernelGGL(k_scale_norm<double>, dim3(nb), dim3(VEC_THREADS), 0, s, n,
                            (const double*)b, (const double*)invd, (double*)w, partials, ks, mode);
@@ -277,11 +348,98 @@ __global__ __launch_bounds__(VEC_THREADS) void k_maxpy(long long n, TW* __restri
     block_finish<MAXD>(acc, redot ? nd : 1, partials, ks, mode, j, nullptr);
 }
 
+template <typename TW, typename TV, int MAXD>
+__global__ __launch_bounds__(VEC_THREADS) void k_mdot4(long long n, const TW* __restrict__ w,
+                                                       const TV* __restrict__ V, long long ldv,
+                                                       int nd, double* __restrict__ partials,
+                                                       KState* ks, int mode, int j) {
+    if (ks && ks->done) return;
+    double acc[MAXD];
+#pragma unroll
+    for (int d = 0; d < MAXD; ++d) acc[d] = 0.0;
+    const long long n4 = n >> 2;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n4; q += stride) {
+        double wv[4];
+        ld4(w + 4 * q, wv);
+#pragma unroll
+        for (int d = 0; d < MAXD; ++d)
+            if (d < nd) {
+                double vv[4];
+                ld4(V + (long long)d * ldv + 4 * q, vv);
+                acc[d] += vv[0] * wv[0] + vv[1] * wv[1] + vv[2] * wv[2] + vv[3] * wv[3];
+            }
+    }
+    for (long long i = 4 * n4 + blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double wv = (double)w[i];
+#pragma unroll
+        for (int d = 0; d < MAXD; ++d)
+            if (d < nd) acc[d] += (double)V[(long long)d * ldv + i] * wv;
+    }
+    block_finish<MAXD>(acc, nd, partials, ks, mode, j, nullptr);
+}
+
+// w -= sum_d coef_d V_d and ||w||^2 (FIN_GIVENS) -- the vectorised path has no
+// re-orthogonalisation mode.
+template <typename TW, typename TV, int MAXD>
+__global__ __launch_bounds__(VEC_THREADS) void k_maxpy4(long long n, TW* __restrict__ w,
+                                                        const TV* __restrict__ V, long long ldv,
+                                                        int nd, double* __restrict__ partials,
+                                                        KState* ks, int mode, int j) {
+    if (ks->done) return;
+    __shared__ double c[MAXD];
+    if (threadIdx.x < MAXD) c[threadIdx.x] = (int)threadIdx.x < nd ? ks->coef[threadIdx.x] : 0.0;
+    __syncthreads();
+    double acc[1] = {0.0};
+    const long long n4 = n >> 2;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n4; q += stride) {
+        double wv[4];
+        ld4(w + 4 * q, wv);
+#pragma unroll
+        for (int d = 0; d < MAXD; ++d)
+            if (d < nd) {
+                double vv[4];
+                ld4(V + (long long)d * ldv + 4 * q, vv);
+                const double cd = c[d];
+                wv[0] -= cd * vv[0]; wv[1] -= cd * vv[1]; wv[2] -= cd * vv[2]; wv[3] -= cd * vv[3];
+            }
+        // round to the storage type before the norm, as the scalar path does
+        typename V4<TW>::type o;
+        o.x = (TW)wv[0]; o.y = (TW)wv[1]; o.z = (TW)wv[2]; o.w = (TW)wv[3];
+        *reinterpret_cast<typename V4<TW>::type*>(w + 4 * q) = o;
+        acc[0] += (double)o.x * (double)o.x + (double)o.y * (double)o.y +
+                  (double)o.z * (double)o.z + (double)o.w * (double)o.w;
+    }
+    for (long long i = 4 * n4 + blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += stride) {
+        double wv = (double)w[i];
+#pragma unroll
+        for (int d = 0; d < MAXD; ++d)
+            if (d < nd) wv -= c[d] * (double)V[(long long)d * ldv + i];
+        const TW wo = (TW)wv;
+        w[i] = wo;
+        acc[0] += (double)wo * (double)wo;
+    }
+    (void)mode;
+    block_finish<1>(acc, 1, partials, ks, FIN_GIVENS, j, nullptr);
+}
+
 template <int MAXD>
 static void mdot_dispatch(hipStream_t s, long long n, int pw, int pv, const void* w,
                           const void* V, long long ldv, int nd, double* partials, KState* ks,
                           int mode, int j) {
     const unsigned nb = red_grid(n);
+    const bool vec = pw == pv && ldv % 4 == 0 && al4(w, pw ? 4 : 8) && al4(V, pv ? 4 : 8);
+    if (vec) {
+        const unsigned nb4 = red_grid4(n);
+        if (pw == 0)
+            hipLaunchKernelGGL((k_mdot4<double, double, MAXD>), dim3(nb4), dim3(VEC_THREADS), 0, s,
+                               n, (const double*)w, (const double*)V, ldv, nd, partials, ks, mode, j);
+        else
+            hipLaunchKernelGGL((k_mdot4<float, float, MAXD>), dim3(nb4), dim3(VEC_THREADS), 0, s,
+                               n, (const float*)w, (const float*)V, ldv, nd, partials, ks, mode, j);
+        return;
+    }
     if (pw == 0 && pv == 0)
         hipLaunchKernelGGL((k_mdot<double, double, MAXD>), dim3(nb), dim3(VEC_THREADS), 0, s, n,
                            (const double*)w, (const double*)V, ldv, nd, partials, ks, mode, j);
@@ -311,6 +469,18 @@ template <int MAXD>
 static void maxpy_dispatch(hipStream_t s, long long n, int pw, int pv, void* w, const void* V,
                            long long ldv, int nd, double* partials, KState* ks, int mode, int j) {
     const unsigned nb = red_grid(n);
+    const bool vec = mode == FIN_GIVENS && pw == pv && ldv % 4 == 0 && al4(w, pw ? 4 : 8) &&
+                     al4(V, pv ? 4 : 8);
+    if (vec) {
+        const unsigned nb4 = red_grid4(n);
+        if (pw == 0)
+            hipLaunchKernelGGL((k_maxpy4<double, double, MAXD>), dim3(nb4), dim3(VEC_THREADS), 0,
+                               s, n, (double*)w, (const double*)V, ldv, nd, partials, ks, mode, j);
+        else
+            hipLaunchKernelGGL((k_maxpy4<float, float, MAXD>), dim3(nb4), dim3(VEC_THREADS), 0, s,
+                               n, (float*)w, (const float*)V, ldv, nd, partials, ks, mode, j);
+        return;
+    }
     if (pw == 0 && pv == 0)
         hipLaunchKernelGGL((k_maxpy<double, double, MAXD>), dim3(nb), dim3(VEC_THREADS), 0, s, n,
                            (double*)w, (const double*)V, ldv, nd, partials, ks, mode, j);
@@ -343,11 +513,52 @@ __global__ __launch_bounds__(VEC_THREADS) void k_update(long long n, TX* __restr
     }
 }
 
+template <typename TX, typename TV>
+__global__ __launch_bounds__(VEC_THREADS) void k_update4(long long n, TX* __restrict__ x,
+                                                         const TV* __restrict__ V, long long ldv,
+                                                         const KState* __restrict__ ks,
+                                                         int zero_x0) {
+    const int k = ks->k;
+    if (k == 0 && !zero_x0) return;
+    const long long n4 = n >> 2;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n4; q += stride) {
+        double xv[4] = {0.0, 0.0, 0.0, 0.0};
+        if (!zero_x0) ld4(x + 4 * q, xv);
+        for (int d = 0; d < k; ++d) {
+            double vv[4];
+            ld4(V + (long long)d * ldv + 4 * q, vv);
+            const double yd = ks->y[d];
+            xv[0] += yd * vv[0]; xv[1] += yd * vv[1]; xv[2] += yd * vv[2]; xv[3] += yd * vv[3];
+        }
+        st4(x + 4 * q, xv);
+    }
+    for (long long i = 4 * n4 + blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += stride) {
+        double v = zero_x0 ? 0.0 : (double)x[i];
+        for (int d = 0; d < k; ++d) v += ks->y[d] * (double)V[(long long)d * ldv + i];
+        x[i] = (TX)v;
+    }
+}
+
 void launch_update(hipStream_t s, long long n, int prec_x, int prec_v, void* x, const void* V,
                    long long ldv, KState* ks, int zero_x0, int maxd) {
     (void)maxd;
     long long nb = (n + VEC_THREADS - 1) / VEC_THREADS;
     if (nb > 65535) nb = 65535;
+    const bool vec = ldv % 4 == 0 && al4(x, prec_x ? 4 : 8) && al4(V, prec_v ? 4 : 8);
+    if (vec) {
+        const unsigned nb4 = red_grid4(n);
+        if (prec_x == 0 && prec_v == 0)
+            hipLaunchKernelGGL((k_update4<double, double>), dim3(nb4), dim3(VEC_THREADS), 0, s, n,
+                               (double*)x, (const double*)V, ldv, ks, zero_x0);
+        else if (prec_x == 0 && prec_v == 1)
+            hipLaunchKernelGGL((k_update4<double, float>), dim3(nb4), dim3(VEC_THREADS), 0, s, n,
+                               (double*)x, (const float*)V, ldv, ks, zero_x0);
+        else
+            hipLaunchKernelGGL((k_update4<float, float>), dim3(nb4), dim3(VEC_THREADS), 0, s, n,
+                               (float*)x, (const float*)V, ldv, ks, zero_x0);
+        return;
+    }
     if (prec_x == 0 && prec_v == 0)
         hipLaunchKernelGGL((k_update<double, double>), dim3((unsigned)nb), dim3(VEC_THREADS), 0, s,
                            n, (double*)x, (const double*)V, ldv, ks, zero_x0);
@@ -397,40 +608,47 @@ __device__ __forceinline__ double block_sum_1(double v, double* sh) {
     return sh[CT / 64];
 }
 
-template <typename TIO>
+// LDS layout: the current basis vector v_j and the work vector w (2n doubles)
+// when they fit (USE_LDS), otherwise both live in global memory.
+template <typename TIO, bool USE_LDS>
 __global__ __launch_bounds__(CT) void k_coarse_gmres(
     int nx, int ny, int nt, int nplanes, const double* __restrict__ st,
     const int* __restrict__ pmap, const double* __restrict__ invd, const TIO* __restrict__ bio,
     TIO* __restrict__ xio, double* __restrict__ V, double* __restrict__ work, int maxit,
     int restart, double rtol, int zero_x0, int trans) {
-    const long long row = nx + 1, P = row * (ny + 1), n = P * (nt + 1);
-    const long long DS = P * nplanes;
+    const int row = nx + 1, P = row * (ny + 1), n = P * (nt + 1);
+    const long long DS = (long long)P * nplanes;
+    extern __shared__ double dyn[];
     double* x = work;
-    double* w = work + n;
+    double* w = USE_LDS ? dyn : work + n;
+    double* vj = USE_LDS ? dyn + n : work + 2 * n;
     __shared__ double H[KMAX + 1][KMAX];
     __shared__ double cs[KMAX], sn[KMAX], g[KMAX + 1], y[KMAX], h[KMAX + 1];
     __shared__ double sh[CT / 64 + 1];
     __shared__ int flag;
     const int tid = threadIdx.x;
 
-    auto apply = [&](const double* in, long long idx) -> double {
-        const int nn0 = (int)(idx / P);
-        const long long r = idx - nn0 * P;
-        const int j = (int)(r / row), i = (int)(r - (long long)j * row);
+    // (A v)[idx] for a vector in LDS/global, forward or transposed stencil.
+    auto apply = [&](const double* in, int idx) -> double {
+        const int nn0 = idx / P;
+        const int r = idx - nn0 * P;
+        const int j = r / row, i = r - j * row;
         double acc = 0.0;
+#pragma unroll
         for (int dn = -1; dn <= 1; ++dn) {
             const int nn = nn0 + dn;
             if (nn < 0 || nn > nt) continue;
+#pragma unroll
             for (int dj = -1; dj <= 1; ++dj) {
                 const int jj = j + dj;
                 if (jj < 0 || jj > ny) continue;
+#pragma unroll
                 for (int di = -1; di <= 1; ++di) {
                     const int ii = i + di;
                     if (ii < 0 || ii > nx) continue;
                     const int d = (dn + 1) * 9 + (dj + 1) * 3 + (di + 1);
-                    const long long nb = (long long)nn * P + (long long)jj * row + ii;
-                    const double a = trans ? st[(long long)(26 - d) * DS + (long long)pmap[nn] * P +
-                                                (long long)jj * row + ii]
+                    const int nb = nn * P + jj * row + ii;
+                    const double a = trans ? st[(long long)(26 - d) * DS + (long long)pmap[nn] * P + jj * row + ii]
                                            : st[(long long)d * DS + (long long)pmap[nn0] * P + r];
                     acc += a * in[nb];
                 }
@@ -439,13 +657,12 @@ __global__ __launch_bounds__(CT) void k_coarse_gmres(
         return acc;
     };
 
-    for (long long i = tid; i < n; i += CT) x[i] = zero_x0 ? 0.0 : (double)xio[i];
+    for (int i = tid; i < n; i += CT) x[i] = zero_x0 ? 0.0 : (double)xio[i];
     __syncthreads();
-    // r0 = D^-1 (b - A x) into V[0]
     double loc = 0.0;
-    for (long long i = tid; i < n; i += CT) {
+    for (int i = tid; i < n; i += CT) {
         const double v = invd[i] * ((double)bio[i] - (zero_x0 ? 0.0 : apply(x, i)));
-        V[i] = v;
+        w[i] = v;
         loc += v * v;
     }
     double beta = sqrt(block_sum_1(loc, sh));
@@ -453,30 +670,44 @@ __global__ __launch_bounds__(CT) void k_coarse_gmres(
     int its = 0;
     bool finished = !(beta > 0.0) || !isfinite(beta);
     while (!finished) {
-        for (long long i = tid; i < n; i += CT) V[i] *= 1.0 / beta;
+        const double ib = 1.0 / beta;
+        for (int i = tid; i < n; i += CT) {
+            const double v = w[i] * ib;
+            vj[i] = v;
+            V[i] = v;
+        }
         if (tid < KMAX + 1) g[tid] = 0.0;
         __syncthreads();
         if (tid == 0) g[0] = beta;
         int k = 0;
         bool stop = false;
         for (int jcol = 0; jcol < restart && !stop; ++jcol) {
-            const double* vj = V + (long long)jcol * n;
             __syncthreads();
-            for (long long i = tid; i < n; i += CT) w[i] = invd[i] * apply(vj, i);
+            for (int i = tid; i < n; i += CT) w[i] = invd[i] * apply(vj, i);
             __syncthreads();
-            // projections h_d = <v_d, w>, d <= jcol: 32 threads per d
+            // h_d = <v_d, w>, d <= jcol: 32 lanes per d, 4 independent sums
             {
                 const int d = tid >> 5, q = tid & 31;
-                double a = 0.0;
-                if (d <= jcol)
-                    for (long long i = q; i < n; i += 32) a += V[(long long)d * n + i] * w[i];
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                if (d <= jcol) {
+                    const double* vd = V + (long long)d * n;
+                    int i = q;
+                    for (; i + 96 < n; i += 128) {
+                        a0 += vd[i] * w[i];
+                        a1 += vd[i + 32] * w[i + 32];
+                        a2 += vd[i + 64] * w[i + 64];
+                        a3 += vd[i + 96] * w[i + 96];
+                    }
+                    for (; i < n; i += 32) a0 += vd[i] * w[i];
+                }
+                double a = (a0 + a1) + (a2 + a3);
 #pragma unroll
                 for (int o = 16; o > 0; o >>= 1) a += __shfl_down(a, o, 32);
                 if (q == 0 && d <= jcol) h[d] = a;
             }
             __syncthreads();
             loc = 0.0;
-            for (long long i = tid; i < n; i += CT) {
+            for (int i = tid; i < n; i += CT) {
                 double v = w[i];
                 for (int d = 0; d <= jcol; ++d) v -= h[d] * V[(long long)d * n + i];
                 w[i] = v;
@@ -484,7 +715,6 @@ __global__ __launch_bounds__(CT) void k_coarse_gmres(
             }
             const double hn = sqrt(block_sum_1(loc, sh));
             if (tid == 0) {
-                // rotate column jcol in place in shared H
                 double hn2 = hn * hn;
                 for (int i = 0; i <= jcol; ++i) {
                     H[i][jcol] = h[i];
@@ -520,10 +750,14 @@ __global__ __launch_bounds__(CT) void k_coarse_gmres(
             const int f = flag;
             if (f) {
                 stop = true;
-                if (f & 3) finished = true;
-                if (f & 4) finished = true;
+                finished = true;
             } else if (jcol + 1 < restart) {
-                for (long long i = tid; i < n; i += CT) V[(long long)(jcol + 1) * n + i] = w[i] / hn;
+                const double ih = 1.0 / hn;
+                for (int i = tid; i < n; i += CT) {
+                    const double v = w[i] * ih;
+                    vj[i] = v;
+                    V[(long long)(jcol + 1) * n + i] = v;
+                }
             }
         }
         __syncthreads();
@@ -535,7 +769,7 @@ __global__ __launch_bounds__(CT) void k_coarse_gmres(
             }
         }
         __syncthreads();
-        for (long long i = tid; i < n; i += CT) {
+        for (int i = tid; i < n; i += CT) {
             double v = x[i];
             for (int d = 0; d < k; ++d) v += y[d] * V[(long long)d * n + i];
             x[i] = v;
@@ -543,29 +777,45 @@ __global__ __launch_bounds__(CT) void k_coarse_gmres(
         __syncthreads();
         if (finished || its >= maxit) break;
         loc = 0.0;
-        for (long long i = tid; i < n; i += CT) {
+        for (int i = tid; i < n; i += CT) {
             const double v = invd[i] * ((double)bio[i] - apply(x, i));
-            V[i] = v;
+            w[i] = v;
             loc += v * v;
         }
         beta = sqrt(block_sum_1(loc, sh));
         if (!(beta > 0.0) || !isfinite(beta)) break;
     }
     __syncthreads();
-    for (long long i = tid; i < n; i += CT) xio[i] = (TIO)x[i];
+    for (int i = tid; i < n; i += CT) xio[i] = (TIO)x[i];
 }
 
+// work must hold 3 n doubles (x, and w / v_j when they do not fit in LDS).
 void launch_coarse_solve(hipStream_t s, const Level& L, int prec_io, int trans, const void* b,
                          void* x, double* V, double* work, int maxit, int restart, double rtol,
                          int zero_x0) {
-    if (prec_io == 0)
-        hipLaunchKernelGGL(k_coarse_gmres<double>, dim3(1), dim3(CT), 0, s, L.nx, L.ny, L.nt,
-                           L.nplanes, L.st64, L.plane_map, L.invd64, (const double*)b, (double*)x,
-                           V, work, maxit, restart, rtol, zero_x0, trans);
-    else
-        hipLaunchKernelGGL(k_coarse_gmres<float>, dim3(1), dim3(CT), 0, s, L.nx, L.ny, L.nt,
-                           L.nplanes, L.st64, L.plane_map, L.invd64, (const float*)b, (float*)x, V,
-                           work, maxit, restart, rtol, zero_x0, trans);
+    const long long n = L.nn;
+    const size_t lds = (size_t)2 * n * sizeof(double);
+    const bool use_lds = lds <= 52 * 1024;   // stays within the default 64 KB per block
+    const size_t dyn = use_lds ? lds : 0;
+    if (prec_io == 0) {
+        if (use_lds)
+            hipLaunchKernelGGL((k_coarse_gmres<double, true>), dim3(1), dim3(CT), dyn, s, L.nx, L.ny,
+                               L.nt, L.nplanes, L.st64, L.plane_map, L.invd64, (const double*)b,
+                               (double*)x, V, work, maxit, restart, rtol, zero_x0, trans);
+        else
+            hipLaunchKernelGGL((k_coarse_gmres<double, false>), dim3(1), dim3(CT), 0, s, L.nx, L.ny,
+                               L.nt, L.nplanes, L.st64, L.plane_map, L.invd64, (const double*)b,
+                               (double*)x, V, work, maxit, restart, rtol, zero_x0, trans);
+    } else {
+        if (use_lds)
+            hipLaunchKernelGGL((k_coarse_gmres<float, true>), dim3(1), dim3(CT), dyn, s, L.nx, L.ny,
+                               L.nt, L.nplanes, L.st64, L.plane_map, L.invd64, (const float*)b,
+                               (float*)x, V, work, maxit, restart, rtol, zero_x0, trans);
+        else
+            hipLaunchKernelGGL((k_coarse_gmres<float, false>), dim3(1), dim3(CT), 0, s, L.nx, L.ny,
+                               L.nt, L.nplanes, L.st64, L.plane_map, L.invd64, (const float*)b,
+                               (float*)x, V, work, maxit, restart, rtol, zero_x0, trans);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -21,12 +21,6 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
     return (uint16_t)(u >> 16);
 }
 
-template <typename S> __device__ __forceinline__ float ld_st(const S* p);
-template <> __device__ __forceinline__ float ld_st<float>(const float* p) { return *p; }
-template <> __device__ __forceinline__ float ld_st<uint16_t>(const uint16_t* p) {
-    return bf16_to_f32(*p);
-}
-
 static inline unsigned grid_for(long long n, int threads = 256, long long cap = 65535) {
     long long nb = (n + threads - 1) / threads;
     if (nb < 1) nb = 1;
@@ -37,146 +31,138 @@ static inline unsigned grid_for(long long n, int threads = 256, long long cap = 
 // ---------------------------------------------------------------------------
 // y = A x (or A^T x) with the same epilogue as the fine apply:
 //   v = A x;  if b: v = b - v;  if invd: v *= invd;  v *= scale.
+// A thread owns one in-plane position r = j (nx+1) + i and marches through a
+// chunk of time levels, keeping the x values of levels n-1, n, n+1 around r in
+// registers (9 new loads per level).  The 27 coefficients of a row depend on
+// the plane index only, so they are loaded again only when plane_map changes
+// (time-invariant operators load them a handful of times per column).
+template <typename S> __device__ __forceinline__ float ldc(const S* p);
+template <> __device__ __forceinline__ float ldc<float>(const float* p) { return *p; }
+template <> __device__ __forceinline__ float ldc<uint16_t>(const uint16_t* p) {
+    return bf16_to_f32(*p);
+}
+template <typename TC, typename S> __device__ __forceinline__ TC ldcoef(const S* p) {
+    return (TC)ldc<S>(p);
+}
+template <> __device__ __forceinline__ double ldcoef<double, double>(const double* p) {
+    return *p;
+}
+
 template <typename T, typename S, typename TC, bool TRANS>
-__global__ __launch_bounds__(256) void k_stencil_apply(
+__global__ __launch_bounds__(256) void k_stencil_march(
     int nx, int ny, int nt, int nplanes, const S* __restrict__ st, const int* __restrict__ pmap,
     const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ b,
-    const T* __restrict__ invd, const double* __restrict__ scale, const int* __restrict__ skip) {
+    const T* __restrict__ invd, const double* __restrict__ scale, const int* __restrict__ skip,
+    int nchunk) {
     if (skip && *skip) return;
-    const long long rowp = nx + 1;
-    const long long P = rowp * (ny + 1);
-    const long long N = P * (nt + 1);
-    const long long DS = P * nplanes;   // stride between stencil entries
+    const int rowp = nx + 1;
+    const int P = rowp * (ny + 1);
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= P) return;
+    const int n0 = blockIdx.y * nchunk;
+    if (n0 > nt) return;
+    const int n1 = min(n0 + nchunk, nt + 1);
+    const int j = r / rowp, i = r - j * rowp;
+    const long long DS = (long long)P * nplanes;
+    unsigned valid = 0;
+    int off[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const int di = q % 3 - 1, dj = q / 3 - 1;
+        off[q] = dj * rowp + di;
+        if (i + di >= 0 && i + di <= nx && j + dj >= 0 && j + dj <= ny) valid |= 1u << q;
+    }
+    auto load_plane = [&](int n, TC u[9]) {
+        if (n < 0 || n > nt) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) u[q] = (TC)0;
+            return;
+        }
+        const T* xp = x + (long long)n * P + r;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) u[q] = ((valid >> q) & 1u) ? (TC)xp[off[q]] : (TC)0;
+    };
+    TC xm[9], xc[9], xp[9], c[27];
+    load_plane(n0 - 1, xm);
+    load_plane(n0, xc);
+    int key0 = -2, key1 = -2, key2 = -2;
     const TC sc = scale ? (TC)(*scale) : (TC)1;
-    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < N;
-         idx += (long long)gridDim.x * blockDim.x) {
-        const int n = (int)(idx / P);
-        const long long r = idx - n * P;
-        const int j = (int)(r / rowp), i = (int)(r - (long long)j * rowp);
-        TC acc = 0;
+    for (int n = n0; n < n1; ++n) {
+        load_plane(n + 1, xp);
+        const int pm = n > 0 ? pmap[n - 1] : -1;
+        const int pc = pmap[n];
+        const int pp = n < nt ? pmap[n + 1] : -1;
+        const bool same = TRANS ? (pm == key0 && pc == key1 && pp == key2) : (pc == key1);
+        if (!same) {
+            key0 = pm;
+            key1 = pc;
+            key2 = pp;
+            if (!TRANS) {
+                const S* sp = st + (long long)pc * P + r;
 #pragma unroll
-        for (int dn = -1; dn <= 1; ++dn) {
-            const int nn = n + dn;
-            if (nn < 0 || nn > nt) continue;
-            const long long pl = TRANS ? (long long)pmap[nn] * P : (long long)pmap[n] * P;
+                for (int d = 0; d < 27; ++d) c[d] = ldcoef<TC, S>(sp + (long long)d * DS);
+            } else {
 #pragma unroll
-            for (int dj = -1; dj <= 1; ++dj) {
-                const int jj = j + dj;
-                if (jj < 0 || jj > ny) continue;
+                for (int dn = -1; dn <= 1; ++dn) {
+                    const int pl = dn < 0 ? pm : (dn == 0 ? pc : pp);
 #pragma unroll
-                for (int di = -1; di <= 1; ++di) {
-                    const int ii = i + di;
-                    if (ii < 0 || ii > nx) continue;
-                    const int d = (dn + 1) * 9 + (dj + 1) * 3 + (di + 1);
-                    const long long nb = (long long)nn * P + (long long)jj * rowp + ii;
-                    TC a;
-                    if (TRANS)
-                        a = (TC)st[(long long)(26 - d) * DS + pl + (long long)jj * rowp + ii];
-                    else
-                        a = (TC)st[(long long)d * DS + pl + r];
-                    acc += a * (TC)x[nb];
+                    for (int q = 0; q < 9; ++q) {
+                        const int d = (dn + 1) * 9 + q;
+                        c[d] = (pl >= 0 && ((valid >> q) & 1u))
+                                   ? ldcoef<TC, S>(st + (long long)(26 - d) * DS + (long long)pl * P + r + off[q])
+                                   : (TC)0;
+                    }
                 }
             }
         }
+        TC acc = 0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) acc += c[q] * xm[q];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) acc += c[9 + q] * xc[q];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) acc += c[18 + q] * xp[q];
+        const long long idx = (long long)n * P + r;
         TC v = acc;
         if (b) v = (TC)b[idx] - v;
         if (invd) v *= (TC)invd[idx];
         y[idx] = (T)(v * sc);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            xm[q] = xc[q];
+            xc[q] = xp[q];
+        }
     }
 }
 
-// BF16 storage variant (FP32 arithmetic).
-template <bool TRANS>
-__global__ __launch_bounds__(256) void k_stencil_apply_bf16(
-    int nx, int ny, int nt, int nplanes, const uint16_t* __restrict__ st,
-    const int* __restrict__ pmap, const float* __restrict__ x, float* __restrict__ y,
-    const float* __restrict__ b, const float* __restrict__ invd, const double* __restrict__ scale,
-    const int* __restrict__ skip) {
-    if (skip && *skip) return;
-    const long long rowp = nx + 1;
-    const long long P = rowp * (ny + 1);
-    const long long N = P * (nt + 1);
-    const long long DS = P * nplanes;
-    const float sc = scale ? (float)(*scale) : 1.0f;
-    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < N;
-         idx += (long long)gridDim.x * blockDim.x) {
-        const int n = (int)(idx / P);
-        const long long r = idx - n * P;
-        const int j = (int)(r / rowp), i = (int)(r - (long long)j * rowp);
-        float acc = 0.0f;
-#pragma unroll
-        for (int dn = -1; dn <= 1; ++dn) {
-            const int nn = n + dn;
-            if (nn < 0 || nn > nt) continue;
-            const long long pl = TRANS ? (long long)pmap[nn] * P : (long long)pmap[n] * P;
-#pragma unroll
-            for (int dj = -1; dj <= 1; ++dj) {
-                const int jj = j + dj;
-                if (jj < 0 || jj > ny) continue;
-#pragma unroll
-                for (int di = -1; di <= 1; ++di) {
-                    const int ii = i + di;
-                    if (ii < 0 || ii > nx) continue;
-                    const int d = (dn + 1) * 9 + (dj + 1) * 3 + (di + 1);
-                    const long long nb = (long long)nn * P + (long long)jj * rowp + ii;
-                    float a;
-                    if (TRANS)
-                        a = bf16_to_f32(st[(long long)(26 - d) * DS + pl + (long long)jj * rowp + ii]);
-                    else
-                        a = bf16_to_f32(st[(long long)d * DS + pl + r]);
-                    acc += a * x[nb];
-                }
-            }
-        }
-        float v = acc;
-        if (b) v = b[idx] - v;
-        if (invd) v *= invd[idx];
-        y[idx] = v * sc;
-    }
+template <typename T, typename S, typename TC>
+static void stencil_dispatch(hipStream_t s, const Level& L, const S* st, int trans, const void* x,
+                             void* y, const void* b, const void* invd, const double* scale,
+                             const int* skip) {
+    const int P = (L.nx + 1) * (L.ny + 1);
+    const int gx = (P + 255) / 256;
+    int nchunk = 32;
+    while (nchunk > 2 && (long long)gx * ((L.nt + 1 + nchunk - 1) / nchunk) < 2048) nchunk /= 2;
+    const int gy = (L.nt + 1 + nchunk - 1) / nchunk;
+    if (trans)
+        hipLaunchKernelGGL((k_stencil_march<T, S, TC, true>), dim3(gx, gy), dim3(256), 0, s, L.nx,
+                           L.ny, L.nt, L.nplanes, st, L.plane_map, (const T*)x, (T*)y, (const T*)b,
+                           (const T*)invd, scale, skip, nchunk);
+    else
+        hipLaunchKernelGGL((k_stencil_march<T, S, TC, false>), dim3(gx, gy), dim3(256), 0, s, L.nx,
+                           L.ny, L.nt, L.nplanes, st, L.plane_map, (const T*)x, (T*)y, (const T*)b,
+                           (const T*)invd, scale, skip, nchunk);
 }
 
 void launch_stencil_apply(hipStream_t s, const Level& L, int prec, int trans, const void* x,
                           void* y, const void* b, const void* invd, const double* scale,
                           const int* skip) {
-    const unsigned nb = grid_for(L.nn);
-    if (prec == 0) {
-        auto* xx = (const double*)x;
-        auto* yy = (double*)y;
-        auto* bb = (const double*)b;
-        auto* dd = (const double*)invd;
-        if (trans)
-            hipLaunchKernelGGL((k_stencil_apply<double, double, double, true>), dim3(nb), dim3(256),
-                               0, s, L.nx, L.ny, L.nt, L.nplanes, L.st64, L.plane_map, xx, yy, bb,
-                               dd, scale, skip);
-        else
-            hipLaunchKernelGGL((k_stencil_apply<double, double, double, false>), dim3(nb),
-                               dim3(256), 0, s, L.nx, L.ny, L.nt, L.nplanes, L.st64, L.plane_map,
-                               xx, yy, bb, dd, scale, skip);
-    } else {
-        auto* xx = (const float*)x;
-        auto* yy = (float*)y;
-        auto* bb = (const float*)b;
-        auto* dd = (const float*)invd;
-        if (L.sprec == 2) {
-            if (trans)
-                hipLaunchKernelGGL(k_stencil_apply_bf16<true>, dim3(nb), dim3(256), 0, s, L.nx,
-                                   L.ny, L.nt, L.nplanes, L.st16, L.plane_map, xx, yy, bb, dd,
-                                   scale, skip);
-            else
-                hipLaunchKernelGGL(k_stencil_apply_bf16<false>, dim3(nb), dim3(256), 0, s, L.nx,
-                                   L.ny, L.nt, L.nplanes, L.st16, L.plane_map, xx, yy, bb, dd,
-                                   scale, skip);
-        } else {
-            if (trans)
-                hipLaunchKernelGGL((k_stencil_apply<float, float, float, true>), dim3(nb),
-                                   dim3(256), 0, s, L.nx, L.ny, L.nt, L.nplanes, L.st32,
-                                   L.plane_map, xx, yy, bb, dd, scale, skip);
-            else
-                hipLaunchKernelGGL((k_stencil_apply<float, float, float, false>), dim3(nb),
-                                   dim3(256), 0, s, L.nx, L.ny, L.nt, L.nplanes, L.st32,
-                                   L.plane_map, xx, yy, bb, dd, scale, skip);
-        }
-    }
+    if (prec == 0)
+        stencil_dispatch<double, double, double>(s, L, L.st64, trans, x, y, b, invd, scale, skip);
+    else if (L.sprec == 2)
+        stencil_dispatch<float, uint16_t, float>(s, L, L.st16, trans, x, y, b, invd, scale, skip);
+    else
+        stencil_dispatch<float, float, float>(s, L, L.st32, trans, x, y, b, invd, scale, skip);
 }
 
 // ---------------------------------------------------------------------------

@@ -40,6 +40,8 @@ struct st_handle {
     int nlev = 0;
     Level lev[ST_MAX_LEVELS];
     long long n0 = 0;          // fine nodes
+    long long ld0 = 0;         // FGMRES basis stride (n0 rounded up to 64)
+    double* x64 = nullptr;     // FGMRES iterate (internal, aligned)
     long long ne = 0;          // coefficient elements (design layout)
     long long nde = 0;         // design entries
     // fine level data
@@ -177,8 +179,10 @@ size_t carve(st_handle* h, char* base) {
     h->src = c.take<double>(h->n0);
     h->adj_rhs = c.take<double>(h->n0);
     h->gtmp = o.filter_r > 0 ? c.take<double>(h->nde) : nullptr;
-    h->V = c.take<double>((size_t)(m + 1) * h->n0);
-    h->Z = mixed ? (void*)c.take<float>((size_t)m * h->n0) : (void*)c.take<double>((size_t)m * h->n0);
+    h->ld0 = (h->n0 + 63) / 64 * 64;
+    h->x64 = c.take<double>(h->n0);
+    h->V = c.take<double>((size_t)(m + 1) * h->ld0);
+    h->Z = mixed ? (void*)c.take<float>((size_t)m * h->ld0) : (void*)c.take<double>((size_t)m * h->ld0);
     h->ks_outer = c.take<KState>(1);
     h->partials = c.take<double>((size_t)RED_BLOCKS * KMAX + 2 * KMAX);
     h->dscal = c.take<double>(64);
@@ -204,12 +208,12 @@ size_t carve(st_handle* h, char* base) {
         L.x = (l > 0) ? (void*)c.take<char>(L.nn * vb) : nullptr;
         L.b = c.take<char>(L.nn * vb);
         L.r = coarsest ? nullptr : (void*)c.take<char>(L.nn * vb);
-        L.V = coarsest ? nullptr : (void*)c.take<char>((size_t)(si + 1) * L.nn * vb);
+        L.V = coarsest ? nullptr : (void*)c.take<char>((size_t)(si + 1) * L.ld * vb);
         L.ks = coarsest ? nullptr : c.take<KState>(1);
     }
     const Level& Lc = h->lev[h->nlev - 1];
     h->coarseV = c.take<double>((size_t)(o.coarse_restart + 1) * Lc.nn);
-    h->coarseWork = c.take<double>((size_t)2 * Lc.nn);
+    h->coarseWork = c.take<double>((size_t)3 * Lc.nn);
     if (o.filter_r > 0) {
         h->fnt = h->rho_tv ? h->grid.nt : 1;
         h->fnn = (long long)(h->grid.nx + 1) * (h->grid.ny + 1) * (h->fnt + 1);
@@ -253,6 +257,7 @@ void make_levels(st_handle* h) {
         L.dt = dims[l].dt;
         L.how = dims[l].how;
         L.nn = (long long)(L.nx + 1) * (L.ny + 1) * (L.nt + 1);
+        L.ld = (L.nn + 63) / 64 * 64;
         L.nplanes = L.nt + 1;
         L.vprec = mixed ? 1 : 0;
         L.sprec = 0;
@@ -356,9 +361,10 @@ void smooth(st_handle* h, int l, int prec, int trans, const void* b, void* x, in
     Level& L = h->lev[l];
     hipStream_t s = h->stream;
     const long long n = L.nn;
+    const long long ld = L.ld;
     const size_t vb = vbytes(prec);
     char* V = (char*)Vbuf;
-    auto Vj = [&](int j) { return (void*)(V + (size_t)j * n * vb); };
+    auto Vj = [&](int j) { return (void*)(V + (size_t)j * ld * vb); };
     const void* invd = level_invd(h, l, prec);
     launch_init_state(s, ks, its, rtol, 1, nullptr);
     const int kd = l == 0 ? KC_DOT : KC_DOT_C, ka = l == 0 ? KC_AXPY : KC_AXPY_C;
@@ -368,21 +374,21 @@ void smooth(st_handle* h, int l, int prec, int trans, const void* b, void* x, in
     } else {
         level_apply(h, l, prec, trans, x, Vj(0), b, invd, nullptr, nullptr);
         Timed t(h, kd, n * (int64_t)vb);
-        launch_mdot(s, n, prec, prec, Vj(0), Vj(0), n, 1, h->partials, ks, FIN_INIT_SELF, 0, 1);
+        launch_mdot(s, n, prec, prec, Vj(0), Vj(0), ld, 1, h->partials, ks, FIN_INIT_SELF, 0, 1);
     }
     for (int j = 0; j < its; ++j) {
         level_apply(h, l, prec, trans, Vj(j), Vj(j + 1), nullptr, invd, &ks->scale[j], &ks->done);
         {
             Timed t(h, kd, n * (int64_t)vb * (j + 2));
-            launch_mdot(s, n, prec, prec, Vj(j + 1), V, n, j + 1, h->partials, ks, FIN_PROJ1, j, SMAX);
+            launch_mdot(s, n, prec, prec, Vj(j + 1), V, ld, j + 1, h->partials, ks, FIN_PROJ1, j, SMAX);
         }
         {
             Timed t(h, ka, n * (int64_t)vb * (j + 3));
-            launch_maxpy(s, n, prec, prec, Vj(j + 1), V, n, j + 1, h->partials, ks, FIN_GIVENS, j, SMAX);
+            launch_maxpy(s, n, prec, prec, Vj(j + 1), V, ld, j + 1, h->partials, ks, FIN_GIVENS, j, SMAX);
         }
     }
     Timed t(h, KC_UPDATE, n * (int64_t)vb * (its + 2));
-    launch_update(s, n, prec, prec, x, V, n, ks, zero_x0, SMAX);
+    launch_update(s, n, prec, prec, x, V, ld, ks, zero_x0, SMAX);
 }
 
 // Classical V-cycle (§3.2): pre-smoothing from zero, residual, restriction,
@@ -598,8 +604,9 @@ st_status fgmres(st_handle* h, const double* f, const double* fnorm_dev, double*
     const int zp = h->lev[0].vprec;
     const size_t zb = vbytes(zp);
     KState* ks = h->ks_outer;
-    auto Vj = [&](int j) { return h->V + (size_t)j * n; };
-    auto Zj = [&](int j) { return (void*)((char*)h->Z + (size_t)j * n * zb); };
+    const long long ld = h->ld0;
+    auto Vj = [&](int j) { return h->V + (size_t)j * ld; };
+    auto Zj = [&](int j) { return (void*)((char*)h->Z + (size_t)j * ld * zb); };
     HIPCHK(hipMemcpyAsync(h->hbuf, fnorm_dev, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const double fnorm = std::sqrt(h->hbuf[0]);
@@ -619,7 +626,7 @@ st_status fgmres(st_handle* h, const double* f, const double* fnorm_dev, double*
             Timed t(h, KC_FINE64, n * 24);
             launch_fine_apply(s, h->fg, cf, 0, 0, 1, trans, x, Vj(0), f, nullptr, nullptr, nullptr, 1, 1);
         }
-        launch_mdot(s, n, 0, 0, Vj(0), Vj(0), n, 1, h->partials, ks, FIN_INIT_REF, 0, 1);
+        launch_mdot(s, n, 0, 0, Vj(0), Vj(0), ld, 1, h->partials, ks, FIN_INIT_REF, 0, 1);
         HIPCHK(hipMemcpyAsync(h->hbuf, &ks->est, 4 * sizeof(double) + 4 * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         {
@@ -645,15 +652,15 @@ st_status fgmres(st_handle* h, const double* f, const double* fnorm_dev, double*
             }
             {
                 Timed t(h, KC_OUTER, n * 8 * (j + 2));
-                launch_mdot(s, n, 0, 0, Vj(j + 1), h->V, n, j + 1, h->partials, ks, FIN_PROJ1, j, KMAX);
+                launch_mdot(s, n, 0, 0, Vj(j + 1), h->V, ld, j + 1, h->partials, ks, FIN_PROJ1, j, KMAX);
             }
             {
                 Timed t(h, KC_OUTER, n * 8 * (j + 3));
-                launch_maxpy(s, n, 0, 0, Vj(j + 1), h->V, n, j + 1, h->partials, ks, FIN_PROJ2, j, KMAX);
+                launch_maxpy(s, n, 0, 0, Vj(j + 1), h->V, ld, j + 1, h->partials, ks, FIN_PROJ2, j, KMAX);
             }
             {
                 Timed t(h, KC_OUTER, n * 8 * (j + 3));
-                launch_maxpy(s, n, 0, 0, Vj(j + 1), h->V, n, j + 1, h->partials, ks, FIN_GIVENS, j, KMAX);
+                launch_maxpy(s, n, 0, 0, Vj(j + 1), h->V, ld, j + 1, h->partials, ks, FIN_GIVENS, j, KMAX);
             }
             HIPCHK(hipMemcpyAsync(h->hbuf, &ks->est, 4 * sizeof(double) + 4 * sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
@@ -669,7 +676,7 @@ st_status fgmres(st_handle* h, const double* f, const double* fnorm_dev, double*
         (void)k;
         {
             Timed t(h, KC_UPDATE, n * (16 + zb * m));
-            launch_update(s, n, 0, zp, x, h->Z, n, ks, 0, KMAX);
+            launch_update(s, n, 0, zp, x, h->Z, ld, ks, 0, KMAX);
         }
         // true residual
         {
@@ -887,7 +894,9 @@ st_status st_solve(st_handle* h, double* T_dev, st_info* info) {
     if (!h->setup_done) return ST_ERR_STATE;
     if (info) memset(info, 0, sizeof(*info));
     const double t0 = now_s();
-    st_status rc = fgmres(h, h->f_m, h->dscal + 0, T_dev, 0, info);
+    HIPCHK(hipMemcpyAsync(h->x64, T_dev, sizeof(double) * h->n0, hipMemcpyDeviceToDevice, h->stream));
+    st_status rc = fgmres(h, h->f_m, h->dscal + 0, h->x64, 0, info);
+    HIPCHK(hipMemcpyAsync(T_dev, h->x64, sizeof(double) * h->n0, hipMemcpyDeviceToDevice, h->stream));
     if (hipStreamSynchronize(h->stream) != hipSuccess) return ST_ERR_HIP;
     const double t1 = now_s();
     if (info) {
@@ -906,7 +915,9 @@ st_status st_adjoint_solve(st_handle* h, const double* g_dev, double* lambda_dev
     const double t0 = now_s();
     launch_mask_vec(s, h->n0, h->lev[0].mask, g_dev, h->adj_rhs);
     launch_dot(s, h->n0, h->adj_rhs, h->adj_rhs, h->partials, h->dscal + 1);
-    st_status rc = fgmres(h, h->adj_rhs, h->dscal + 1, lambda_dev, 1, info);
+    HIPCHK(hipMemcpyAsync(h->x64, lambda_dev, sizeof(double) * h->n0, hipMemcpyDeviceToDevice, s));
+    st_status rc = fgmres(h, h->adj_rhs, h->dscal + 1, h->x64, 1, info);
+    HIPCHK(hipMemcpyAsync(lambda_dev, h->x64, sizeof(double) * h->n0, hipMemcpyDeviceToDevice, s));
     if (hipStreamSynchronize(s) != hipSuccess) return ST_ERR_HIP;
     if (info) {
         info->t_solve_s = now_s() - t0;

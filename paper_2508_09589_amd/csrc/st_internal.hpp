@@ -15,7 +15,7 @@ namespace st {
 // Small fixed limits.
 constexpr int KMAX = 32;          // largest Krylov basis (FGMRES / coarse restart)
 constexpr int SMAX = 16;          // largest smoother basis
-constexpr int RED_BLOCKS = 1024;  // most blocks of a grid-stride reduction kernel
+constexpr int RED_BLOCKS = 2048;  // most blocks of a grid-stride reduction kernel
 constexpr int VEC_THREADS = 256;
 
 // Device-resident state of one GMRES / FGMRES cycle.  Every small scalar step
@@ -75,6 +75,7 @@ struct FineGeom {
 struct Level {
     int nx, ny, nt;
     long long nn;           // nodes
+    long long ld;           // basis stride: nn rounded up to 64 elements
     double dx, dt;
     int how;                // 0 finest, 1 space-coarsened, 2 time-coarsened
     int nplanes;            // distinct stencil time levels
