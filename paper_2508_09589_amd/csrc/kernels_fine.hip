@@ -69,31 +69,12 @@ void launch_simp(hipStream_t s, long long ne, const double* rho, const st_materi
 
 // ---------------------------------------------------------------------------
 // Matrix-free apply.
-template <typename TC>
-__device__ __forceinline__ TC stiff6(const TC u[9], const TC kq[4]) {
-    // 6 * (2-D bilinear stiffness) at the centre node; quads SW, SE, NW, NE.
-    const TC ks = kq[0] + kq[1] + kq[2] + kq[3];
-    TC v = (TC)4 * u[4] * ks;
-    v -= u[3] * (kq[0] + kq[2]);
-    v -= u[5] * (kq[1] + kq[3]);
-    v -= u[1] * (kq[0] + kq[1]);
-    v -= u[7] * (kq[2] + kq[3]);
-    v -= (TC)2 * (kq[0] * u[0] + kq[1] * u[2] + kq[2] * u[6] + kq[3] * u[8]);
-    return v;
-}
-
-template <typename TC>
-__device__ __forceinline__ TC mass36(const TC u[9], const TC cq[4]) {
-    // (36 / dx^2) * (2-D bilinear mass) at the centre node.
-    const TC cs = cq[0] + cq[1] + cq[2] + cq[3];
-    TC v = (TC)4 * u[4] * cs;
-    v += (TC)2 * u[3] * (cq[0] + cq[2]);
-    v += (TC)2 * u[5] * (cq[1] + cq[3]);
-    v += (TC)2 * u[1] * (cq[0] + cq[1]);
-    v += (TC)2 * u[7] * (cq[2] + cq[3]);
-    v += cq[0] * u[0] + cq[1] * u[2] + cq[2] * u[6] + cq[3] * u[8];
-    return v;
-}
+// Register-blocked form: a thread owns RY consecutive rows (j) of one column
+// (i) and marches through a chunk of time levels; one level costs 3 (RY+2)
+// loads of x for RY outputs.  Block = 64 x 4 threads = 64 x 4 RY nodes.
+// RY = 4 for FP32 arithmetic, 2 for FP64 (register budget).
+template <typename TC> struct RowBlock { static constexpr int value = 4; };
+template <> struct RowBlock<double> { static constexpr int value = 2; };
 
 template <typename TIN, typename TOUT, typename TC, bool TRANS, bool TCONST>
 __global__ __launch_bounds__(256) void k_fine_apply(
@@ -101,60 +82,87 @@ __global__ __launch_bounds__(256) void k_fine_apply(
     TOUT* __restrict__ y, const TOUT* __restrict__ b, const TOUT* __restrict__ invd,
     const double* __restrict__ scale, const int* __restrict__ skip, int nchunk, int mask_in,
     int dir_rows) {
+    constexpr int RY = RowBlock<TC>::value;
     if (skip && *skip) return;
     const int nx = g.nx, ny = g.ny, nt = g.nt;
     const int i = blockIdx.x * 64 + threadIdx.x;
-    const int j = blockIdx.y * 4 + threadIdx.y;
-    if (i > nx || j > ny) return;
+    const int j0 = (blockIdx.y * 4 + threadIdx.y) * RY;
+    if (i > nx || j0 > ny) return;
     const int n0 = blockIdx.z * nchunk;
     if (n0 > nt) return;
     const int n1 = min(n0 + nchunk, nt + 1);
     const long long rowp = nx + 1;
     const long long P = rowp * (ny + 1);
-    const long long cidx = (long long)j * rowp + i;
-
-    // Neighbour validity and patch membership (time-invariant).
-    unsigned valid = 0, patch = 0;
-    long long off[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        const int di = q % 3 - 1, dj = q / 3 - 1;
-        const int ii = i + di, jj = j + dj;
-        off[q] = (long long)dj * rowp + di;
-        const bool v = ii >= 0 && ii <= nx && jj >= 0 && jj <= ny;
-        if (v) valid |= 1u << q;
-        if (v && on_patch(g.patches, nx, ny, ii, jj)) patch |= 1u << q;
-    }
-    const unsigned live_in = mask_in ? (valid & ~patch) : valid;
-    const bool centre_patch = (patch >> 4) & 1u;
-
-    // Quad existence: SW, SE, NW, NE.
-    const bool qv[4] = {i >= 1 && j >= 1, i < nx && j >= 1, i >= 1 && j < ny, i < nx && j < ny};
-    const long long qoff[4] = {(long long)(j - 1) * nx + (i - 1), (long long)(j - 1) * nx + i,
-                               (long long)j * nx + (i - 1), (long long)j * nx + i};
     const long long slab = (long long)nx * ny;
 
-    TC kq[4], cq[4];
-    auto load_coef = [&](int s) {
-        const long long base = TCONST ? 0 : (long long)s * slab;
+    // Loaded window: rows j0-1 .. j0+RY (RY+2), columns i-1 .. i+1.
+    unsigned valid = 0, patch = 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            kq[q] = qv[q] ? kc[base + qoff[q]] : (TC)0;
-            cq[q] = qv[q] ? (g.cuniform ? (TC)g.c0 : cc[base + qoff[q]]) : (TC)0;
+    for (int m = 0; m < RY + 2; ++m)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int ii = i + c - 1, jj = j0 + m - 1;
+            const bool v = ii >= 0 && ii <= nx && jj >= 0 && jj <= ny;
+            const int bit = m * 3 + c;
+            if (v) valid |= 1u << bit;
+            if (v && on_patch(g.patches, nx, ny, ii, jj)) patch |= 1u << bit;
         }
-    };
-    auto load_plane = [&](int n, TC u[9]) {
-        const TIN* xp = x + (long long)n * P + cidx;
+    const unsigned live_in = mask_in ? (valid & ~patch) : valid;
+    const long long base = (long long)(j0 - 1) * rowp + (i - 1);
+
+    auto load_plane = [&](int n, TC u[RY + 2][3]) {
+        const TIN* xp = x + (long long)n * P + base;
         const unsigned live = (mask_in && g.ic_dir && n == 0) ? 0u : live_in;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) u[q] = ((live >> q) & 1u) ? (TC)xp[off[q]] : (TC)0;
+        for (int m = 0; m < RY + 2; ++m)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                u[m][c] = ((live >> (m * 3 + c)) & 1u) ? (TC)xp[(long long)m * rowp + c] : (TC)0;
+    };
+    // Element coefficients of rows j0-1 .. j0+RY-1 (RY+1), columns i-1, i.
+    TC ke[RY + 1][2], ce[RY + 1][2];
+    auto load_coef = [&](int s) {
+        const long long sb = TCONST ? 0 : (long long)s * slab;
+#pragma unroll
+        for (int m = 0; m < RY + 1; ++m)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int ei = i + c - 1, ej = j0 + m - 1;
+                const bool v = ei >= 0 && ei < nx && ej >= 0 && ej < ny;
+                const long long e = sb + (long long)ej * nx + ei;
+                ke[m][c] = v ? kc[e] : (TC)0;
+                ce[m][c] = v ? (g.cuniform ? (TC)g.c0 : cc[e]) : (TC)0;
+            }
     };
     const TC kt = (TC)g.dt6;
     const TC mw = (TC)g.mw;
     const TC sc = scale ? (TC)(*scale) : (TC)1;
-    auto emit = [&](int n, TC v) {
-        const long long idx = (long long)n * P + cidx;
-        const bool dir = dir_rows && ((g.ic_dir && n == 0) || centre_patch);
+    // 6 * stiffness and 36/dx^2 * mass at row m of the window.
+    auto stiff = [&](const TC u[RY + 2][3], int m) -> TC {
+        const TC kSW = ke[m][0], kSE = ke[m][1], kNW = ke[m + 1][0], kNE = ke[m + 1][1];
+        TC v = (TC)4 * u[m + 1][1] * (kSW + kSE + kNW + kNE);
+        v -= u[m + 1][0] * (kSW + kNW);
+        v -= u[m + 1][2] * (kSE + kNE);
+        v -= u[m][1] * (kSW + kSE);
+        v -= u[m + 2][1] * (kNW + kNE);
+        v -= (TC)2 * (kSW * u[m][0] + kSE * u[m][2] + kNW * u[m + 2][0] + kNE * u[m + 2][2]);
+        return v;
+    };
+    auto mass = [&](const TC u[RY + 2][3], int m) -> TC {
+        const TC cSW = ce[m][0], cSE = ce[m][1], cNW = ce[m + 1][0], cNE = ce[m + 1][1];
+        TC v = (TC)4 * u[m + 1][1] * (cSW + cSE + cNW + cNE);
+        v += (TC)2 * u[m + 1][0] * (cSW + cNW);
+        v += (TC)2 * u[m + 1][2] * (cSE + cNE);
+        v += (TC)2 * u[m][1] * (cSW + cSE);
+        v += (TC)2 * u[m + 2][1] * (cNW + cNE);
+        v += cSW * u[m][0] + cSE * u[m][2] + cNW * u[m + 2][0] + cNE * u[m + 2][2];
+        return v;
+    };
+    auto emit = [&](int n, int m, TC v) {
+        const int j = j0 + m;
+        if (j > ny) return;
+        const long long idx = (long long)n * P + (long long)j * rowp + i;
+        const bool dir = dir_rows && ((g.ic_dir && n == 0) || ((patch >> ((m + 1) * 3 + 1)) & 1u));
         TC val = dir ? (TC)x[idx] : v;
         if (b) val = (TC)b[idx] - val;
         if (invd) val *= (TC)invd[idx];
@@ -163,47 +171,57 @@ __global__ __launch_bounds__(256) void k_fine_apply(
 
     const int sa = max(n0 - 1, 0);
     const int sb = min(n1 - 1, nt - 1);
-    TC ulo[9], uhi[9];
+    TC ulo[RY + 2][3], uhi[RY + 2][3];
     load_plane(sa, ulo);
-    TC Plo = 0, Rlo = 0;
-    if (TCONST) {
-        load_coef(0);
-        Plo = kt * stiff6(ulo, kq);
-        Rlo = mw * mass36(ulo, cq);
+    TC Plo[RY], Rlo[RY], acc[RY];
+    if (TCONST) load_coef(0);
+#pragma unroll
+    for (int m = 0; m < RY; ++m) {
+        acc[m] = 0;
+        Plo[m] = TCONST ? kt * stiff(ulo, m) : (TC)0;
+        Rlo[m] = TCONST ? mw * mass(ulo, m) : (TC)0;
     }
-    TC acc = 0;
     for (int s = sa; s <= sb; ++s) {
         load_plane(s + 1, uhi);
         if (!TCONST) load_coef(s);
-        const TC Pv = TCONST ? Plo : kt * stiff6(ulo, kq);
-        const TC Qv = kt * stiff6(uhi, kq);
-        const TC Sv = mw * mass36(uhi, cq);
-        TC bottom = (TC)2 * Pv + Qv;
-        TC top = Pv + (TC)2 * Qv;
-        if (TRANS) {
-            bottom -= Sv;
-            top += Sv;
-        } else {
-            const TC Rv = TCONST ? Rlo : mw * mass36(ulo, cq);
-            top += Sv - Rv;
-        }
-        if (s >= n0) emit(s, acc + bottom);
-        acc = top;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) ulo[q] = uhi[q];
-        if (TCONST) {
-            Plo = Qv;
-            Rlo = Sv;
+        for (int m = 0; m < RY; ++m) {
+            const TC Pv = TCONST ? Plo[m] : kt * stiff(ulo, m);
+            const TC Qv = kt * stiff(uhi, m);
+            const TC Sv = mw * mass(uhi, m);
+            TC bottom = (TC)2 * Pv + Qv;
+            TC top = Pv + (TC)2 * Qv;
+            if (TRANS) {
+                bottom -= Sv;
+                top += Sv;
+            } else {
+                const TC Rv = TCONST ? Rlo[m] : mw * mass(ulo, m);
+                top += Sv - Rv;
+            }
+            if (s >= n0) emit(s, m, acc[m] + bottom);
+            acc[m] = top;
+            if (TCONST) {
+                Plo[m] = Qv;
+                Rlo[m] = Sv;
+            }
         }
+#pragma unroll
+        for (int m = 0; m < RY + 2; ++m)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ulo[m][c] = uhi[m][c];
     }
-    if (sb + 1 == nt && nt >= n0 && nt < n1) emit(nt, acc);
+    if (sb + 1 == nt && nt >= n0 && nt < n1) {
+#pragma unroll
+        for (int m = 0; m < RY; ++m) emit(nt, m, acc[m]);
+    }
 }
 
 template <typename TIN, typename TOUT, typename TC>
 static void fine_dispatch(hipStream_t s, const FineGeom& g, const TC* kc, const TC* cc, int trans,
                           const void* x, void* y, const void* b, const void* invd,
                           const double* scale, const int* skip, int mask_in, int dir_rows) {
-    const int gx = (g.nx + 1 + 63) / 64, gy = (g.ny + 1 + 3) / 4;
+    constexpr int RY = RowBlock<TC>::value;
+    const int gx = (g.nx + 1 + 63) / 64, gy = (g.ny + 1 + 4 * RY - 1) / (4 * RY);
     long long cols = (long long)gx * gy;
     int nchunk = 32;
     while (nchunk > 4 && cols * ((g.nt + 1 + nchunk - 1) / nchunk) < 4096) nchunk /= 2;

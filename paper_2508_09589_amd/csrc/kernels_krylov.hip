@@ -420,7 +420,7 @@ __global__ __launch_bounds__(VEC_THREADS) void k_maxpy4(long long n, TW* __restr
         w[i] = wo;
         acc[0] += (double)wo * (double)wo;
     }
-    (void)mode;
+    if (mode == FIN_NONE) return;   // uniform: no reduction wanted
     block_finish<1>(acc, 1, partials, ks, FIN_GIVENS, j, nullptr);
 }
 
@@ -469,8 +469,8 @@ template <int MAXD>
 static void maxpy_dispatch(hipStream_t s, long long n, int pw, int pv, void* w, const void* V,
                            long long ldv, int nd, double* partials, KState* ks, int mode, int j) {
     const unsigned nb = red_grid(n);
-    const bool vec = mode == FIN_GIVENS && pw == pv && ldv % 4 == 0 && al4(w, pw ? 4 : 8) &&
-                     al4(V, pv ? 4 : 8);
+    const bool vec = (mode == FIN_GIVENS || mode == FIN_NONE) && pw == pv && ldv % 4 == 0 &&
+                     al4(w, pw ? 4 : 8) && al4(V, pv ? 4 : 8);
     if (vec) {
         const unsigned nb4 = red_grid4(n);
         if (pw == 0)
@@ -692,11 +692,14 @@ __global__ __launch_bounds__(CT) void k_coarse_gmres(
                 if (d <= jcol) {
                     const double* vd = V + (long long)d * n;
                     int i = q;
-                    for (; i + 96 < n; i += 128) {
-                        a0 += vd[i] * w[i];
-                        a1 += vd[i + 32] * w[i + 32];
-                        a2 += vd[i + 64] * w[i + 64];
-                        a3 += vd[i + 96] * w[i + 96];
+                    for (; i + 224 < n; i += 256) {
+                        double t[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) t[u] = vd[i + 32 * u];
+                        a0 += t[0] * w[i] + t[4] * w[i + 128];
+                        a1 += t[1] * w[i + 32] + t[5] * w[i + 160];
+                        a2 += t[2] * w[i + 64] + t[6] * w[i + 192];
+                        a3 += t[3] * w[i + 96] + t[7] * w[i + 224];
                     }
                     for (; i < n; i += 32) a0 += vd[i] * w[i];
                 }
@@ -708,8 +711,21 @@ __global__ __launch_bounds__(CT) void k_coarse_gmres(
             __syncthreads();
             loc = 0.0;
             for (int i = tid; i < n; i += CT) {
-                double v = w[i];
-                for (int d = 0; d <= jcol; ++d) v -= h[d] * V[(long long)d * n + i];
+                // eight independent loads per step keep the L2 latency hidden
+                double v0 = w[i], v1 = 0.0;
+                int d = 0;
+                for (; d + 7 <= jcol; d += 8) {
+                    double t[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) t[u] = V[(long long)(d + u) * n + i];
+#pragma unroll
+                    for (int u = 0; u < 8; u += 2) {
+                        v0 -= h[d + u] * t[u];
+                        v1 -= h[d + u + 1] * t[u + 1];
+                    }
+                }
+                for (; d <= jcol; ++d) v0 -= h[d] * V[(long long)d * n + i];
+                const double v = v0 + v1;
                 w[i] = v;
                 loc += v * v;
             }
@@ -770,9 +786,20 @@ __global__ __launch_bounds__(CT) void k_coarse_gmres(
         }
         __syncthreads();
         for (int i = tid; i < n; i += CT) {
-            double v = x[i];
-            for (int d = 0; d < k; ++d) v += y[d] * V[(long long)d * n + i];
-            x[i] = v;
+            double v0 = x[i], v1 = 0.0;
+            int d = 0;
+            for (; d + 7 < k; d += 8) {
+                double t[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) t[u] = V[(long long)(d + u) * n + i];
+#pragma unroll
+                for (int u = 0; u < 8; u += 2) {
+                    v0 += y[d + u] * t[u];
+                    v1 += y[d + u + 1] * t[u + 1];
+                }
+            }
+            for (; d < k; ++d) v0 += y[d] * V[(long long)d * n + i];
+            x[i] = v0 + v1;
         }
         __syncthreads();
         if (finished || its >= maxit) break;

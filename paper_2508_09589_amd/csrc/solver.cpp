@@ -655,8 +655,14 @@ st_status fgmres(st_handle* h, const double* f, const double* fnorm_dev, double*
                 launch_mdot(s, n, 0, 0, Vj(j + 1), h->V, ld, j + 1, h->partials, ks, FIN_PROJ1, j, KMAX);
             }
             {
+                // CGS2: subtract the first projections, project again, subtract
+                // the corrections and take the norm (three streaming passes).
                 Timed t(h, KC_OUTER, n * 8 * (j + 3));
-                launch_maxpy(s, n, 0, 0, Vj(j + 1), h->V, ld, j + 1, h->partials, ks, FIN_PROJ2, j, KMAX);
+                launch_maxpy(s, n, 0, 0, Vj(j + 1), h->V, ld, j + 1, h->partials, ks, FIN_NONE, j, KMAX);
+            }
+            {
+                Timed t(h, KC_OUTER, n * 8 * (j + 2));
+                launch_mdot(s, n, 0, 0, Vj(j + 1), h->V, ld, j + 1, h->partials, ks, FIN_PROJ2, j, KMAX);
             }
             {
                 Timed t(h, KC_OUTER, n * 8 * (j + 3));

@@ -49,7 +49,8 @@ enum FinMode {
     FIN_PROJ1 = 2,       // first CGS projections h_d
     FIN_PROJ2 = 3,       // re-orthogonalisation projections (CGS2)
     FIN_GIVENS = 4,      // norm of the new vector, Givens update, convergence test
-    FIN_SUM = 5          // plain sums to out[]
+    FIN_SUM = 5,         // plain sums to out[]
+    FIN_NONE = 6         // maxpy only: subtract, no reduction
 };
 
 // T = 0 patches translated to index ranges.
