@@ -15,17 +15,21 @@
 namespace st {
 
 // Blocks of the vectorised reductions: four elements per thread per step.
+// Streaming reductions use at most one block per CU: measured on MI355X, 256
+// blocks of 256 threads stream at 5.2-5.4 TB/s, more blocks only add tail.
+constexpr long long MAX_RED_GRID = 256;
+
 static inline unsigned red_grid4(long long n) {
     long long nb = (n + 8LL * VEC_THREADS - 1) / (8LL * VEC_THREADS);
     if (nb < 1) nb = 1;
-    if (nb > RED_BLOCKS) nb = RED_BLOCKS;
+    if (nb > MAX_RED_GRID) nb = MAX_RED_GRID;
     return (unsigned)nb;
 }
 
 static inline unsigned red_grid(long long n) {
     long long nb = (n + 4LL * VEC_THREADS - 1) / (4LL * VEC_THREADS);
     if (nb < 1) nb = 1;
-    if (nb > RED_BLOCKS) nb = RED_BLOCKS;
+    if (nb > MAX_RED_GRID) nb = MAX_RED_GRID;
     return (unsigned)nb;
 }
 
@@ -148,9 +152,13 @@ __device__ void kstate_finalize(KState* ks, int mode, int j, const double* sums,
     }
 }
 
-// Block reduction of MAXD accumulators into partials[blockIdx][.], then the
-// last block reduces the partials and finalises.  Returns nothing; must be
-// called by every thread of every block.
+// Block reduction of MAXD accumulators into partials[blockIdx][.].  Grids of
+// at most FUSE_MAX blocks then finalise in the last block to arrive (arrival
+// counter); larger grids leave the partials to k_reduce_finalize, launched
+// right after them on the stream: a device-scope fence per block costs more
+// than one extra launch once there are more than a handful of blocks.
+constexpr int FUSE_MAX = 16;
+
 template <int MAXD>
 __device__ void block_finish(double (&acc)[MAXD], int nd, double* __restrict__ partials,
                              KState* ks, int mode, int j, double* out) {
@@ -172,6 +180,7 @@ __device__ void block_finish(double (&acc)[MAXD], int nd, double* __restrict__ p
         for (int w = 0; w < VEC_THREADS / 64; ++w) v += red[w][threadIdx.x];
         partials[(long long)blockIdx.x * MAXD + threadIdx.x] = v;
     }
+    if (gridDim.x > FUSE_MAX) return;   // uniform over the grid
     __threadfence();
     __syncthreads();
     unsigned* counter = ks ? &ks->counter : (unsigned*)(partials + (long long)RED_BLOCKS * KMAX + KMAX);
@@ -198,6 +207,37 @@ __device__ void block_finish(double (&acc)[MAXD], int nd, double* __restrict__ p
         }
         *counter = 0u;
     }
+}
+
+// One block: sum the partials of a reduction grid (block order) and finalise.
+template <int MAXD>
+__global__ __launch_bounds__(VEC_THREADS) void k_reduce_finalize(const double* __restrict__ partials,
+                                                                 int nb, int nd, KState* ks,
+                                                                 int mode, int j, double* out) {
+    __shared__ double sums[MAXD];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (ks && ks->done && mode != FIN_INIT_SELF && mode != FIN_INIT_REF) return;
+    for (int d = wave; d < nd; d += VEC_THREADS / 64) {
+        double v = 0.0;
+        for (int b = lane; b < nb; b += 64) v += partials[(long long)b * MAXD + d];
+        v = wave_sum(v);
+        if (lane == 0) sums[d] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (ks)
+            kstate_finalize(ks, mode, j, sums, nd);
+        else
+            for (int d = 0; d < nd; ++d) out[d] = sums[d];
+    }
+}
+
+template <int MAXD>
+static void finish(hipStream_t s, unsigned nb, int nd, double* partials, KState* ks, int mode,
+                   int j, double* out) {
+    if ((int)nb <= FUSE_MAX) return;
+    hipLaunchKernelGGL(k_reduce_finalize<MAXD>, dim3(1), dim3(VEC_THREADS), 0, s, partials,
+                       (int)nb, nd, ks, mode, j, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -282,6 +322,7 @@ void launch_scale_norm(hipStream_t s, long long n, int prec, const void* b, cons
         else
             hipLaunchKernelGGL(k_scale_norm4<float>, dim3(nb4), dim3(VEC_THREADS), 0, s, n,
                                (const float*)b, (const float*)invd, (float*)w, partials, ks, mode);
+        finish<1>(s, nb4, 1, partials, ks, mode, 0, nullptr);
         return;
     }
     if (prec == 0)
@@ -290,6 +331,7 @@ void launch_scale_norm(hipStream_t s, long long n, int prec, const void* b, cons
     else
         hipLaunchKernelGGL(k_scale_norm<float>, dim3(nb), dim3(VEC_THREADS), 0, s, n,
                            (const float*)b, (const float*)invd, (float*)w, partials, ks, mode);
+    finish<1>(s, nb, 1, partials, ks, mode, 0, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -438,6 +480,7 @@ static void mdot_dispatch(hipStream_t s, long long n, int pw, int pv, const void
         else
             hipLaunchKernelGGL((k_mdot4<float, float, MAXD>), dim3(nb4), dim3(VEC_THREADS), 0, s,
                                n, (const float*)w, (const float*)V, ldv, nd, partials, ks, mode, j);
+        finish<MAXD>(s, nb4, nd, partials, ks, mode, j, nullptr);
         return;
     }
     if (pw == 0 && pv == 0)
@@ -452,6 +495,7 @@ static void mdot_dispatch(hipStream_t s, long long n, int pw, int pv, const void
     else
         hipLaunchKernelGGL((k_mdot<float, double, MAXD>), dim3(nb), dim3(VEC_THREADS), 0, s, n,
                            (const float*)w, (const double*)V, ldv, nd, partials, ks, mode, j);
+    finish<MAXD>(s, nb, nd, partials, ks, mode, j, nullptr);
 }
 
 void launch_mdot(hipStream_t s, long long n, int prec_w, int prec_v, const void* w,
@@ -479,6 +523,7 @@ static void maxpy_dispatch(hipStream_t s, long long n, int pw, int pv, void* w, 
         else
             hipLaunchKernelGGL((k_maxpy4<float, float, MAXD>), dim3(nb4), dim3(VEC_THREADS), 0, s,
                                n, (float*)w, (const float*)V, ldv, nd, partials, ks, mode, j);
+        if (mode != FIN_NONE) finish<1>(s, nb4, 1, partials, ks, FIN_GIVENS, j, nullptr);
         return;
     }
     if (pw == 0 && pv == 0)
@@ -487,6 +532,7 @@ static void maxpy_dispatch(hipStream_t s, long long n, int pw, int pv, void* w, 
     else
         hipLaunchKernelGGL((k_maxpy<float, float, MAXD>), dim3(nb), dim3(VEC_THREADS), 0, s, n,
                            (float*)w, (const float*)V, ldv, nd, partials, ks, mode, j);
+    if (mode != FIN_NONE) finish<MAXD>(s, nb, mode == FIN_PROJ2 ? nd : 1, partials, ks, mode, j, nullptr);
 }
 
 void launch_maxpy(hipStream_t s, long long n, int prec_w, int prec_v, void* w, const void* V,
@@ -584,7 +630,9 @@ __global__ __launch_bounds__(VEC_THREADS) void k_dot(long long n, const double* 
 
 void launch_dot(hipStream_t s, long long n, const double* a, const double* b, double* partials,
                 double* out) {
-    hipLaunchKernelGGL(k_dot, dim3(red_grid(n)), dim3(VEC_THREADS), 0, s, n, a, b, partials, out);
+    const unsigned nb = red_grid(n);
+    hipLaunchKernelGGL(k_dot, dim3(nb), dim3(VEC_THREADS), 0, s, n, a, b, partials, out);
+    finish<1>(s, nb, 1, partials, nullptr, FIN_SUM, 0, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -927,10 +975,12 @@ void launch_cg_step(hipStream_t s, int step, long long n, double* x, double* r, 
     switch (step) {
     case 0:   // p . q
         hipLaunchKernelGGL(k_cg_pq, dim3(nb), dim3(VEC_THREADS), 0, s, n, p, q, partials, scal);
+        finish<1>(s, nb, 1, partials, nullptr, FIN_SUM, 0, scal + 5);
         break;
     case 1:   // x, r, z updates and r.z, r.r
         hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(VEC_THREADS), 0, s, n, x, r, z, p, q, invd,
                            partials, scal);
+        finish<2>(s, nb, 2, partials, nullptr, FIN_SUM, 0, scal + 6);
         break;
     case 2:   // p = z + beta p
         hipLaunchKernelGGL(k_cg_p, dim3((unsigned)nb2), dim3(VEC_THREADS), 0, s, n, z, p, scal, 0);
@@ -944,6 +994,7 @@ void launch_cg_step(hipStream_t s, int step, long long n, double* x, double* r, 
     case 5:   // init from b (= q argument): r = b, z = p = invd .* b
         hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(VEC_THREADS), 0, s, n, q, r, z, p, invd,
                            partials, scal);
+        finish<2>(s, nb, 2, partials, nullptr, FIN_SUM, 0, scal + 6);
         break;
     }
 }
