@@ -15,9 +15,11 @@
 namespace st {
 
 // Blocks of the vectorised reductions: four elements per thread per step.
-// Streaming reductions use at most one block per CU: measured on MI355X, 256
-// blocks of 256 threads stream at 5.2-5.4 TB/s, more blocks only add tail.
-constexpr long long MAX_RED_GRID = 256;
+// Streaming reductions use at most four blocks of 256 threads per CU: measured
+// on MI355X this is where the multi-dot and maxpy kernels stream fastest
+// (one block per CU leaves a single wave per SIMD to hide latency, more
+// blocks only lengthen the tail).
+constexpr long long MAX_RED_GRID = 1024;
 
 static inline unsigned red_grid4(long long n) {
     long long nb = (n + 8LL * VEC_THREADS - 1) / (8LL * VEC_THREADS);
@@ -402,15 +404,27 @@ __global__ __launch_bounds__(VEC_THREADS) void k_mdot4(long long n, const TW* __
     const long long n4 = n >> 2;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n4; q += stride) {
-        double wv[4];
-        ld4(w + 4 * q, wv);
+        if (sizeof(TW) == 4 && sizeof(TV) == 4) {
+            // FP32 storage: the four products are summed in FP32, the running
+            // sum is FP64.
+            const float4 x = *reinterpret_cast<const float4*>(w + 4 * q);
 #pragma unroll
-        for (int d = 0; d < MAXD; ++d)
-            if (d < nd) {
-                double vv[4];
-                ld4(V + (long long)d * ldv + 4 * q, vv);
-                acc[d] += vv[0] * wv[0] + vv[1] * wv[1] + vv[2] * wv[2] + vv[3] * wv[3];
-            }
+            for (int d = 0; d < MAXD; ++d)
+                if (d < nd) {
+                    const float4 v = *reinterpret_cast<const float4*>(V + (long long)d * ldv + 4 * q);
+                    acc[d] += (double)(v.x * x.x + v.y * x.y + v.z * x.z + v.w * x.w);
+                }
+        } else {
+            double wv[4];
+            ld4(w + 4 * q, wv);
+#pragma unroll
+            for (int d = 0; d < MAXD; ++d)
+                if (d < nd) {
+                    double vv[4];
+                    ld4(V + (long long)d * ldv + 4 * q, vv);
+                    acc[d] += vv[0] * wv[0] + vv[1] * wv[1] + vv[2] * wv[2] + vv[3] * wv[3];
+                }
+        }
     }
     for (long long i = 4 * n4 + blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += stride) {
         const double wv = (double)w[i];
@@ -437,21 +451,38 @@ __global__ __launch_bounds__(VEC_THREADS) void k_maxpy4(long long n, TW* __restr
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n4; q += stride) {
         double wv[4];
-        ld4(w + 4 * q, wv);
+        if (sizeof(TW) == 4) {
+            // FP32 storage: FP32 arithmetic, the basis read as float4
+            float4 x = *reinterpret_cast<const float4*>(w + 4 * q);
 #pragma unroll
-        for (int d = 0; d < MAXD; ++d)
-            if (d < nd) {
-                double vv[4];
-                ld4(V + (long long)d * ldv + 4 * q, vv);
-                const double cd = c[d];
-                wv[0] -= cd * vv[0]; wv[1] -= cd * vv[1]; wv[2] -= cd * vv[2]; wv[3] -= cd * vv[3];
-            }
+            for (int d = 0; d < MAXD; ++d)
+                if (d < nd) {
+                    const float4 v = *reinterpret_cast<const float4*>(V + (long long)d * ldv + 4 * q);
+                    const float cd = (float)c[d];
+                    x.x -= cd * v.x; x.y -= cd * v.y; x.z -= cd * v.z; x.w -= cd * v.w;
+                }
+            wv[0] = x.x; wv[1] = x.y; wv[2] = x.z; wv[3] = x.w;
+        } else {
+            ld4(w + 4 * q, wv);
+#pragma unroll
+            for (int d = 0; d < MAXD; ++d)
+                if (d < nd) {
+                    double vv[4];
+                    ld4(V + (long long)d * ldv + 4 * q, vv);
+                    const double cd = c[d];
+                    wv[0] -= cd * vv[0]; wv[1] -= cd * vv[1]; wv[2] -= cd * vv[2]; wv[3] -= cd * vv[3];
+                }
+        }
         // round to the storage type before the norm, as the scalar path does
         typename V4<TW>::type o;
         o.x = (TW)wv[0]; o.y = (TW)wv[1]; o.z = (TW)wv[2]; o.w = (TW)wv[3];
         *reinterpret_cast<typename V4<TW>::type*>(w + 4 * q) = o;
-        acc[0] += (double)o.x * (double)o.x + (double)o.y * (double)o.y +
-                  (double)o.z * (double)o.z + (double)o.w * (double)o.w;
+        if (sizeof(TW) == 4)
+            acc[0] += (double)((float)o.x * (float)o.x + (float)o.y * (float)o.y +
+                               (float)o.z * (float)o.z + (float)o.w * (float)o.w);
+        else
+            acc[0] += (double)o.x * (double)o.x + (double)o.y * (double)o.y +
+                      (double)o.z * (double)o.z + (double)o.w * (double)o.w;
     }
     for (long long i = 4 * n4 + blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += stride) {
         double wv = (double)w[i];
