@@ -181,6 +181,10 @@ st_status st_load_vector(st_handle* h, double* f_dev);
  * layout.  ST_ERR_STATE when the problem has no filter. */
 st_status st_filter(st_handle* h, const double* in_dev, double* out_dev);
 
+/* Move a built problem to another HIP stream (e.g. a serving slot's); the
+ * old stream is synchronised first. */
+st_status st_set_stream(st_handle* h, void* hip_stream);
+
 /* Replace the option flags (ST_FLAG_TIME_KERNELS and its class mask) of a
  * built problem; the other options are fixed at setup. */
 st_status st_set_flags(st_handle* h, int32_t flags);

@@ -72,6 +72,7 @@ _SIGS = {
     "st_filter": (C.c_int, [_P, _P, _P]),
     "st_hierarchy": (C.c_int, [_P, C.POINTER(st_info)]),
     "st_set_flags": (C.c_int, [_P, C.c_int32]),
+    "st_set_stream": (C.c_int, [_P, _P]),
     "st_destroy": (None, [_P]),
     "st_debug_apply": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P]),
     "st_debug_stencil": (C.c_int, [_P, C.c_int32, _P]),

@@ -707,16 +707,43 @@ __global__ __launch_bounds__(CT) void k_coarse_gmres(
     __shared__ int flag;
     const int tid = threadIdx.x;
 
-    // (A v)[idx] for a vector in LDS/global, forward or transposed stencil.
-    auto apply = [&](const double* in, int idx) -> double {
-        const int nn0 = idx / P;
-        const int r = idx - nn0 * P;
-        const int j = r / row, i = r - j * row;
+    // Plane map in LDS; each thread's node coordinates computed once (a thread
+    // owns nodes tid, tid + CT, ...; at most CMAXN of them are cached).
+    __shared__ int pm[1025];
+    for (int q = tid; q <= nt && q < 1025; q += CT) pm[q] = pmap[q];
+    constexpr int CMAXN = 4;
+    int cn[CMAXN], cj[CMAXN], ci[CMAXN];
+#pragma unroll
+    for (int u = 0; u < CMAXN; ++u) {
+        const int idx = tid + u * CT;
+        const int nn0 = idx / P, r = idx - nn0 * P;
+        cn[u] = nn0;
+        cj[u] = r / row;
+        ci[u] = r - cj[u] * row;
+    }
+    __syncthreads();
+    const bool pm_lds = nt < 1025;
+    // (A v)[idx] for a vector in LDS/global, forward or transposed stencil;
+    // u is the index of idx among this thread's nodes.
+    auto apply = [&](const double* in, int idx, int u) -> double {
+        int nn0, j, i;
+        if (u < CMAXN) {
+            nn0 = cn[u];
+            j = cj[u];
+            i = ci[u];
+        } else {
+            nn0 = idx / P;
+            const int r = idx - nn0 * P;
+            j = r / row;
+            i = r - j * row;
+        }
+        const int r = j * row + i;
         double acc = 0.0;
 #pragma unroll
         for (int dn = -1; dn <= 1; ++dn) {
             const int nn = nn0 + dn;
             if (nn < 0 || nn > nt) continue;
+            const int pl = pm_lds ? (trans ? pm[nn] : pm[nn0]) : (trans ? pmap[nn] : pmap[nn0]);
 #pragma unroll
             for (int dj = -1; dj <= 1; ++dj) {
                 const int jj = j + dj;
@@ -727,8 +754,8 @@ __global__ __launch_bounds__(CT) void k_coarse_gmres(
                     if (ii < 0 || ii > nx) continue;
                     const int d = (dn + 1) * 9 + (dj + 1) * 3 + (di + 1);
                     const int nb = nn * P + jj * row + ii;
-                    const double a = trans ? st[(long long)(26 - d) * DS + (long long)pmap[nn] * P + jj * row + ii]
-                                           : st[(long long)d * DS + (long long)pmap[nn0] * P + r];
+                    const double a = trans ? st[(long long)(26 - d) * DS + (long long)pl * P + jj * row + ii]
+                                           : st[(long long)d * DS + (long long)pl * P + r];
                     acc += a * in[nb];
                 }
             }
@@ -739,8 +766,8 @@ __global__ __launch_bounds__(CT) void k_coarse_gmres(
     for (int i = tid; i < n; i += CT) x[i] = zero_x0 ? 0.0 : (double)xio[i];
     __syncthreads();
     double loc = 0.0;
-    for (int i = tid; i < n; i += CT) {
-        const double v = invd[i] * ((double)bio[i] - (zero_x0 ? 0.0 : apply(x, i)));
+    for (int i = tid, u = 0; i < n; i += CT, ++u) {
+        const double v = invd[i] * ((double)bio[i] - (zero_x0 ? 0.0 : apply(x, i, u)));
         w[i] = v;
         loc += v * v;
     }
@@ -762,7 +789,7 @@ __global__ __launch_bounds__(CT) void k_coarse_gmres(
         bool stop = false;
         for (int jcol = 0; jcol < restart && !stop; ++jcol) {
             __syncthreads();
-            for (int i = tid; i < n; i += CT) w[i] = invd[i] * apply(vj, i);
+            for (int i = tid, u = 0; i < n; i += CT, ++u) w[i] = invd[i] * apply(vj, i, u);
             __syncthreads();
             // h_d = <v_d, w>, d <= jcol: 32 lanes per d, 4 independent sums
             {
@@ -883,8 +910,8 @@ __global__ __launch_bounds__(CT) void k_coarse_gmres(
         __syncthreads();
         if (finished || its >= maxit) break;
         loc = 0.0;
-        for (int i = tid; i < n; i += CT) {
-            const double v = invd[i] * ((double)bio[i] - apply(x, i));
+        for (int i = tid, u = 0; i < n; i += CT, ++u) {
+            const double v = invd[i] * ((double)bio[i] - apply(x, i, u));
             w[i] = v;
             loc += v * v;
         }
@@ -901,7 +928,7 @@ void launch_coarse_solve(hipStream_t s, const Level& L, int prec_io, int trans, 
                          int zero_x0) {
     const long long n = L.nn;
     const size_t lds = (size_t)2 * n * sizeof(double);
-    const bool use_lds = lds <= 52 * 1024;   // stays within the default 64 KB per block
+    const bool use_lds = lds <= 48 * 1024;   // with ~14 KB static LDS: within 64 KB per block
     const size_t dyn = use_lds ? lds : 0;
     if (prec_io == 0) {
         if (use_lds)

@@ -976,6 +976,13 @@ st_status st_filter(st_handle* h, const double* in_dev, double* out_dev) {
     return ST_OK;
 }
 
+st_status st_set_stream(st_handle* h, void* hip_stream) {
+    if (!h) return ST_ERR_ARG;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->stream = (hipStream_t)hip_stream;
+    return ST_OK;
+}
+
 st_status st_set_flags(st_handle* h, int32_t flags) {
     if (!h) return ST_ERR_ARG;
     const int keep = h->opts.flags & ST_FLAG_NO_PLANE_DEDUP;

@@ -132,6 +132,10 @@ class Problem:
         rho = _dev_f64(rho, self.device).reshape(self.design_shape)
         L.check("st_update_density", self.lib.st_update_density(self.h, _ptr(rho)))
 
+    def set_stream(self, stream):
+        L.check("st_set_stream", self.lib.st_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
+        self.stream = stream
+
     def set_flags(self, flags):
         L.check("st_set_flags", self.lib.st_set_flags(self.h, int(flags)))
 

@@ -122,3 +122,25 @@ def test_adjoint_gradient_matches_central_differences(tv, filt):
         Jp = objective_and_gradient(g, MAT, rp.reshape(rho.shape), PATCH, 1.0, filt, False)["J"]
         Jn = objective_and_gradient(g, MAT, rm.reshape(rho.shape), PATCH, 1.0, filt, False)["J"]
         assert abs((Jp - Jn) / (2 * h) - ad) <= 1e-4 * abs(ad)
+
+
+def test_filter_cg_route_equals_lu():
+    rng = np.random.default_rng(9)
+    g = rng.uniform(0, 1, (6, 9, 8))
+    a = filter_apply(g, 0.125, 0.1, 0.19, 0.15, method="lu")
+    b = filter_apply(g, 0.125, 0.1, 0.19, 0.15, method="cg")
+    assert np.max(np.abs(a - b)) < 1e-12
+
+
+def test_block_gradient_route_equals_direct():
+    """The block-in-time gradient chain used for large fixtures equals the
+    global-LU chain."""
+    from oracle.blockgrad import objective_and_gradient_blocks
+    nx, nt = 8, 6
+    g = Grid(nx, nx, nt, 1 / 8, 1 / 6)
+    rng = np.random.default_rng(10)
+    rho = rng.uniform(0.1, 0.9, (nt, nx, nx))
+    a = objective_and_gradient(g, MAT, rho, PATCH, 1.0, 1.5)
+    b = objective_and_gradient_blocks(g, MAT, rho, PATCH, 1.0, 1.5)
+    assert abs(a["J"] - b["J"]) < 1e-13 * abs(a["J"])
+    assert np.max(np.abs(a["grad"] - b["grad"])) < 1e-11 * np.max(np.abs(a["grad"]))

@@ -1,0 +1,120 @@
+"""Serving loop: scheduling logic on a CPU mock backend, and on the GPU the
+continuous-batching run with the alone-vs-in-the-mix equality."""
+import threading
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2508_09589_amd.serve import Request, Server, request_density, run_stream
+
+
+class MockProblem:
+    """Stand-in with the Problem interface: a scripted duration per solve."""
+    live = 0
+    peak = 0
+    lock = threading.Lock()
+
+    def __init__(self, req, nbytes):
+        self.workspace_bytes = nbytes - 256
+        self.created_for = req.id
+        self.updates = 0
+        with MockProblem.lock:
+            MockProblem.live += 1
+
+    def set_stream(self, s):
+        pass
+
+    def update_density(self, rho):
+        self.updates += 1
+
+    def solve(self, allow_not_converged=False):
+        time.sleep(0.01)
+        info = type("I", (), dict(iterations=3, true_rel_res=1e-9))()
+        return np.zeros(1), info
+
+    def load_vector(self):
+        return np.zeros(1)
+
+    def adjoint(self, f, allow_not_converged=False):
+        time.sleep(0.01)
+        return np.zeros(1), type("I", (), dict(iterations=4))()
+
+    def sensitivity(self, T, lam):
+        return np.zeros(1)
+
+    def objective(self, T):
+        return 0.0
+
+    def close(self):
+        with MockProblem.lock:
+            MockProblem.live -= 1
+
+
+def _mock_server(budget, slots=3):
+    fp = lambda n, nt, tv, prec: n * n * nt * 100 + 256
+    mk = lambda req, dev, s: MockProblem(req, fp(req.n, req.nt, True, req.precision))
+    return Server(budget, slots=slots, device="cpu", make_problem=mk, footprint_fn=fp)
+
+
+def test_admission_respects_budget_and_reuses_resident_problems():
+    budget = 32 * 32 * 32 * 100 * 2 + 1000        # room for two 32^3 problems
+    srv = _mock_server(budget, slots=4)
+    reqs = [Request(i, 32, 32, np.zeros((32, 32, 32)), adjoint=(i % 2 == 1)) for i in range(12)]
+    futs = [srv.submit(r) for r in reqs]
+    out = [f.result(timeout=30) for f in futs]
+    srv.close()
+    assert [o["id"] for o in out] == list(range(12))
+    assert srv.peak_bytes <= budget
+    assert all("grad" in o for o in out if o["id"] % 2 == 1)
+    # at most two problems were ever built; the rest reused them
+    assert MockProblem.live == 0
+
+
+def test_oversized_request_is_rejected_not_stuck():
+    srv = _mock_server(1000, slots=1)
+    f = srv.submit(Request(0, 32, 32, np.zeros((32, 32, 32))))
+    with pytest.raises(MemoryError):
+        f.result(timeout=10)
+    srv.close()
+
+
+def test_eviction_makes_room_for_new_shapes():
+    fp32 = 32 * 32 * 32 * 100 + 256
+    srv = _mock_server(fp32 + 100, slots=1)     # room for one problem at a time
+    a = srv.submit(Request(0, 32, 32, np.zeros((32, 32, 32)))).result(timeout=10)
+    b = srv.submit(Request(1, 16, 16, np.zeros((16, 16, 16)))).result(timeout=10)
+    c = srv.submit(Request(2, 32, 32, np.zeros((32, 32, 32)))).result(timeout=10)
+    srv.close()
+    assert srv.peak_bytes <= fp32 + 100 and a and b and c
+
+
+def test_request_density_range_and_determinism():
+    a = request_density(32, 16, 7)
+    b = request_density(32, 16, 7)
+    assert a.shape == (16, 32, 32) and np.array_equal(a, b)
+    assert a.min() >= 0.001 and a.max() <= 1.0
+
+
+@pytest.mark.gpu
+def test_alone_equals_in_the_mix(require_gpu):
+    """Each request's temperature (and gradient) is bitwise the same when it
+    runs alone and when it runs concurrently with others."""
+    specs = [(32, 32, False), (64, 32, True), (32, 64, True), (64, 64, False), (32, 32, True)]
+    reqs = lambda: [Request(i, n, nt, request_density(n, nt, 100 + i), adjoint=adj, precision="mixed")
+                    for i, (n, nt, adj) in enumerate(specs)]
+    alone = {}
+    srv = Server(8 << 30, slots=1)
+    for r in reqs():
+        alone[r.id] = srv.submit(r).result(timeout=120)
+    srv.close()
+    srv = Server(8 << 30, slots=4)
+    futs = [srv.submit(r) for r in reqs()]
+    mix = {f.result(timeout=120)["id"]: f.result() for f in futs}
+    srv.close()
+    for i in alone:
+        assert torch.equal(alone[i]["T"], mix[i]["T"]), i
+        if "grad" in alone[i]:
+            assert torch.equal(alone[i]["grad"], mix[i]["grad"]), i
+        assert alone[i]["true_rel_res"] <= 1e-8
