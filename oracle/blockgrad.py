@@ -13,7 +13,8 @@ from .grid import dirichlet_mask
 from .solve import BlockTimeSystem
 
 
-def objective_and_gradient_blocks(grid, mat, rho, patches, q0=1.0, r_elems=None, tol=1e-13):
+def objective_and_gradient_blocks(grid, mat, rho, patches, q0=1.0, r_elems=None, tol=1e-12,
+                                  max_sweeps=60):
     rho = np.asarray(rho, dtype=np.float64)
     if r_elems is not None:
         rho_phys = filter_apply(rho, grid.dx, grid.dt, r_elems * grid.dx, r_elems * grid.dt)
@@ -23,8 +24,9 @@ def objective_and_gradient_blocks(grid, mat, rho, patches, q0=1.0, r_elems=None,
     mask = dirichlet_mask(grid, patches)
     f = load_vector(grid, q0)
     bs = BlockTimeSystem(grid, k, C, mask)
-    s, sw, rel = bs.gauss_seidel(bs.masked_rhs(f), tol=tol)
-    lam, sw2, rel2 = bs.gauss_seidel(bs.masked_rhs(f), tol=tol, transpose=True)
+    s, sw, rel = bs.gauss_seidel(bs.masked_rhs(f), tol=tol, max_sweeps=max_sweeps)
+    lam, sw2, rel2 = bs.gauss_seidel(bs.masked_rhs(f), tol=tol, transpose=True,
+                                     max_sweeps=max_sweeps)
     ge = element_sensitivity(grid, s, lam, dk, dC)
     g = reduce_to_design(ge, rho.shape)
     if r_elems is not None:

@@ -78,6 +78,8 @@ class Server:
                  make_problem=None, footprint_fn=None):
         self.budget = int(hbm_budget)
         self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         self.keep_outputs = keep_outputs
         self.make_problem = make_problem or _gpu_problem
         self.footprint_fn = footprint_fn or footprint
@@ -162,8 +164,12 @@ class Server:
                 self.cv.wait(timeout=0.05)
 
     def _worker(self, stream):
-        if self.device.type == "cuda":
-            torch.cuda.set_device(self.device)
+        try:
+            if self.device.type == "cuda":
+                torch.cuda.set_device(self.device)
+        except Exception as e:          # a slot that cannot start fails its requests
+            self._fail_all(e)
+            return
         while True:
             with self.cv:
                 item = self._take()
@@ -182,6 +188,14 @@ class Server:
                     self.busy_bytes -= holding
                     self.cv.notify_all()
                 fut.set_exception(e)
+
+    def _fail_all(self, exc):
+        with self.cv:
+            while self.queue:
+                _, fut = self.queue.popleft()
+                fut.set_exception(exc)
+            self.closed = True
+            self.cv.notify_all()
 
     def _run(self, req, prob, stream):
         ctx = torch.cuda.stream(stream) if stream is not None else _nullctx()

@@ -41,7 +41,8 @@ def grad():
     np.savez(os.path.join(HERE, "grad_128.npz"), J=out["J"], elems=idx,
              grad_at=out["grad"].ravel()[idx], grad_norm=np.linalg.norm(out["grad"]),
              nodes=nodes, s_at=out["s"][nodes], s_norm=np.linalg.norm(out["s"]),
-             lam_at=out["lam"][nodes], lam_norm=np.linalg.norm(out["lam"]))
+             lam_at=out["lam"][nodes], lam_norm=np.linalg.norm(out["lam"]),
+             rel_res=np.array(out["rel"]), sweeps=np.array(out["sweeps"]))
     print("grad fixture", out["J"], out["sweeps"], out["rel"], f"{time.time() - t:.1f} s")
 
 
@@ -54,7 +55,7 @@ def medium():
     f = load_vector(g, 1.0)
     t = time.time()
     bs = BlockTimeSystem(g, k, C, mask)
-    s, sw, rel = bs.gauss_seidel(bs.masked_rhs(f), tol=1e-13)
+    s, sw, rel = bs.gauss_seidel(bs.masked_rhs(f), tol=1e-12, max_sweeps=60)
     nodes = np.random.default_rng(6).choice(g.n_nodes, 4000, replace=False)
     np.savez(os.path.join(HERE, "medium_256.npz"), nodes=nodes, s_at=s[nodes],
              s_norm=np.linalg.norm(s), sweeps=sw, rel=rel)
