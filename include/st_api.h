@@ -58,7 +58,12 @@ enum { ST_EDGE_X1_LO = 0, ST_EDGE_X1_HI = 1, ST_EDGE_X2_LO = 2, ST_EDGE_X2_HI = 
 enum {
     ST_FLAG_TIME_KERNELS = 1,   /* record per-kernel-class GPU times in st_info;
                                    bits 8.. of flags select classes (0 = all)     */
-    ST_FLAG_NO_PLANE_DEDUP = 2  /* keep every time level of coarse stencils       */
+    ST_FLAG_NO_PLANE_DEDUP = 2, /* keep every time level of coarse stencils       */
+    ST_FLAG_COARSE_GMRES = 4    /* coarsest level: Jacobi-GMRES (coarse_max_it,
+                                   coarse_rtol, coarse_restart) as in §3.2, instead
+                                   of the default exact solve by block-tridiagonal
+                                   factorisation in time (used when
+                                   (nx + 1)(ny + 1) <= 2048 on that level)        */
 };
 
 #define ST_MAX_LEVELS 32
@@ -185,8 +190,10 @@ st_status st_filter(st_handle* h, const double* in_dev, double* out_dev);
  * old stream is synchronised first. */
 st_status st_set_stream(st_handle* h, void* hip_stream);
 
-/* Replace the option flags (ST_FLAG_TIME_KERNELS and its class mask) of a
- * built problem; the other options are fixed at setup. */
+/* Replace the option flags (ST_FLAG_TIME_KERNELS and its class mask,
+ * ST_FLAG_COARSE_GMRES) of a built problem; ST_FLAG_NO_PLANE_DEDUP and the
+ * other options are fixed at setup.  Switching to the exact coarse solve
+ * factorises the coarsest operator on the next V-cycle. */
 st_status st_set_flags(st_handle* h, int32_t flags);
 
 /* Fill the hierarchy fields of *info (levels, dims, distinct planes). */

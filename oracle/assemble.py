@@ -80,6 +80,20 @@ def load_vector(grid, q0=1.0, q_nodal=None):
     return f
 
 
+def load_vector_uniform(grid, q0=1.0):
+    """The uniform-Q load of load_vector without the connectivity scatter, for
+    grids too large for it: node a lies in c_x c_y c_t elements (c = 1 on a
+    boundary plane of that axis, 2 inside), so f_a = c_x c_y c_t q0 V_e / 8."""
+    def counts(n):
+        c = np.full(n + 1, 2.0)
+        c[0] = c[-1] = 1.0
+        return c
+    ve8 = q0 * grid.dx * grid.dx * grid.dt / 8.0
+    f = (counts(grid.nt)[:, None, None] * counts(grid.ny)[None, :, None]) * counts(grid.nx)[None, None, :]
+    f *= ve8
+    return f.ravel()
+
+
 def apply_dirichlet(J, f, mask, g=None):
     """Symmetric elimination of the Dirichlet set (reading: the paper is silent).
 

@@ -17,8 +17,12 @@ Readings (the paper gives only the parameters above):
   * pre-smoothing starts from zero, post-smoothing from the current iterate;
   * the outer FGMRES uses classical Gram-Schmidt with one re-orthogonalisation
     pass and stops on ||f - J s||_2 <= rtol ||f||_2.
+The V-cycle can also solve the coarsest level exactly (sparse LU), the
+variant the GPU library uses by default.
 """
 import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 
 def _givens(a, b):
@@ -90,18 +94,30 @@ def gmres_jacobi(A, b, x0=None, maxit=10, rtol=1e-6, restart=None, dinv=None):
 
 
 class VCycle:
-    """One classical V-cycle over the Galerkin hierarchy (§3.2)."""
+    """One classical V-cycle over the Galerkin hierarchy (§3.2).
+
+    coarse="gmres": the coarsest level is solved with Jacobi-GMRES as in §3.2;
+    coarse="direct": it is solved exactly (sparse LU of the coarsest operator).
+    """
 
     def __init__(self, A, Pm, smooth_its=10, smooth_rtol=1e-6, coarse_its=200,
-                 coarse_rtol=1e-6, coarse_restart=30):
+                 coarse_rtol=1e-6, coarse_restart=30, coarse="gmres"):
+        if coarse not in ("gmres", "direct"):
+            raise ValueError(coarse)
         self.A, self.Pm = A, Pm
         self.dinv = [1.0 / a.diagonal() for a in A]
         self.si, self.sr = smooth_its, smooth_rtol
         self.ci, self.cr, self.crs = coarse_its, coarse_rtol, coarse_restart
+        self.coarse = coarse
+        self._lu = None
 
     def __call__(self, b, l=0):
         A, dinv = self.A[l], self.dinv[l]
         if l == len(self.A) - 1:
+            if self.coarse == "direct":
+                if self._lu is None:
+                    self._lu = spla.splu(sp.csc_matrix(A))
+                return self._lu.solve(np.asarray(b, dtype=np.float64))
             return gmres_jacobi(A, b, None, self.ci, self.cr, self.crs, dinv)[0]
         x = gmres_jacobi(A, b, None, self.si, self.sr, None, dinv)[0]
         r = b - A @ x

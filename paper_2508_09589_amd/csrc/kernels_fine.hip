@@ -12,11 +12,11 @@
 //   y_s     += dt/6 K_s (2 x_s + x_{s+1})
 //   y_{s+1} += dt/6 K_s (x_s + 2 x_{s+1}) + M_s (x_{s+1} - x_s)
 // and for the transpose the capacity part moves to  y_s -= M_s x_{s+1},
-// y_{s+1} += M_s x_{s+1}.  A thread owns one (i, j) node column and marches
-// through a chunk of time levels, so every x value is loaded once per chunk
-// from its plane and the stiffness of the lower plane is reused when the
-// coefficients do not change in time.  Dirichlet nodes: inputs are masked to
-// zero and rows become identity rows (N J N + I - N).
+// y_{s+1} += M_s x_{s+1}.  A workgroup owns a tile of (i, j) node columns
+// and marches through a chunk of time levels, so every x value is loaded once
+// per chunk from its plane and the stiffness of the lower plane is reused when
+// the coefficients do not change in time.  Dirichlet nodes: inputs are masked
+// to zero and rows become identity rows (N J N + I - N).
 #include "st_internal.hpp"
 
 namespace st {
@@ -68,72 +68,143 @@ void launch_simp(hipStream_t s, long long ne, const double* rho, const st_materi
 }
 
 // ---------------------------------------------------------------------------
-// Matrix-free apply.
-// Register-blocked form: a thread owns RY consecutive rows (j) of one column
-// (i) and marches through a chunk of time levels; one level costs 3 (RY+2)
-// loads of x for RY outputs.  Block = 64 x 4 threads = 64 x 4 RY nodes.
-// RY = 4 for FP32 arithmetic, 2 for FP64 (register budget).
-template <typename TC> struct RowBlock { static constexpr int value = 4; };
-template <> struct RowBlock<double> { static constexpr int value = 2; };
+// Matrix-free apply, LDS-tiled.
+// A workgroup of 64 x 4 threads owns a tile of 64 node columns x 8 node rows
+// and marches through a chunk of time levels.  Per level the tile's x window
+// (10 x 66 values, halo included) and per slab its coefficient window (9 x 65
+// elements) are loaded once, coalesced, into LDS; the loads of level s + 2 and
+// slab s + 1 are issued before the arithmetic of slab s, so they are in flight
+// while it runs (three x buffers, two coefficient buffers, one barrier per
+// level).  A thread reads its 3 x 4 stencil window of the two levels of a slab
+// from LDS and produces 2 outputs of one column.  Workgroups are numbered so
+// that the eight XCDs (separate L2 caches) each get a contiguous range of
+// tiles: the halo rows a tile shares with its neighbours are then read from
+// the same L2.
+constexpr int FA_TX = 64, FA_RY = 2, FA_TY = 4 * FA_RY;
 
-template <typename TIN, typename TOUT, typename TC, bool TRANS, bool TCONST>
+template <typename TIN, typename TOUT, typename TC, bool TRANS, bool TCONST, bool CUNI>
 __global__ __launch_bounds__(256) void k_fine_apply(
     FineGeom g, const TC* __restrict__ kc, const TC* __restrict__ cc, const TIN* __restrict__ x,
     TOUT* __restrict__ y, const TOUT* __restrict__ b, const TOUT* __restrict__ invd,
-    const double* __restrict__ scale, const int* __restrict__ skip, int nchunk, int mask_in,
-    int dir_rows) {
-    constexpr int RY = RowBlock<TC>::value;
+    const double* __restrict__ scale, const int* __restrict__ skip, int gx, int gy, int nchunk,
+    int per_xcd, int mask_in, int dir_rows) {
+    constexpr int RY = FA_RY, TX = FA_TX, TY = FA_TY;
+    constexpr int WX = TX + 2, NW = WX * (TY + 2);            // x window
+    constexpr int EX = TX + 1, NE = EX * (TY + 1);            // element window
+    constexpr int LW = (NW + 255) / 256, LE = (NE + 255) / 256;
+    __shared__ TC xs[3][NW];
+    __shared__ TC ks[2][NE];
+    __shared__ TC cs[CUNI ? 1 : 2][CUNI ? 1 : NE];
+
     if (skip && *skip) return;
+    // XCD-aware tile order: hardware workgroup b runs on XCD b % 8.
+    const int bid = blockIdx.x;
+    const int lin = (bid & 7) * per_xcd + (bid >> 3);
+    const int tiles = gx * gy;
+    const int bz = lin / tiles;
+    const int rem = lin - bz * tiles;
+    const int by = rem / gx, bx = rem - by * gx;
     const int nx = g.nx, ny = g.ny, nt = g.nt;
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    const int j0 = (blockIdx.y * 4 + threadIdx.y) * RY;
-    if (i > nx || j0 > ny) return;
-    const int n0 = blockIdx.z * nchunk;
-    if (n0 > nt) return;
+    const int n0 = bz * nchunk;
+    if (n0 > nt) return;                      // uniform over the workgroup
     const int n1 = min(n0 + nchunk, nt + 1);
-    const long long rowp = nx + 1;
-    const long long P = rowp * (ny + 1);
+    const int tx = threadIdx.x, ry0 = threadIdx.y * RY;
+    const int tid = threadIdx.y * 64 + tx;
+    const int i0 = bx * TX, jb = by * TY;
+    const int rowp = nx + 1;
+    const long long P = (long long)rowp * (ny + 1);
     const long long slab = (long long)nx * ny;
 
-    // Loaded window: rows j0-1 .. j0+RY (RY+2), columns i-1 .. i+1.
-    unsigned valid = 0, patch = 0;
+    // Which window entries tid + 256 r this thread loads, and which of them
+    // are live (inside the grid and, with mask_in, not on a patch).
+    unsigned xlive = 0, elive = 0;
 #pragma unroll
-    for (int m = 0; m < RY + 2; ++m)
+    for (int r = 0; r < LW; ++r) {
+        const int e = tid + 256 * r;
+        const int row = e / WX, col = e - (e / WX) * WX;
+        const int gi = i0 - 1 + col, gj = jb - 1 + row;
+        if (e < NW && gi >= 0 && gi <= nx && gj >= 0 && gj <= ny &&
+            !(mask_in && on_patch(g.patches, nx, ny, gi, gj)))
+            xlive |= 1u << r;
+    }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int ii = i + c - 1, jj = j0 + m - 1;
-            const bool v = ii >= 0 && ii <= nx && jj >= 0 && jj <= ny;
-            const int bit = m * 3 + c;
-            if (v) valid |= 1u << bit;
-            if (v && on_patch(g.patches, nx, ny, ii, jj)) patch |= 1u << bit;
-        }
-    const unsigned live_in = mask_in ? (valid & ~patch) : valid;
-    const long long base = (long long)(j0 - 1) * rowp + (i - 1);
-
-    auto load_plane = [&](int n, TC u[RY + 2][3]) {
-        const TIN* xp = x + (long long)n * P + base;
-        const unsigned live = (mask_in && g.ic_dir && n == 0) ? 0u : live_in;
-#pragma unroll
-        for (int m = 0; m < RY + 2; ++m)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                u[m][c] = ((live >> (m * 3 + c)) & 1u) ? (TC)xp[(long long)m * rowp + c] : (TC)0;
+    for (int r = 0; r < LE; ++r) {
+        const int e = tid + 256 * r;
+        const int row = e / EX, col = e - (e / EX) * EX;
+        const int ei = i0 - 1 + col, ej = jb - 1 + row;
+        if (e < NE && ei >= 0 && ei < nx && ej >= 0 && ej < ny) elive |= 1u << r;
+    }
+    auto xoff = [&](int r) -> unsigned {
+        const int e = tid + 256 * r;
+        const int row = e / WX;
+        return (unsigned)((jb - 1 + row) * rowp + (i0 - 1 + e - row * WX));
     };
-    // Element coefficients of rows j0-1 .. j0+RY-1 (RY+1), columns i-1, i.
-    TC ke[RY + 1][2], ce[RY + 1][2];
-    auto load_coef = [&](int s) {
-        const long long sb = TCONST ? 0 : (long long)s * slab;
+    auto eoff = [&](int r) -> unsigned {
+        const int e = tid + 256 * r;
+        const int row = e / EX;
+        return (unsigned)((jb - 1 + row) * nx + (i0 - 1 + e - row * EX));
+    };
+    TC px[LW], pk[LE], pc[CUNI ? 1 : LE];
+    auto fetch_x = [&](int n) {
+        const TIN* xp = x + (long long)n * P;
+        const unsigned live = (mask_in && g.ic_dir && n == 0) ? 0u : xlive;
+#pragma unroll
+        for (int r = 0; r < LW; ++r) px[r] = ((live >> r) & 1u) ? (TC)xp[xoff(r)] : (TC)0;
+    };
+    auto put_x = [&](int n) {
+        TC* d = xs[n % 3];
+#pragma unroll
+        for (int r = 0; r < LW; ++r)
+            if (tid + 256 * r < NW) d[tid + 256 * r] = px[r];
+    };
+    auto fetch_c = [&](int s) {
+        const TC* kp = kc + (TCONST ? 0 : (long long)s * slab);
+        const TC* cp = cc + (TCONST ? 0 : (long long)s * slab);
+#pragma unroll
+        for (int r = 0; r < LE; ++r) {
+            const bool v = (elive >> r) & 1u;
+            pk[r] = v ? kp[eoff(r)] : (TC)0;
+            if (!CUNI) pc[r] = v ? cp[eoff(r)] : (TC)0;
+        }
+    };
+    auto put_c = [&](int s) {
+#pragma unroll
+        for (int r = 0; r < LE; ++r)
+            if (tid + 256 * r < NE) {
+                ks[s & 1][tid + 256 * r] = pk[r];
+                if (!CUNI) cs[s & 1][tid + 256 * r] = pc[r];
+            }
+    };
+    // Capacity of the elements around this thread's nodes when it is uniform.
+    unsigned cval = 0;
+    if (CUNI) {
 #pragma unroll
         for (int m = 0; m < RY + 1; ++m)
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                const int ei = i + c - 1, ej = j0 + m - 1;
-                const bool v = ei >= 0 && ei < nx && ej >= 0 && ej < ny;
-                const long long e = sb + (long long)ej * nx + ei;
-                ke[m][c] = v ? kc[e] : (TC)0;
-                ce[m][c] = v ? (g.cuniform ? (TC)g.c0 : cc[e]) : (TC)0;
+                const int ei = i0 + tx + c - 1, ej = jb + ry0 + m - 1;
+                if (ei >= 0 && ei < nx && ej >= 0 && ej < ny) cval |= 1u << (m * 2 + c);
+            }
+    }
+    TC ke[RY + 1][2], ce[RY + 1][2];
+    auto read_c = [&](int s) {
+#pragma unroll
+        for (int m = 0; m < RY + 1; ++m)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                ke[m][c] = ks[s & 1][(ry0 + m) * EX + tx + c];
+                ce[m][c] = CUNI ? (((cval >> (m * 2 + c)) & 1u) ? (TC)g.c0 : (TC)0)
+                                : cs[CUNI ? 0 : (s & 1)][CUNI ? 0 : (ry0 + m) * EX + tx + c];
             }
     };
+    auto read_x = [&](int n, TC u[RY + 2][3]) {
+        const TC* sx = xs[n % 3];
+#pragma unroll
+        for (int m = 0; m < RY + 2; ++m)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) u[m][c] = sx[(ry0 + m) * WX + tx + c];
+    };
+
     const TC kt = (TC)g.dt6;
     const TC mw = (TC)g.mw;
     const TC sc = scale ? (TC)(*scale) : (TC)1;
@@ -158,32 +229,76 @@ __global__ __launch_bounds__(256) void k_fine_apply(
         v += cSW * u[m][0] + cSE * u[m][2] + cNW * u[m + 2][0] + cNE * u[m + 2][2];
         return v;
     };
+
+    // Own outputs: column i, rows jb + ry0 + m.
+    const int i = i0 + tx;
+    unsigned own = 0, opatch = 0;
+#pragma unroll
+    for (int m = 0; m < RY; ++m) {
+        const int j = jb + ry0 + m;
+        if (i <= nx && j <= ny) {
+            own |= 1u << m;
+            if (on_patch(g.patches, nx, ny, i, j)) opatch |= 1u << m;
+        }
+    }
+    const long long obase = (long long)(jb + ry0) * rowp + i;
+    TOUT bv[RY], dv[RY];
+    auto fetch_bd = [&](int n) {
+#pragma unroll
+        for (int m = 0; m < RY; ++m) {
+            const long long idx = (long long)n * P + obase + (long long)m * rowp;
+            const bool o = (own >> m) & 1u;
+            bv[m] = (b && o) ? b[idx] : (TOUT)0;
+            dv[m] = (invd && o) ? invd[idx] : (TOUT)0;
+        }
+    };
     auto emit = [&](int n, int m, TC v) {
-        const int j = j0 + m;
-        if (j > ny) return;
-        const long long idx = (long long)n * P + (long long)j * rowp + i;
-        const bool dir = dir_rows && ((g.ic_dir && n == 0) || ((patch >> ((m + 1) * 3 + 1)) & 1u));
+        if (!((own >> m) & 1u)) return;
+        const long long idx = (long long)n * P + obase + (long long)m * rowp;
+        const bool dir = dir_rows && ((g.ic_dir && n == 0) || ((opatch >> m) & 1u));
         TC val = dir ? (TC)x[idx] : v;
-        if (b) val = (TC)b[idx] - val;
-        if (invd) val *= (TC)invd[idx];
+        if (b) val = (TC)bv[m] - val;
+        if (invd) val *= (TC)dv[m];
         y[idx] = (TOUT)(val * sc);
     };
 
     const int sa = max(n0 - 1, 0);
     const int sb = min(n1 - 1, nt - 1);
     TC ulo[RY + 2][3], uhi[RY + 2][3];
-    load_plane(sa, ulo);
     TC Plo[RY], Rlo[RY], acc[RY];
-    if (TCONST) load_coef(0);
+    fetch_x(sa);
+    put_x(sa);
+    fetch_c(sa);
+    put_c(sa);
+    fetch_x(sa + 1);
+    if (!TCONST && sa + 1 <= sb) fetch_c(sa + 1);
+    __syncthreads();
+    read_c(sa);
 #pragma unroll
     for (int m = 0; m < RY; ++m) {
         acc[m] = 0;
-        Plo[m] = TCONST ? kt * stiff(ulo, m) : (TC)0;
-        Rlo[m] = TCONST ? mw * mass(ulo, m) : (TC)0;
+        Plo[m] = 0;
+        Rlo[m] = 0;
+    }
+    if (TCONST) {
+        read_x(sa, ulo);
+#pragma unroll
+        for (int m = 0; m < RY; ++m) {
+            Plo[m] = kt * stiff(ulo, m);
+            Rlo[m] = mw * mass(ulo, m);
+        }
     }
     for (int s = sa; s <= sb; ++s) {
-        load_plane(s + 1, uhi);
-        if (!TCONST) load_coef(s);
+        put_x(s + 1);
+        if (!TCONST && s + 1 <= sb) put_c(s + 1);
+        __syncthreads();
+        if (s + 1 <= sb) {
+            fetch_x(s + 2);
+            if (!TCONST && s + 2 <= sb) fetch_c(s + 2);
+        }
+        if (s >= n0) fetch_bd(s);
+        if (!TCONST) read_x(s, ulo);
+        read_x(s + 1, uhi);
 #pragma unroll
         for (int m = 0; m < RY; ++m) {
             const TC Pv = TCONST ? Plo[m] : kt * stiff(ulo, m);
@@ -205,12 +320,10 @@ __global__ __launch_bounds__(256) void k_fine_apply(
                 Rlo[m] = Sv;
             }
         }
-#pragma unroll
-        for (int m = 0; m < RY + 2; ++m)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) ulo[m][c] = uhi[m][c];
+        if (!TCONST && s + 1 <= sb) read_c(s + 1);
     }
     if (sb + 1 == nt && nt >= n0 && nt < n1) {
+        fetch_bd(nt);
 #pragma unroll
         for (int m = 0; m < RY; ++m) emit(nt, m, acc[m]);
     }
@@ -220,32 +333,36 @@ template <typename TIN, typename TOUT, typename TC>
 static void fine_dispatch(hipStream_t s, const FineGeom& g, const TC* kc, const TC* cc, int trans,
                           const void* x, void* y, const void* b, const void* invd,
                           const double* scale, const int* skip, int mask_in, int dir_rows) {
-    constexpr int RY = RowBlock<TC>::value;
-    const int gx = (g.nx + 1 + 63) / 64, gy = (g.ny + 1 + 4 * RY - 1) / (4 * RY);
-    long long cols = (long long)gx * gy;
+    const int gx = (g.nx + 1 + FA_TX - 1) / FA_TX, gy = (g.ny + 1 + FA_TY - 1) / FA_TY;
+    const long long tiles = (long long)gx * gy;
     int nchunk = 32;
-    while (nchunk > 4 && cols * ((g.nt + 1 + nchunk - 1) / nchunk) < 4096) nchunk /= 2;
-    const int gz = (g.nt + 1 + nchunk - 1) / nchunk;
-    dim3 grid(gx, gy, gz), block(64, 4);
+    while (nchunk > 8 && tiles * ((g.nt + 1 + nchunk - 1) / nchunk) < 2048) nchunk /= 2;
+    const long long gz = (g.nt + 1 + nchunk - 1) / nchunk;
+    const long long per_xcd = (tiles * gz + 7) / 8;
+    dim3 grid((unsigned)(8 * per_xcd)), block(64, 4);
     const TIN* xi = (const TIN*)x;
     TOUT* yo = (TOUT*)y;
     const TOUT* bi = (const TOUT*)b;
     const TOUT* di = (const TOUT*)invd;
+    const int px = (int)per_xcd;
+#define FA_LAUNCH(TR, TCN, CU)                                                                  \
+    hipLaunchKernelGGL((k_fine_apply<TIN, TOUT, TC, TR, TCN, CU>), grid, block, 0, s, g, kc, cc, \
+                       xi, yo, bi, di, scale, skip, gx, gy, nchunk, px, mask_in, dir_rows)
+    const bool cu = g.cuniform != 0;
     if (g.tconst) {
-        if (trans)
-            hipLaunchKernelGGL((k_fine_apply<TIN, TOUT, TC, true, true>), grid, block, 0, s, g, kc,
-                               cc, xi, yo, bi, di, scale, skip, nchunk, mask_in, dir_rows);
-        else
-            hipLaunchKernelGGL((k_fine_apply<TIN, TOUT, TC, false, true>), grid, block, 0, s, g,
-                               kc, cc, xi, yo, bi, di, scale, skip, nchunk, mask_in, dir_rows);
+        if (trans) {
+            if (cu) FA_LAUNCH(true, true, true); else FA_LAUNCH(true, true, false);
+        } else {
+            if (cu) FA_LAUNCH(false, true, true); else FA_LAUNCH(false, true, false);
+        }
     } else {
-        if (trans)
-            hipLaunchKernelGGL((k_fine_apply<TIN, TOUT, TC, true, false>), grid, block, 0, s, g,
-                               kc, cc, xi, yo, bi, di, scale, skip, nchunk, mask_in, dir_rows);
-        else
-            hipLaunchKernelGGL((k_fine_apply<TIN, TOUT, TC, false, false>), grid, block, 0, s, g,
-                               kc, cc, xi, yo, bi, di, scale, skip, nchunk, mask_in, dir_rows);
+        if (trans) {
+            if (cu) FA_LAUNCH(true, false, true); else FA_LAUNCH(true, false, false);
+        } else {
+            if (cu) FA_LAUNCH(false, false, true); else FA_LAUNCH(false, false, false);
+        }
     }
+#undef FA_LAUNCH
 }
 
 // prec_in / prec_out: 0 = double, 1 = float.  compute64: arithmetic and

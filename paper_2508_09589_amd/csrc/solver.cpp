@@ -62,6 +62,14 @@ struct st_handle {
     KState* ks_outer = nullptr;
     double* coarseV = nullptr;
     double* coarseWork = nullptr;
+    // exact coarsest solve: factors D'^{-1} [nt+1][P][P] and G [nt][P][P],
+    // Gauss-Jordan matrix (when it does not fit in LDS), pivot scratch
+    bool cd_fit = false;       // plane small enough for the factorisation
+    bool cd_ok = false;        // ... and no zero pivot met
+    bool cd_factored = false;  // factors match the current coarse operator
+    double *cd_Dinv = nullptr, *cd_G = nullptr, *cd_A = nullptr, *cd_colk = nullptr;
+    int* cd_perm = nullptr;
+    int* cd_status = nullptr;
     double* partials = nullptr;
     double* dscal = nullptr;   // device scalars
     int* neq = nullptr;        // plane comparison flags
@@ -214,6 +222,18 @@ size_t carve(st_handle* h, char* base) {
     const Level& Lc = h->lev[h->nlev - 1];
     h->coarseV = c.take<double>((size_t)(o.coarse_restart + 1) * Lc.nn);
     h->coarseWork = c.take<double>((size_t)3 * Lc.nn);
+    {
+        const long long P = (long long)(Lc.nx + 1) * (Lc.ny + 1);
+        h->cd_fit = coarse_direct_fits((int)std::min<long long>(P, 1 << 30));
+        if (h->cd_fit) {
+            h->cd_Dinv = c.take<double>((size_t)P * P * (Lc.nt + 1));
+            h->cd_G = c.take<double>((size_t)P * P * Lc.nt);
+            h->cd_A = coarse_direct_lds((int)P) > CD_LDS_MAX ? c.take<double>((size_t)P * P) : nullptr;
+            h->cd_colk = c.take<double>((size_t)P);
+            h->cd_perm = c.take<int>((size_t)P);
+            h->cd_status = c.take<int>(1);
+        }
+    }
     if (o.filter_r > 0) {
         h->fnt = h->rho_tv ? h->grid.nt : 1;
         h->fnn = (long long)(h->grid.nx + 1) * (h->grid.ny + 1) * (h->fnt + 1);
@@ -327,6 +347,14 @@ void collect_timing(st_handle* h, st_info* info) {
 enum { KC_FINE64 = 0, KC_FINEV = 1, KC_STENCIL = 2, KC_DOT = 3, KC_AXPY = 4, KC_TRANSFER = 5,
        KC_COARSE = 6, KC_MISC = 7, KC_DOT_C = 8, KC_AXPY_C = 9, KC_OUTER = 10, KC_UPDATE = 11 };
 
+// Coefficient bytes one fine apply reads: k, and C unless it is uniform, per
+// element (one slab of them when the density does not vary in time).
+int64_t fine_coef_bytes(const st_handle* h, int vb) {
+    const Level& L = h->lev[0];
+    const int64_t ne = (int64_t)L.nx * L.ny * (h->fg.tconst ? 1 : L.nt);
+    return ne * vb * (h->fg.cuniform ? 1 : 2);
+}
+
 // ---------------------------------------------------------------------------
 // Operator applications on a level.  Level 0 is matrix-free; coarse levels
 // use their Galerkin stencil.  prec: storage/arithmetic precision (0 FP64,
@@ -337,8 +365,10 @@ void level_apply(st_handle* h, int l, int prec, int trans, const void* x, void* 
     if (l == 0) {
         Coef cf{h->k64, h->c64, h->k32, h->c32};
         const int v = prec;
+        // x, y, optional b and invd per node, k (and C unless uniform) per element.
         Timed t(h, v == 0 ? KC_FINE64 : KC_FINEV,
-                (int64_t)L.nn * (int64_t)(2 * vbytes(v) + (b ? vbytes(v) : 0) + (invd ? vbytes(v) : 0)));
+                (int64_t)L.nn * (int64_t)(2 * vbytes(v) + (b ? vbytes(v) : 0) + (invd ? vbytes(v) : 0)) +
+                    fine_coef_bytes(h, vbytes(v)));
         launch_fine_apply(h->stream, h->fg, cf, v, v, v == 0, trans, x, y, b, invd, scale, skip, 1, 1);
     } else {
         const int sb = prec == 0 ? 8 : (L.sprec == 2 ? 2 : 4);
@@ -391,6 +421,23 @@ void smooth(st_handle* h, int l, int prec, int trans, const void* b, void* x, in
     launch_update(s, n, prec, prec, x, V, ld, ks, zero_x0, SMAX);
 }
 
+// Factorise the coarsest operator for the exact coarse solve (once per
+// operator build).  A zero pivot leaves the level to the iterative solve.
+st_status coarse_factor(st_handle* h) {
+    const Level& L = h->lev[h->nlev - 1];
+    hipStream_t s = h->stream;
+    launch_coarse_factor(s, L, h->cd_A, h->cd_Dinv, h->cd_G, h->cd_colk, h->cd_perm,
+                         h->cd_status);
+    int st = 0;
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(h->hbuf, h->cd_status, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    memcpy(&st, h->hbuf, sizeof(int));
+    h->cd_factored = true;
+    if (st) h->cd_ok = false;
+    return ST_OK;
+}
+
 // Classical V-cycle (§3.2): pre-smoothing from zero, residual, restriction,
 // recursion, prolongation, post-smoothing; Jacobi-GMRES on the coarsest level.
 void vcycle(st_handle* h, int l, const void* b, void* x, int trans) {
@@ -400,9 +447,14 @@ void vcycle(st_handle* h, int l, const void* b, void* x, int trans) {
     hipStream_t s = h->stream;
     if (l == h->nlev - 1) {
         if (!L.st64) return;   // unreachable: setup builds a stencil for the coarsest level
+        if (!(o.flags & ST_FLAG_COARSE_GMRES) && h->cd_ok && !h->cd_factored)
+            (void)coarse_factor(h);   // flags changed after the operator build
         Timed t(h, KC_COARSE, 0);
-        launch_coarse_solve(s, L, p, trans, b, x, h->coarseV, h->coarseWork, o.coarse_max_it,
-                            o.coarse_restart, o.coarse_rtol, 1);
+        if (!(o.flags & ST_FLAG_COARSE_GMRES) && h->cd_ok)
+            launch_coarse_direct(s, L, p, trans, b, x, h->cd_Dinv, h->cd_G, h->coarseWork);
+        else
+            launch_coarse_solve(s, L, p, trans, b, x, h->coarseV, h->coarseWork, o.coarse_max_it,
+                                o.coarse_restart, o.coarse_rtol, 1);
         return;
     }
     smooth(h, l, p, trans, b, x, 1, o.smooth_its, o.smooth_rtol, L.V, L.ks);
@@ -562,6 +614,12 @@ st_status build_operators(st_handle* h) {
         launch_stencil_invdiag(s, C, C.invd64, C.invd32);
         if (C.st32 || C.st16) launch_stencil_cast(s, C, C.st32, C.st16);
     }
+    h->cd_ok = h->cd_fit;
+    h->cd_factored = false;
+    if (h->cd_ok && !(h->opts.flags & ST_FLAG_COARSE_GMRES)) {
+        rc = coarse_factor(h);
+        if (rc != ST_OK) return rc;
+    }
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
     return ST_OK;
@@ -623,7 +681,7 @@ st_status fgmres(st_handle* h, const double* f, const double* fnorm_dev, double*
         // r0 = f - J x
         {
             Coef cf{h->k64, h->c64, h->k32, h->c32};
-            Timed t(h, KC_FINE64, n * 24);
+            Timed t(h, KC_FINE64, n * 24 + fine_coef_bytes(h, 8));
             launch_fine_apply(s, h->fg, cf, 0, 0, 1, trans, x, Vj(0), f, nullptr, nullptr, nullptr, 1, 1);
         }
         launch_mdot(s, n, 0, 0, Vj(0), Vj(0), ld, 1, h->partials, ks, FIN_INIT_REF, 0, 1);
@@ -646,7 +704,7 @@ st_status fgmres(st_handle* h, const double* f, const double* fnorm_dev, double*
             vcycle(h, 0, h->lev[0].b, Zj(j), trans);
             {
                 Coef cf{h->k64, h->c64, h->k32, h->c32};
-                Timed t(h, KC_FINE64, n * (8 + zb));
+                Timed t(h, KC_FINE64, n * (8 + zb) + fine_coef_bytes(h, 8));
                 launch_fine_apply(s, h->fg, cf, zp, 0, 1, trans, Zj(j), Vj(j + 1), nullptr, nullptr,
                                   nullptr, nullptr, 1, 1);
             }

@@ -154,6 +154,16 @@ void launch_coarse_solve(hipStream_t s, const Level& L, int prec_io, int trans, 
                          void* x, double* V, double* work, int maxit, int restart, double rtol,
                          int zero_x0);
 
+// Exact coarsest-level solve by block-tridiagonal factorisation in time.
+constexpr int CD_MAX_PLANE = 2048;        // largest (nx + 1)(ny + 1) it is used for
+constexpr size_t CD_LDS_MAX = 56 * 1024;  // Gauss-Jordan matrix in LDS up to this size
+bool coarse_direct_fits(int P);
+size_t coarse_direct_lds(int P);
+void launch_coarse_factor(hipStream_t s, const Level& L, double* Ag, double* Dinv, double* G,
+                          double* colk, int* perm, int* status);
+void launch_coarse_direct(hipStream_t s, const Level& L, int prec_io, int trans, const void* b,
+                          void* x, const double* Dinv, const double* G, double* work);
+
 // Right-hand side, objective, sensitivities, filter.
 void launch_load_uniform(hipStream_t s, const FineGeom& g, double q0, double dx, double dt,
                          double* f);

@@ -128,16 +128,39 @@ def test_smoother_matches_oracle_gmres(torch_cuda, level):
 
 
 @pytest.mark.parametrize("tv", [False, True])
-def test_vcycle_matches_oracle(torch_cuda, tv):
+@pytest.mark.parametrize("coarse", ["gmres", "direct"])
+def test_vcycle_matches_oracle(torch_cuda, tv, coarse):
     c = Case(16, 16, 16, tv=tv, seed=11, max_coarse_nodes=200)
-    p = c.problem(max_coarse_nodes=200)
+    p = c.problem(max_coarse_nodes=200, coarse=coarse)
     A, masks, Pm = c.ops
     rng = np.random.default_rng(5)
     b = rng.standard_normal(A[0].shape[0])
     b[masks[0]] = 0.0
     for trans in (False, True):
         At = [a.T.tocsr() for a in A] if trans else A
-        xo = VCycle(At, Pm)(b)
+        xo = VCycle(At, Pm, coarse=coarse)(b)
         xg = p.debug_vcycle(_t(b).reshape(p.level_shape(0)), transpose=trans).cpu().numpy()
         assert rel(xg, xo) < 1e-9, (trans, rel(xg, xo))
+    p.close()
+
+
+@pytest.mark.parametrize("nx,ny,nt,tv", [(8, 8, 16, True), (5, 7, 3, False), (12, 12, 4, True),
+                                         (1, 1, 1, False), (3, 2, 9, True)])
+def test_direct_coarse_solve_is_exact(torch_cuda, nx, ny, nt, tv):
+    """A one-level hierarchy makes the V-cycle the coarsest-level solve: the
+    block-tridiagonal factorisation must reproduce the oracle's direct solve,
+    forward and transposed (12 x 12 runs the Gauss-Jordan step out of LDS)."""
+    from oracle.solve import solve_direct, solve_adjoint_direct
+    c = Case(nx, ny, nt, tv=tv, seed=nx + 3 * ny + 7 * nt,
+             patches=((0, 0.5 * ny / max(nx, ny), 0.2), (3, 0.4, 0.3)))
+    p = c.problem(max_levels=1)
+    assert p.hierarchy()[0] == [(nx, ny, nt)]
+    rng = np.random.default_rng(8)
+    b = rng.standard_normal(c.Jm.shape[0])
+    shp = p.level_shape(0)
+    xg = p.debug_vcycle(_t(b).reshape(shp), transpose=False).cpu().numpy()
+    assert rel(xg, solve_direct(c.Jm, b)) < 1e-11
+    xg = p.debug_vcycle(_t(b).reshape(shp), transpose=True).cpu().numpy()
+    import scipy.sparse as sp
+    assert rel(xg, solve_direct(sp.csr_matrix(c.Jm.T), b)) < 1e-11
     p.close()

@@ -16,12 +16,14 @@ def torch_cuda(require_gpu):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_small_workload_parity(torch_cuda, precision):
+@pytest.mark.parametrize("coarse", ["direct", "gmres"])
+def test_small_workload_parity(torch_cuda, precision, coarse):
     """32^2 x 32, time-constant uniform-random density, left-edge patch: the
-    solution in parity mode (rtol 1e-12) matches the direct solve to 1e-10."""
+    solution in parity mode (rtol 1e-12) matches the direct solve to 1e-10,
+    with either coarsest-level solver."""
     from paper_2508_09589_amd.inputs import uniform_density
     c = Case(32, 32, 32, rho=uniform_density(32, seed=0))
-    p = c.problem(precision=precision, rtol=1e-12)
+    p = c.problem(precision=precision, rtol=1e-12, coarse=coarse)
     T, info = p.solve()
     s = solve_direct(c.Jm, c.fm)
     assert info.true_rel_res <= 1e-12

@@ -96,3 +96,14 @@ def test_simp_endpoints_and_derivative():
     km, Cm, _, _ = simp(np.array([0.3 - h]), mat)
     assert abs((kp - km)[0] / (2 * h) - dk[2]) < 1e-8
     assert abs((Cp - Cm)[0] / (2 * h) - dC[2]) < 1e-8
+
+
+def test_uniform_load_without_scatter():
+    """The separable uniform load equals the scattered one on ragged grids,
+    and the loads sum to q0 times the space-time volume."""
+    from oracle.assemble import load_vector_uniform
+    for nx, ny, nt in [(1, 1, 1), (5, 3, 4), (7, 9, 2)]:
+        g = Grid(nx, ny, nt, 0.3, 0.7)
+        f = load_vector_uniform(g, 2.5)
+        assert np.max(np.abs(f - load_vector(g, 2.5))) < 1e-15
+        assert abs(f.sum() - 2.5 * nx * ny * 0.09 * nt * 0.7) < 1e-12

@@ -144,3 +144,44 @@ def test_block_gradient_route_equals_direct():
     b = objective_and_gradient_blocks(g, MAT, rho, PATCH, 1.0, 1.5)
     assert abs(a["J"] - b["J"]) < 1e-13 * abs(a["J"])
     assert np.max(np.abs(a["grad"] - b["grad"])) < 1e-11 * np.max(np.abs(a["grad"]))
+
+
+@pytest.mark.parametrize("trans", [False, True])
+def test_direct_coarse_vcycle_one_level_is_exact(trans):
+    """With one level the V-cycle is the coarsest-level solve: the exact
+    variant leaves no residual."""
+    g, A, b, mask = _system(6, 5, seed=7, tv=True)
+    At = A.T.tocsr() if trans else A
+    x = VCycle([At], [], coarse="direct")(b)
+    assert np.linalg.norm(b - At @ x) <= 1e-13 * np.linalg.norm(b)
+
+
+def test_direct_coarse_two_grid_galerkin_orthogonality():
+    """Without smoothing, a two-level cycle with an exact coarse solve is the
+    Galerkin correction x = P A_c^-1 P^T b, whose residual is orthogonal to
+    range(P): P^T (b - A x) = 0."""
+    g, A, b, mask = _system(8, 8, seed=3, tv=True)
+    lv = build_hierarchy(8, 8, 8, 1 / 8, 1 / 8, 1.0, 1e-3, 1.0, 1.0, n_levels=2)
+    As, masks, Pm = build_operators(lv, A, mask)
+    x = VCycle(As, Pm, smooth_its=0, coarse="direct")(b)
+    assert np.linalg.norm(Pm[0].T @ (b - A @ x)) <= 1e-13 * np.linalg.norm(Pm[0].T @ b)
+    assert np.linalg.norm(x) > 0
+
+
+def test_fgmres_direct_coarse_matches_direct_solution():
+    """The exact coarse solve changes neither the converged solution nor (on
+    the small workload) the outer iteration count by more than one."""
+    from paper_2508_09589_amd.inputs import uniform_density
+    rho = uniform_density(32, seed=0)
+    g = Grid(32, 32, 32, 1 / 32, 1 / 32)
+    k = 1e-3 + (1 - 1e-3) * rho ** 3
+    mask = dirichlet_mask(g, PATCH)
+    Jm, fm = apply_dirichlet(assemble_matrix(g, k, np.ones_like(k)), load_vector(g, 1.0), mask)
+    lv = build_hierarchy(32, 32, 32, 1 / 32, 1 / 32, 1.0, 1e-3, 1.0, 1.0)
+    A, masks, Pm = build_operators(lv, Jm, mask)
+    x1, its1, rel1 = fgmres(Jm, fm, VCycle(A, Pm), m=30, rtol=1e-10)
+    x2, its2, rel2 = fgmres(Jm, fm, VCycle(A, Pm, coarse="direct"), m=30, rtol=1e-10)
+    xs = solve_direct(Jm, fm)
+    assert rel2 <= 1e-10
+    assert np.linalg.norm(x2 - xs) <= 1e-8 * np.linalg.norm(xs)
+    assert abs(its1 - its2) <= 1
