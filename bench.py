@@ -214,6 +214,19 @@ def run_serving(args):
     return out
 
 
+def copy_calibration():
+    """Three copies of a 1 GiB FP32 buffer: 1 GiB read and 1 GiB written per
+    dispatch, the reference for scaling FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    log("copy calibration: 3 x 1 GiB device copies done")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,16 +238,23 @@ def main():
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--bf16-from-level", type=int, default=0)
+    ap.add_argument("--bf16-from-level", type=int, default=1,
+                    help="mixed precision: store coarse stencils of levels >= this in BF16 "
+                         "(0 = FP32 everywhere)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare-fp64", action="store_true")
     ap.add_argument("--max-it", type=int, default=400)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the run, copy 1 GiB device buffers three times (a plain copy "
+                         "kernel of known size, for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU time-slab sharding is a design only)", file=sys.stderr)
         sys.exit(2)
     print(json.dumps(run_serving(args) if args.workload == "serving" else run(args)), flush=True)
+    if args.copy_calibration:
+        copy_calibration()
 
 
 if __name__ == "__main__":

@@ -396,8 +396,28 @@ void smooth(st_handle* h, int l, int prec, int trans, const void* b, void* x, in
     char* V = (char*)Vbuf;
     auto Vj = [&](int j) { return (void*)(V + (size_t)j * ld * vb); };
     const void* invd = level_invd(h, l, prec);
-    launch_init_state(s, ks, its, rtol, 1, nullptr);
     const int kd = l == 0 ? KC_DOT : KC_DOT_C, ka = l == 0 ? KC_AXPY : KC_AXPY_C;
+    int nchunk, gx, gy;
+    if (l > 0 && sm_fused_plan(L, &nchunk, &gx, &gy)) {
+        // small coarse level: two kernels per iteration
+        const int64_t stb = (int64_t)27 * (prec == 0 ? 8 : (L.sprec == 2 ? 2 : 4)) *
+                            (L.nx + 1) * (L.ny + 1) * L.nplanes;
+        int nbn = 0;
+        {
+            Timed t(h, zero_x0 ? kd : KC_STENCIL, zero_x0 ? n * (int64_t)(3 * vb) : n * (int64_t)(4 * vb) + stb);
+            launch_sm_init(s, L, prec, trans, b, x, zero_x0, invd, Vj(0), ks, h->partials, its, rtol, &nbn);
+        }
+        for (int j = 0; j < its; ++j) {
+            {
+                Timed t(h, KC_STENCIL, n * (int64_t)vb * (j + 4) + stb);
+                launch_sm_iteration(s, L, prec, trans, invd, V, j, ks, h->partials, &nbn);
+            }
+        }
+        Timed t(h, KC_UPDATE, n * (int64_t)vb * (its + 2));
+        launch_sm_update(s, L, prec, x, V, ks, h->partials, nbn, its, zero_x0);
+        return;
+    }
+    launch_init_state(s, ks, its, rtol, 1, nullptr);
     if (zero_x0) {
         Timed t(h, kd, n * (int64_t)(3 * vb));
         launch_scale_norm(s, n, prec, b, invd, Vj(0), h->partials, ks, FIN_INIT_SELF, its, rtol, 1);

@@ -40,6 +40,8 @@ struct KState {
     unsigned counter;           // arrival counter of the last-block reduction
     int scale_update;           // 1: y_d multiplied by scale_d (unnormalised basis)
     int pad[2];
+    double gcarry[2];           // fused smoother: unrotated g of the next column,
+                                // alternating by column parity
 };
 
 // Finalisation modes of the fused reduction kernels.
@@ -153,6 +155,17 @@ void launch_dot(hipStream_t s, long long n, const double* a, const double* b, do
 void launch_coarse_solve(hipStream_t s, const Level& L, int prec_io, int trans, const void* b,
                          void* x, double* V, double* work, int maxit, int restart, double rtol,
                          int zero_x0);
+
+// Fused smoother for small coarse levels (two kernels per GMRES iteration).
+bool sm_fused_plan(const Level& L, int* nchunk, int* gx, int* gy);
+size_t sm_partials_doubles();
+void launch_sm_init(hipStream_t s, const Level& L, int prec, int trans, const void* b,
+                    const void* x, int zero_x0, const void* invd, void* V0, KState* ks,
+                    double* part, int maxit, double rtol, int* nbn);
+void launch_sm_iteration(hipStream_t s, const Level& L, int prec, int trans, const void* invd,
+                         void* V, int j, KState* ks, double* part, int* nbn);
+void launch_sm_update(hipStream_t s, const Level& L, int prec, void* x, const void* V, KState* ks,
+                      const double* part, int nbn, int its, int zero_x0);
 
 // Exact coarsest-level solve by block-tridiagonal factorisation in time.
 constexpr int CD_MAX_PLANE = 2048;        // largest (nx + 1)(ny + 1) it is used for

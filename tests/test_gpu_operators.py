@@ -88,6 +88,44 @@ def test_galerkin_hierarchy(torch_cuda, nx, ny, nt, tv):
     p.close()
 
 
+def _bf16_round(a):
+    """FP64 -> FP32 -> BF16 (round to nearest even on the upper 16 bits), the
+    storage rounding of BF16 coarse stencils, back as FP64."""
+    u = np.asarray(a, dtype=np.float64).astype(np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def test_bf16_rounding_reference():
+    """The test's BF16 rounding: exact for BF16 values, ties to even."""
+    # BF16 keeps 8 significant bits: the spacing at 1 is 2^-7
+    vals = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -9,
+                     1.0 + 3 * 2.0 ** -9, -2.5, 0.0])
+    assert np.array_equal(_bf16_round(vals), [1.0, 1.0, 1.0 + 2.0 ** -6, 1.0, 1.0 + 2.0 ** -7,
+                                              -2.5, 0.0])
+
+
+@pytest.mark.parametrize("tv", [False, True])
+def test_bf16_stencil_applies(torch_cuda, tv):
+    """Levels >= 1 stored in BF16: the apply equals the oracle operator with
+    every coefficient rounded to BF16, to FP32 accuracy (1e-5), forward and
+    transposed; the level-0 apply is unchanged."""
+    import scipy.sparse as sp
+    c = Case(16, 16, 16, tv=tv, seed=17, max_coarse_nodes=200)
+    p = c.problem(max_coarse_nodes=200, precision="mixed", bf16_from_level=1)
+    A, masks, Pm = c.ops
+    rng = np.random.default_rng(6)
+    for l in range(1, len(c.levels)):
+        Al = sp.csr_matrix(A[l])
+        Ab = sp.csr_matrix((_bf16_round(Al.data), Al.indices, Al.indptr), shape=Al.shape)
+        x = rng.standard_normal(Al.shape[0])
+        for trans in (False, True):
+            y = p.debug_apply(l, _t(x).reshape(p.level_shape(l)), transpose=trans, mixed=True)
+            ref = (Ab.T if trans else Ab) @ x
+            assert rel(y.cpu().numpy(), ref) < 1e-5, (l, trans, rel(y.cpu().numpy(), ref))
+    p.close()
+
+
 @pytest.mark.parametrize("tv", [False, True])
 def test_mixed_precision_applies(torch_cuda, tv):
     """FP32 level operators (mixed precision) against the FP64 oracle: 1e-5."""

@@ -32,6 +32,19 @@ def test_small_workload_parity(torch_cuda, precision, coarse):
     p.close()
 
 
+@pytest.mark.parametrize("tv", [False, True])
+def test_bf16_coarse_levels_solve_parity(torch_cuda, tv):
+    """Mixed precision with BF16 coarse stencils: the FP64 outer FGMRES still
+    reaches the direct solution (rtol 1e-12 -> 1e-10)."""
+    c = Case(32, 32, 32, tv=tv, seed=23)
+    p = c.problem(precision="mixed", bf16_from_level=1, rtol=1e-12)
+    T, info = p.solve()
+    s = solve_direct(c.Jm, c.fm)
+    assert info.true_rel_res <= 1e-12
+    assert rel(T.cpu().numpy(), s) <= 1e-10, rel(T.cpu().numpy(), s)
+    p.close()
+
+
 @pytest.mark.parametrize("nx,ny,nt,tv", [(24, 16, 12, True), (20, 28, 16, False), (1, 1, 1, False),
                                          (2, 2, 1, True)])
 def test_ragged_and_tiny_grids(torch_cuda, nx, ny, nt, tv):
