@@ -73,13 +73,35 @@ void launch_simp(hipStream_t s, long long ne, const double* rho, const st_materi
 // and marches through a chunk of time levels.  Per level the tile's x window
 // (10 x 66 values, halo included) and per slab its coefficient window (9 x 65
 // elements) are loaded once, coalesced, into LDS; the loads of level s + 2 and
-// slab s + 1 are issued before the arithmetic of slab s, so they are in flight
-// while it runs (three x buffers, two coefficient buffers, one barrier per
-// level).  A thread reads its 3 x 4 stencil window of the two levels of a slab
+// slab s + 2 are issued before the arithmetic of slab s, and those of b and
+// invd of level s + 1 after its outputs, so every load has one iteration to
+// arrive (three x buffers, two coefficient buffers, one barrier per level).  A thread reads its 3 x 4 stencil window of the two levels of a slab
 // from LDS and produces 2 outputs of one column.  Workgroups are numbered so
 // that the eight XCDs (separate L2 caches) each get a contiguous range of
 // tiles: the halo rows a tile shares with its neighbours are then read from
 // the same L2.
+// Raw buffer access: base and size in a resource held in scalar registers,
+// 32-bit byte offsets per lane (no 64-bit address arithmetic per load).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, long long bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T> __device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <> __device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void buf_st(T v, __amdgpu_buffer_rsrc_t r, unsigned off);
+template <> __device__ __forceinline__ void buf_st<float>(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+template <> __device__ __forceinline__ void buf_st<double>(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+
 constexpr int FA_TX = 64, FA_RY = 2, FA_TY = 4 * FA_RY;
 
 template <typename TIN, typename TOUT, typename TC, bool TRANS, bool TCONST, bool CUNI>
@@ -115,64 +137,64 @@ __global__ __launch_bounds__(256) void k_fine_apply(
     const long long P = (long long)rowp * (ny + 1);
     const long long slab = (long long)nx * ny;
 
-    // Which window entries tid + 256 r this thread loads, and which of them
-    // are live (inside the grid and, with mask_in, not on a patch).
+    // Byte offsets of the window entries tid + 256 r this thread loads; dead
+    // entries (outside the grid or, with mask_in, on a patch) load offset 0
+    // and are replaced by zero.
     unsigned xlive = 0, elive = 0;
+    unsigned xo[LW], eo[LE];
 #pragma unroll
     for (int r = 0; r < LW; ++r) {
         const int e = tid + 256 * r;
         const int row = e / WX, col = e - (e / WX) * WX;
         const int gi = i0 - 1 + col, gj = jb - 1 + row;
-        if (e < NW && gi >= 0 && gi <= nx && gj >= 0 && gj <= ny &&
-            !(mask_in && on_patch(g.patches, nx, ny, gi, gj)))
-            xlive |= 1u << r;
+        const bool live = e < NW && gi >= 0 && gi <= nx && gj >= 0 && gj <= ny &&
+                          !(mask_in && on_patch(g.patches, nx, ny, gi, gj));
+        if (live) xlive |= 1u << r;
+        xo[r] = live ? (unsigned)(gj * rowp + gi) * (unsigned)sizeof(TIN) : 0u;
     }
 #pragma unroll
     for (int r = 0; r < LE; ++r) {
         const int e = tid + 256 * r;
         const int row = e / EX, col = e - (e / EX) * EX;
         const int ei = i0 - 1 + col, ej = jb - 1 + row;
-        if (e < NE && ei >= 0 && ei < nx && ej >= 0 && ej < ny) elive |= 1u << r;
+        const bool live = e < NE && ei >= 0 && ei < nx && ej >= 0 && ej < ny;
+        if (live) elive |= 1u << r;
+        eo[r] = live ? (unsigned)(ej * nx + ei) * (unsigned)sizeof(TC) : 0u;
     }
-    auto xoff = [&](int r) -> unsigned {
-        const int e = tid + 256 * r;
-        const int row = e / WX;
-        return (unsigned)((jb - 1 + row) * rowp + (i0 - 1 + e - row * WX));
-    };
-    auto eoff = [&](int r) -> unsigned {
-        const int e = tid + 256 * r;
-        const int row = e / EX;
-        return (unsigned)((jb - 1 + row) * nx + (i0 - 1 + e - row * EX));
-    };
-    TC px[LW], pk[LE], pc[CUNI ? 1 : LE];
+    TC pk[LE], pc[CUNI ? 1 : LE];
+    // The loaded values are only touched when they are written to LDS one
+    // iteration later (dead entries are zeroed there), so no wait for the
+    // loads is placed before the arithmetic in between.
+    TIN lx[LW];
     auto fetch_x = [&](int n) {
-        const TIN* xp = x + (long long)n * P;
-        const unsigned live = (mask_in && g.ic_dir && n == 0) ? 0u : xlive;
+        const auto rs = buf_rsrc(x + (long long)n * P, P * (long long)sizeof(TIN));
 #pragma unroll
-        for (int r = 0; r < LW; ++r) px[r] = ((live >> r) & 1u) ? (TC)xp[xoff(r)] : (TC)0;
+        for (int r = 0; r < LW; ++r) lx[r] = buf_ld<TIN>(rs, xo[r]);
     };
     auto put_x = [&](int n) {
         TC* d = xs[n % 3];
+        const unsigned live = (mask_in && g.ic_dir && n == 0) ? 0u : xlive;
 #pragma unroll
         for (int r = 0; r < LW; ++r)
-            if (tid + 256 * r < NW) d[tid + 256 * r] = px[r];
+            if (tid + 256 * r < NW) d[tid + 256 * r] = ((live >> r) & 1u) ? (TC)lx[r] : (TC)0;
     };
     auto fetch_c = [&](int s) {
-        const TC* kp = kc + (TCONST ? 0 : (long long)s * slab);
-        const TC* cp = cc + (TCONST ? 0 : (long long)s * slab);
+        const long long sb = TCONST ? 0 : (long long)s * slab;
+        const auto rk = buf_rsrc(kc + sb, slab * (long long)sizeof(TC));
+        const auto rc = buf_rsrc(cc + sb, CUNI ? 0 : slab * (long long)sizeof(TC));
 #pragma unroll
         for (int r = 0; r < LE; ++r) {
-            const bool v = (elive >> r) & 1u;
-            pk[r] = v ? kp[eoff(r)] : (TC)0;
-            if (!CUNI) pc[r] = v ? cp[eoff(r)] : (TC)0;
+            pk[r] = buf_ld<TC>(rk, eo[r]);
+            if (!CUNI) pc[r] = buf_ld<TC>(rc, eo[r]);
         }
     };
     auto put_c = [&](int s) {
 #pragma unroll
         for (int r = 0; r < LE; ++r)
             if (tid + 256 * r < NE) {
-                ks[s & 1][tid + 256 * r] = pk[r];
-                if (!CUNI) cs[s & 1][tid + 256 * r] = pc[r];
+                const bool v = (elive >> r) & 1u;
+                ks[s & 1][tid + 256 * r] = v ? pk[r] : (TC)0;
+                if (!CUNI) cs[s & 1][tid + 256 * r] = v ? pc[r] : (TC)0;
             }
     };
     // Capacity of the elements around this thread's nodes when it is uniform.
@@ -241,25 +263,42 @@ __global__ __launch_bounds__(256) void k_fine_apply(
             if (on_patch(g.patches, nx, ny, i, j)) opatch |= 1u << m;
         }
     }
-    const long long obase = (long long)(jb + ry0) * rowp + i;
+    // Byte offsets (within a level) of the own outputs; only owned rows are
+    // loaded or stored.
+    unsigned oo[RY];
+#pragma unroll
+    for (int m = 0; m < RY; ++m) oo[m] = ((own >> m) & 1u) ? (unsigned)((jb + ry0 + m) * rowp + i) : 0u;
+    // b, invd and (Dirichlet rows) x of the own outputs of one level, loaded
+    // an iteration before they are used.
+    // Every load is issued unconditionally (straight-line code lets the
+    // compiler wait for exactly the loads a use needs): an absent b or invd
+    // is a zero-size buffer, and a row that is not a Dirichlet row reads x at
+    // an offset past the end of the buffer -- both read as zero without a
+    // memory access.
     TOUT bv[RY], dv[RY];
+    TIN xd[RY];
+    constexpr unsigned OOB = 0x7FFFFFF0u;
     auto fetch_bd = [&](int n) {
+        const auto rb = buf_rsrc(b + (long long)n * P, b ? P * (long long)sizeof(TOUT) : 0);
+        const auto rd = buf_rsrc(invd + (long long)n * P, invd ? P * (long long)sizeof(TOUT) : 0);
+        const auto rx = buf_rsrc(x + (long long)n * P, P * (long long)sizeof(TIN));
+        const bool ic = dir_rows && g.ic_dir && n == 0;
 #pragma unroll
         for (int m = 0; m < RY; ++m) {
-            const long long idx = (long long)n * P + obase + (long long)m * rowp;
-            const bool o = (own >> m) & 1u;
-            bv[m] = (b && o) ? b[idx] : (TOUT)0;
-            dv[m] = (invd && o) ? invd[idx] : (TOUT)0;
+            bv[m] = buf_ld<TOUT>(rb, oo[m] * (unsigned)sizeof(TOUT));
+            dv[m] = buf_ld<TOUT>(rd, oo[m] * (unsigned)sizeof(TOUT));
+            const bool dr = ic || (dir_rows && ((opatch >> m) & 1u));
+            xd[m] = buf_ld<TIN>(rx, dr ? oo[m] * (unsigned)sizeof(TIN) : OOB);
         }
     };
     auto emit = [&](int n, int m, TC v) {
         if (!((own >> m) & 1u)) return;
-        const long long idx = (long long)n * P + obase + (long long)m * rowp;
         const bool dir = dir_rows && ((g.ic_dir && n == 0) || ((opatch >> m) & 1u));
-        TC val = dir ? (TC)x[idx] : v;
+        TC val = dir ? (TC)xd[m] : v;
         if (b) val = (TC)bv[m] - val;
         if (invd) val *= (TC)dv[m];
-        y[idx] = (TOUT)(val * sc);
+        buf_st<TOUT>((TOUT)(val * sc), buf_rsrc(y + (long long)n * P, P * (long long)sizeof(TOUT)),
+                     oo[m] * (unsigned)sizeof(TOUT));
     };
 
     const int sa = max(n0 - 1, 0);
@@ -272,6 +311,7 @@ __global__ __launch_bounds__(256) void k_fine_apply(
     put_c(sa);
     fetch_x(sa + 1);
     if (!TCONST && sa + 1 <= sb) fetch_c(sa + 1);
+    fetch_bd(sa);
     __syncthreads();
     read_c(sa);
 #pragma unroll
@@ -292,11 +332,10 @@ __global__ __launch_bounds__(256) void k_fine_apply(
         put_x(s + 1);
         if (!TCONST && s + 1 <= sb) put_c(s + 1);
         __syncthreads();
-        if (s + 1 <= sb) {
-            fetch_x(s + 2);
-            if (!TCONST && s + 2 <= sb) fetch_c(s + 2);
-        }
-        if (s >= n0) fetch_bd(s);
+        // (past the end of the chunk the last level / slab is loaded again:
+        // a cache hit that keeps the loop free of branches around loads)
+        fetch_x(min(s + 2, sb + 1));
+        if (!TCONST) fetch_c(min(s + 2, sb));
         if (!TCONST) read_x(s, ulo);
         read_x(s + 1, uhi);
 #pragma unroll
@@ -321,9 +360,11 @@ __global__ __launch_bounds__(256) void k_fine_apply(
             }
         }
         if (!TCONST && s + 1 <= sb) read_c(s + 1);
+        // b / invd of the next level: issued after this level's outputs, so
+        // waiting for them never waits for the x / coefficient loads above
+        fetch_bd(s + 1);
     }
     if (sb + 1 == nt && nt >= n0 && nt < n1) {
-        fetch_bd(nt);
 #pragma unroll
         for (int m = 0; m < RY; ++m) emit(nt, m, acc[m]);
     }
