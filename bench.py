@@ -24,6 +24,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+KERNEL_SRC = os.path.join(ROOT, "paper_2508_09589_amd", "csrc", "kernels_fine.hip")
+ROOF_KERNEL = {"mixed": "k_fine_apply<float, float, float, false",
+               "fp64": "k_fine_apply<double, double, double, false"}
+COPY_KIB = 1 << 20      # the calibration copy moves 1 GiB each way
 
 
 def log(msg):
@@ -45,6 +49,98 @@ def workload_problem(name, precision, time_kernels, bf16_from_level=0, max_it=10
     log(f"{name} {precision}: setup {time.perf_counter() - t0:.2f} s, {p.n_nodes} nodes, "
         f"levels {p.hierarchy()[0]}")
     return p, time.perf_counter() - t0, restart
+
+
+def _kernel_sha():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_path(workload, precision):
+    return os.path.join(ROOT, "profiles", f"fine_apply_{workload}_{precision}_hbm_traffic.md")
+
+
+def recorded_traffic(workload, precision):
+    """HBM bytes per launch of the roofline kernel from the committed counter
+    summary, or None when there is none or it was taken on other kernel source."""
+    path = traffic_path(workload, precision)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("source_sha256") != _kernel_sha():
+        return None
+    try:
+        return float(fields["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def summarize_counters(fetch_dir, write_dir, workload, precision, out):
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; each with
+    --copy-calibration) into the traffic summary of the roofline kernel:
+    counters averaged over its dispatches and scaled by what they read for the
+    1 GiB copies."""
+    import csv
+    import glob
+
+    def rows(d, counter):
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            raise SystemExit(f"no counter_collection.csv under {d}")
+        out_rows = []
+        for fn in files:
+            with open(fn) as f:
+                out_rows += [r for r in csv.DictReader(f) if r["Counter_Name"] == counter]
+        return out_rows
+
+    fr, wr = rows(fetch_dir, "FETCH_SIZE"), rows(write_dir, "WRITE_SIZE")
+    kern = ROOF_KERNEL[precision]
+    fk = [float(r["Counter_Value"]) for r in fr if kern in r["Kernel_Name"]]
+    wk = [float(r["Counter_Value"]) for r in wr if kern in r["Kernel_Name"]]
+    cw = [r for r in wr if "copy" in r["Kernel_Name"].lower()
+          and abs(float(r["Counter_Value"]) - COPY_KIB) <= 0.01 * COPY_KIB]
+    ids = {r["Dispatch_Id"] for r in cw}
+    cf = [float(r["Counter_Value"]) for r in fr if r["Dispatch_Id"] in ids and "copy" in r["Kernel_Name"].lower()]
+    if not fk or not wk or not cw or not cf:
+        raise SystemExit("counter runs lack the roofline kernel or the calibration copies")
+    ff = COPY_KIB / (sum(cf) / len(cf))
+    fw = COPY_KIB / (sum(float(r["Counter_Value"]) for r in cw) / len(cw))
+    fa, wa = sum(fk) / len(fk), sum(wk) / len(wk)
+    total = (fa * ff + wa * fw) * 1024.0
+    cmd = ("cd /tmp && export TMPDIR=/tmp && timeout -s KILL 200 rocprofv3 --pmc {c} "
+           "--kernel-include-regex 'k_fine_apply|copy' --output-format csv -d <dir> -o run -- "
+           f"python -u /root/repo/bench.py --workload {workload} --precision {precision} "
+           "--steps 1 --warmup 1 --no-cpu-baseline --copy-calibration")
+    text = f"""# HBM traffic of the fine-level apply, {workload} workload, {precision} precision
+
+Two rocprofv3 counter runs of the same command, one counter each:
+
+    {cmd.format(c="FETCH_SIZE")}
+    {cmd.format(c="WRITE_SIZE")}
+
+then `python bench.py --summarize-counters <fetch dir> <write dir> --workload {workload} --precision {precision}`.
+The counters are averaged over the kernel's dispatches and scaled by what they read for
+the 1 GiB device copies at the end of the run (1 GiB read and 1 GiB written each).
+
+kernel: {kern} ... ({len(fk)} / {len(wk)} dispatches)
+source_sha256: {_kernel_sha()}
+fetch_kib_per_dispatch: {fa:.1f}
+write_kib_per_dispatch: {wa:.1f}
+copy_fetch_kib: {sum(cf) / len(cf):.1f}
+copy_write_kib: {sum(float(r["Counter_Value"]) for r in cw) / len(cw):.1f}
+fetch_scale: {ff:.4f}
+write_scale: {fw:.4f}
+bytes_per_launch: {total:.0f}
+"""
+    with open(out, "w") as f:
+        f.write(text)
+    print(text)
 
 
 def cpu_baseline(name):
@@ -136,7 +232,8 @@ def run(args):
                    "bf16_from_level": args.bf16_from_level},
         "roofline": {"bound": "hbm", "kernel_class": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "launches": launches,
+                     "traffic": recorded_traffic(args.workload, args.precision),
+                     "launches": launches,
                      "avg_launch_ms": ms / launches if launches else None,
                      "bytes_per_launch": nbytes / launches if launches else None},
         "kernel_classes_warmup_ms": {c: round(v["ms"], 3) for c, v in kern.items()},
@@ -244,10 +341,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare-fp64", action="store_true")
     ap.add_argument("--max-it", type=int, default=400)
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the roofline kernel's HBM traffic summary from two rocprofv3 "
+                         "--pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
+    ap.add_argument("--out", default=None, help="output path of --summarize-counters")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy 1 GiB device buffers three times (a plain copy "
                          "kernel of known size, for scaling hardware byte counters)")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters[0], args.summarize_counters[1], args.workload,
+                           args.precision, args.out or traffic_path(args.workload, args.precision))
+        return
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU time-slab sharding is a design only)", file=sys.stderr)
