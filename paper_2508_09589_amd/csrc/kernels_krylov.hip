@@ -154,6 +154,100 @@ __device__ void kstate_finalize(KState* ks, int mode, int j, const double* sums,
     }
 }
 
+// The same finalisation done by a whole workgroup (every thread calls it):
+// the projections are scaled in parallel, and for the Givens update the
+// column and the earlier rotations are loaded into LDS in parallel before one
+// thread applies the rotations -- the serial part then touches LDS only, not a
+// chain of dependent global loads.  Arithmetic and its order are those of
+// kstate_finalize.
+__device__ void kstate_finalize_block(KState* ks, int mode, int j, const double* sums, int nd) {
+    __shared__ double fcol[KMAX + 1], fcs[KMAX], fsn[KMAX], fg[KMAX + 1], fsc[KMAX + 1];
+    __shared__ double fH[KMAX][KMAX + 1];
+    __shared__ double fy[KMAX];
+    __shared__ int fdone, fk;
+    const int t = threadIdx.x;
+    if (mode == FIN_PROJ1 || mode == FIN_PROJ2) {
+        if (t < nd) {
+            const double sd = ks->scale[t];
+            const double h = sums[t] * sd;
+            if (mode == FIN_PROJ1)
+                ks->hcol[t] = h;
+            else
+                ks->hcol[t] += h;
+            ks->coef[t] = h * sd;
+        }
+        return;
+    }
+    if (mode != FIN_GIVENS) {
+        if (t == 0) kstate_finalize(ks, mode, j, sums, nd);
+        return;
+    }
+    if (t <= j) fcol[t] = ks->hcol[t];
+    if (t < j) {
+        fcs[t] = ks->cs[t];
+        fsn[t] = ks->sn[t];
+    }
+    __syncthreads();
+    if (t == 0) {
+        const double hn = sqrt(sums[0]);
+        double hnorm2 = hn * hn;
+        for (int i = 0; i <= j; ++i) hnorm2 += fcol[i] * fcol[i];
+        for (int i = 0; i < j; ++i) {
+            const double a = fcol[i], b = fcol[i + 1];
+            fcol[i] = fcs[i] * a + fsn[i] * b;
+            fcol[i + 1] = -fsn[i] * a + fcs[i] * b;
+        }
+        const double hj = fcol[j];
+        const double r = hypot(hj, hn);
+        double c = 1.0, sn = 0.0;
+        if (r != 0.0) {
+            c = hj / r;
+            sn = hn / r;
+        }
+        fcol[j] = r;
+        const double gj = ks->g[j];
+        ks->cs[j] = c;
+        ks->sn[j] = sn;
+        ks->g[j + 1] = -sn * gj;
+        ks->g[j] = c * gj;
+        ks->scale[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+        ks->k = j + 1;
+        const double est = fabs(-sn * gj);
+        ks->est = est;
+        const bool bad = !isfinite(est) || !isfinite(hn);
+        const bool conv = est <= ks->rtol * ks->ref;
+        const bool brk = hn <= 1e-14 * sqrt(hnorm2);
+        ks->bad |= bad;
+        const int done = (conv || brk || bad || j + 1 >= ks->maxit) ? 1 : 0;
+        if (done) ks->done = 1;
+        fdone = done;
+        fk = j + 1;
+        fg[j] = c * gj;
+    }
+    __syncthreads();
+    if (t <= j) ks->H[t][j] = fcol[t];
+    if (!fdone) return;
+    // Least-squares solve R y = g (R upper triangular, k x k) in LDS.
+    const int k = fk;
+    for (int e = t; e < k * k; e += blockDim.x) {
+        const int i = e / k, c = e - i * k;
+        if (i <= c) fH[i][c] = c == j ? fcol[i] : ks->H[i][c];
+    }
+    if (t < j) fg[t] = ks->g[t];
+    if (t < k) fsc[t] = ks->scale[t];
+    __syncthreads();
+    if (t == 0) {
+        for (int i = k - 1; i >= 0; --i) {
+            double v = fg[i];
+            for (int c = i + 1; c < k; ++c) v -= fH[i][c] * fy[c];
+            const double d = fH[i][i];
+            fy[i] = d != 0.0 ? v / d : 0.0;
+        }
+    }
+    __syncthreads();
+    if (t < k) ks->y[t] = ks->scale_update ? fy[t] * fsc[t] : fy[t];
+}
+
 // Block reduction of MAXD accumulators into partials[blockIdx][.].  Grids of
 // at most FUSE_MAX blocks then finalise in the last block to arrive (arrival
 // counter); larger grids leave the partials to k_reduce_finalize, launched
@@ -201,14 +295,11 @@ __device__ void block_finish(double (&acc)[MAXD], int nd, double* __restrict__ p
         if (lane == 0) sums[d] = v;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        if (ks) {
-            kstate_finalize(ks, mode, j, sums, nd);
-        } else {
-            for (int d = 0; d < nd; ++d) out[d] = sums[d];
-        }
-        *counter = 0u;
-    }
+    if (threadIdx.x == 0) *counter = 0u;
+    if (ks)
+        kstate_finalize_block(ks, mode, j, sums, nd);
+    else if (threadIdx.x == 0)
+        for (int d = 0; d < nd; ++d) out[d] = sums[d];
 }
 
 // One block: sum the partials of a reduction grid (block order) and finalise.
@@ -226,12 +317,10 @@ __global__ __launch_bounds__(VEC_THREADS) void k_reduce_finalize(const double* _
         if (lane == 0) sums[d] = v;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        if (ks)
-            kstate_finalize(ks, mode, j, sums, nd);
-        else
-            for (int d = 0; d < nd; ++d) out[d] = sums[d];
-    }
+    if (ks)
+        kstate_finalize_block(ks, mode, j, sums, nd);
+    else if (threadIdx.x == 0)
+        for (int d = 0; d < nd; ++d) out[d] = sums[d];
 }
 
 template <int MAXD>
@@ -494,7 +583,7 @@ __global__ __launch_bounds__(VEC_THREADS) void k_maxpy4(long long n, TW* __restr
         acc[0] += (double)wo * (double)wo;
     }
     if (mode == FIN_NONE) return;   // uniform: no reduction wanted
-    block_finish<1>(acc, 1, partials, ks, FIN_GIVENS, j, nullptr);
+    block_finish<1>(acc, 1, partials, ks, mode, j, nullptr);
 }
 
 template <int MAXD>
@@ -554,7 +643,7 @@ static void maxpy_dispatch(hipStream_t s, long long n, int pw, int pv, void* w, 
         else
             hipLaunchKernelGGL((k_maxpy4<float, float, MAXD>), dim3(nb4), dim3(VEC_THREADS), 0, s,
                                n, (float*)w, (const float*)V, ldv, nd, partials, ks, mode, j);
-        if (mode != FIN_NONE) finish<1>(s, nb4, 1, partials, ks, FIN_GIVENS, j, nullptr);
+        if (mode != FIN_NONE) finish<1>(s, nb4, 1, partials, ks, mode, j, nullptr);
         return;
     }
     if (pw == 0 && pv == 0)

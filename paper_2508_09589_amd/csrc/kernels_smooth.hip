@@ -69,7 +69,8 @@ __device__ void sm_sum_partials(const double* __restrict__ part, int nb, int str
 
 // Givens update of Hessenberg column jm from ||w|| = sqrt(hn2), the
 // projections ks->hcol, the earlier rotations and the unrotated g_jm (one
-// thread).  col[] returns the rotated column; write: also store it in ks.
+// thread, inputs staged in LDS).  col[] returns the rotated column; write:
+// also store it in ks.
 // Nothing it reads is written by a kernel that runs it (the carry of g sits
 // in gcarry[jm & 1], the next one goes to the other slot), so every
 // workgroup of a kernel sees the same inputs.
@@ -80,16 +81,32 @@ struct SmGivens {
     int done;
 };
 
-__device__ SmGivens sm_givens(KState* ks, int jm, double hn2, bool write) {
-    SmGivens o;
-    double c[SMAX], s[SMAX];
-#pragma unroll
-    for (int i = 0; i < SMAX; ++i) {
-        o.col[i] = i <= jm ? ks->hcol[i] : 0.0;
-        c[i] = i < jm ? ks->cs[i] : 0.0;
-        s[i] = i < jm ? ks->sn[i] : 0.0;
+// What the Givens update of column jm reads from the KState, staged in LDS
+// by the whole workgroup (parallel loads) before one thread uses it.
+struct SmStage {
+    double col[SMAX], cs[SMAX], sn[SMAX];
+    double gj, rtol, ref;
+    int maxit;
+};
+
+__device__ void sm_stage_load(const KState* ks, int jm, SmStage& st) {
+    const int t = threadIdx.x;
+    if (t <= jm) st.col[t] = ks->hcol[t];
+    if (t < jm) {
+        st.cs[t] = ks->cs[t];
+        st.sn[t] = ks->sn[t];
     }
-    const double gj = ks->gcarry[jm & 1];
+    if (t == 64) st.gj = ks->gcarry[jm & 1];
+    if (t == 65) st.rtol = ks->rtol;
+    if (t == 66) st.ref = ks->ref;
+    if (t == 67) st.maxit = ks->maxit;
+}
+
+__device__ SmGivens sm_givens(const SmStage& st, KState* ks, int jm, double hn2, bool write) {
+    SmGivens o;
+#pragma unroll
+    for (int i = 0; i < SMAX; ++i) o.col[i] = i <= jm ? st.col[i] : 0.0;
+    const double gj = st.gj;
     const double hn = sqrt(hn2);
     double hnorm2 = hn * hn;
 #pragma unroll
@@ -99,8 +116,8 @@ __device__ SmGivens sm_givens(KState* ks, int jm, double hn2, bool write) {
     for (int i = 0; i < SMAX - 1; ++i)
         if (i < jm) {
             const double a = o.col[i], b = o.col[i + 1];
-            o.col[i] = c[i] * a + s[i] * b;
-            o.col[i + 1] = -s[i] * a + c[i] * b;
+            o.col[i] = st.cs[i] * a + st.sn[i] * b;
+            o.col[i + 1] = -st.sn[i] * a + st.cs[i] * b;
         }
     double hj = 0.0;
 #pragma unroll
@@ -120,10 +137,10 @@ __device__ SmGivens sm_givens(KState* ks, int jm, double hn2, bool write) {
     o.scale_next = hn > 0.0 ? 1.0 / hn : 0.0;
     const double est = fabs(o.g1);
     const bool bad = !isfinite(est) || !isfinite(hn);
-    const bool conv = est <= ks->rtol * ks->ref;
+    const bool conv = est <= st.rtol * st.ref;
     const bool brk = hn <= 1e-14 * sqrt(hnorm2);
     const int k = jm + 1;
-    o.done = (conv || brk || bad || k >= ks->maxit) ? 1 : 0;
+    o.done = (conv || brk || bad || k >= st.maxit) ? 1 : 0;
     if (write) {
 #pragma unroll
         for (int i = 0; i < SMAX; ++i)
@@ -185,6 +202,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_sm_apply(
     __shared__ double sums[1];
     __shared__ double sc_s;
     __shared__ int done_s;
+    __shared__ SmStage stg;
     TC sc = (TC)1;
     if (phase == 1) {
         // Workgroup 0 may set ks->done during this kernel; a workgroup that
@@ -192,6 +210,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_sm_apply(
         if (threadIdx.x == 0) done_s = ks->done;
         __syncthreads();
         if (done_s) return;
+        if (j > 0) sm_stage_load(ks, j - 1, stg);
         sm_sum_partials(npart, nbn, 1, 1, sums);
         if (threadIdx.x == 0) {
             const bool write = blockIdx.x == 0 && blockIdx.y == 0;
@@ -214,7 +233,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_sm_apply(
                 sc_s = s0;
                 done_s = done;
             } else {
-                const SmGivens o = sm_givens(ks, j - 1, sums[0], write);
+                const SmGivens o = sm_givens(stg, ks, j - 1, sums[0], write);
                 sc_s = o.scale_next;
                 done_s = o.done;
             }
@@ -339,6 +358,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_sm_update(long long n, T* __rest
     __shared__ double ys[SMAX];
     __shared__ double sums[1];
     __shared__ int k_s, done_s, kin_s;
+    __shared__ SmStage stg;
     if (threadIdx.x == 0) {
         done_s = ks->done;
         kin_s = ks->k;
@@ -354,13 +374,16 @@ __global__ __launch_bounds__(SM_THREADS) void k_sm_update(long long n, T* __rest
         gs[threadIdx.x] = (int)threadIdx.x <= k0 ? ks->g[threadIdx.x] : 0.0;
         scl[threadIdx.x] = (int)threadIdx.x <= k0 ? ks->scale[threadIdx.x] : 0.0;
     }
-    if (!done0) sm_sum_partials(npart, nbn, 1, 1, sums);
+    if (!done0) {
+        sm_stage_load(ks, its - 1, stg);
+        sm_sum_partials(npart, nbn, 1, 1, sums);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         int k = k0;
         if (!done0) {
             // the KState is not written here: other workgroups still read it
-            const SmGivens o = sm_givens(ks, its - 1, sums[0], false);
+            const SmGivens o = sm_givens(stg, ks, its - 1, sums[0], false);
 #pragma unroll
             for (int i = 0; i < SMAX; ++i)
                 if (i < its) Hs[i][its - 1] = o.col[i];

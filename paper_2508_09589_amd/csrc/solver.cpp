@@ -735,6 +735,9 @@ st_status fgmres(st_handle* h, const double* f, const double* fnorm_dev, double*
             {
                 // CGS2: subtract the first projections, project again, subtract
                 // the corrections and take the norm (three streaming passes).
+                // (A second pass only where the DGKS test asks for one saved
+                // nothing: with a good preconditioner the first pass cancels
+                // most of w at every iteration, so the test always asks.)
                 Timed t(h, KC_OUTER, n * 8 * (j + 3));
                 launch_maxpy(s, n, 0, 0, Vj(j + 1), h->V, ld, j + 1, h->partials, ks, FIN_NONE, j, KMAX);
             }
