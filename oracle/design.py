@@ -180,3 +180,109 @@ def central_difference(grid, mat, rho, patches, e, h=1e-6, q0=1.0, r_elems=None)
     sm = solve_direct(Jn, fmask)
     ds = solve_direct(Jp, -(keep * (dJ @ (keep * sm))))
     return float(f @ ds) / (2 * h)
+
+
+# ---------------------------------------------------------------------------
+# The design chain of §3.3.1-§3.3.3 beyond the differentiation workload:
+# Heaviside projection of the filtered field, the p-norm objective of the
+# element-averaged temperature with its adjoint right-hand side, and the
+# volume constraint.
+
+def heaviside(x, beta, eta):
+    """Projection of §3.3.2 (Wang et al.): (tanh(b e) + tanh(b (x - e))) /
+    (tanh(b e) + tanh(b (1 - e)))."""
+    x = np.asarray(x, dtype=np.float64)
+    den = np.tanh(beta * eta) + np.tanh(beta * (1.0 - eta))
+    return (np.tanh(beta * eta) + np.tanh(beta * (x - eta))) / den
+
+
+def heaviside_deriv(x, beta, eta):
+    """d heaviside / dx = beta (1 - tanh^2(beta (x - eta))) / den."""
+    x = np.asarray(x, dtype=np.float64)
+    den = np.tanh(beta * eta) + np.tanh(beta * (1.0 - eta))
+    t = np.tanh(beta * (x - eta))
+    return beta * (1.0 - t * t) / den
+
+
+def element_average(grid, s):
+    """T_avg,e = (1/8) sum of the element's 8 nodal values (§3.3.1)."""
+    conn = grid.connectivity()
+    return np.asarray(s, dtype=np.float64).ravel()[conn].mean(axis=1)
+
+
+def pnorm(grid, s, P):
+    """phi = (sum_e T_avg,e^P)^(1/P) and its gradient with respect to the
+    nodal state, assembled from dphi/ds_e = theta^((1-P)/P) T_avg,e^(P-1) / 8
+    per element node (§3.3.3), theta = sum_e T_avg,e^P."""
+    Tavg = element_average(grid, s)
+    theta = float(np.sum(Tavg ** P))
+    phi = theta ** (1.0 / P)
+    w = theta ** ((1.0 - P) / P) * Tavg ** (P - 1.0) / 8.0
+    conn = grid.connectivity()
+    g = np.zeros(grid.n_nodes)
+    np.add.at(g, conn.ravel(), np.repeat(w, 8))
+    return phi, g
+
+
+def volume(grid, rho_phys, vf):
+    """chi = sum_e rho_e v_e / (vf |Pi|) - 1 over all space-time elements (a
+    time-constant field counts in every slab), and d chi / d rho_e (per
+    space-time element) = v_e / (vf |Pi|)."""
+    from .assemble import broadcast_elements
+    r = broadcast_elements(grid, rho_phys)
+    ve = grid.dx * grid.dx * grid.dt
+    vol = ve * grid.n_elems
+    chi = float(np.sum(r) * ve / (vf * vol) - 1.0)
+    return chi, np.full(grid.shape_elems, ve / (vf * vol))
+
+
+def physical_design(grid, rho, r_elems=None, beta=None, eta=0.5):
+    """gamma -> filtered -> projected (each step optional); returns the
+    physical field and the filtered field."""
+    rho = np.asarray(rho, dtype=np.float64)
+    if r_elems is not None:
+        rt = filter_apply(rho, grid.dx, grid.dt, r_elems * grid.dx, r_elems * grid.dt)
+    else:
+        rt = rho
+    rp = heaviside(rt, beta, eta) if beta else rt
+    return rp, rt
+
+
+def chain_to_design(grid, g_phys_elem, rho_shape, rt, r_elems=None, beta=None, eta=0.5):
+    """Chain rule from a per-space-time-element sensitivity with respect to
+    the physical field back to the design variables: extrusion sum, the
+    projection derivative, the (symmetric) filter."""
+    g = reduce_to_design(g_phys_elem, rho_shape)
+    if beta:
+        g = g * heaviside_deriv(rt, beta, eta)
+    if r_elems is not None:
+        g = filter_apply(g, grid.dx, grid.dt, r_elems * grid.dx, r_elems * grid.dt)
+    return g
+
+
+def pnorm_chain(grid, mat, rho, patches, P=20.0, q0=1.0, r_elems=None, beta=None, eta=0.5,
+                vf=0.3, with_grad=True):
+    """phi(gamma) and chi(gamma) with gradients: filter -> projection -> SIMP
+    -> state -> p-norm -> adjoint with J^T lambda = dphi/ds (lambda = 0 on the
+    Dirichlet set) -> element sensitivities -> chain rule (§3.3)."""
+    from .assemble import simp, assemble_matrix, load_vector, apply_dirichlet
+    from .grid import dirichlet_mask
+    from .solve import solve_direct, solve_adjoint_direct
+    rho = np.asarray(rho, dtype=np.float64)
+    rp, rt = physical_design(grid, rho, r_elems, beta, eta)
+    k, C, dk, dC = simp(rp, mat)
+    mask = dirichlet_mask(grid, patches)
+    f = load_vector(grid, q0)
+    Jm, fm = apply_dirichlet(assemble_matrix(grid, k, C), f, mask)
+    s = solve_direct(Jm, fm)
+    phi, dphids = pnorm(grid, s, P)
+    chi, dchi = volume(grid, rp, vf)
+    out = dict(phi=phi, chi=chi, s=s, rho_phys=rp, dphids=dphids)
+    if not with_grad:
+        return out
+    lam = solve_adjoint_direct(Jm, dphids, mask)
+    ge = element_sensitivity(grid, s, lam, dk, dC)
+    out.update(lam=lam,
+               grad=chain_to_design(grid, ge, rho.shape, rt, r_elems, beta, eta),
+               dchi=chain_to_design(grid, dchi, rho.shape, rt, r_elems, beta, eta))
+    return out
