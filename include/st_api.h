@@ -101,6 +101,9 @@ typedef struct {
     double filter_r;          /* PDE filter radius in elements (r_x = r dx,
                                  r_t = r dt); 0 = no filter                      */
     int32_t flags;            /* ST_FLAG_*                                      */
+    double proj_beta;         /* Heaviside projection of the filtered design
+                                 (§3.3.2): sharpness beta; 0 = no projection    */
+    double proj_eta;          /* projection threshold eta, default 0.5          */
 } st_opts;
 
 typedef struct {
@@ -170,8 +173,9 @@ st_status st_solve(st_handle* h, double* T_dev, st_info* info);
 st_status st_adjoint_solve(st_handle* h, const double* g_dev, double* lambda_dev, st_info* info);
 
 /* Density sensitivities (§3.3.3): g_e = -lambda_e^T (k'_e A + C'_e B) s_e per
- * element, summed over slabs for a time-constant design (§3.4.1), then sent
- * through the filter (F^T = F, §3.3.2) when the problem has one.
+ * element, summed over slabs for a time-constant design (§3.4.1), multiplied
+ * by the projection's derivative at the filtered design when the problem
+ * projects, then sent through the filter (F^T = F, §3.3.2) when it filters.
  * dJdrho_dev has the design's layout. */
 st_status st_sensitivity(st_handle* h, const double* T_dev, const double* lambda_dev,
                          double* dJdrho_dev);
@@ -181,6 +185,22 @@ st_status st_objective(st_handle* h, const double* T_dev, double* J_host);
 
 /* Copy the unmasked consistent load f (= dJ/dT of st_objective) to f_dev. */
 st_status st_load_vector(st_handle* h, double* f_dev);
+
+/* p-norm objective of §3.3.1: phi = (sum_e T_avg,e^P)^(1/P) over all
+ * space-time elements, T_avg,e the mean of the element's 8 nodal values of
+ * T_dev (the full state).  dphi_dT_dev (nullable, node layout) receives the
+ * assembled dphi/dT (§3.3.3: theta^((1-P)/P) T_avg,e^(P-1) / 8 to each node
+ * of e), the right-hand side of the p-norm adjoint solve.  P > 0; a
+ * non-integer P needs T_avg >= 0. */
+st_status st_pnorm(st_handle* h, const double* T_dev, double P, double* phi_host,
+                   double* dphi_dT_dev);
+
+/* Volume constraint of §3.3.1 on the physical design (filtered, projected,
+ * extruded over time): chi = sum_e rho_e v_e / (vf |Pi|) - 1.  dchi_drho_dev
+ * (nullable, design layout) receives dchi/d(design), the constant
+ * v_e / (vf |Pi|) sent through the same chain rule as st_sensitivity.
+ * 0 < vf. */
+st_status st_volume(st_handle* h, double vf, double* chi_host, double* dchi_drho_dev);
 
 /* Apply the density filter F (§3.3.2) to an element field of the design's
  * layout.  ST_ERR_STATE when the problem has no filter. */

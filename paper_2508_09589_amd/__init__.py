@@ -6,7 +6,7 @@ Importing the package loads nothing; the HIP library is loaded (and required)
 when a Problem is created.
 """
 
-__all__ = ["Problem", "STSolve", "STObjective", "info_dict"]
+__all__ = ["Problem", "STSolve", "STObjective", "STPNorm", "info_dict"]
 
 
 def __getattr__(name):

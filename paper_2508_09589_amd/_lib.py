@@ -39,7 +39,8 @@ class st_opts(C.Structure):
                 ("smooth_rtol", C.c_double), ("coarse_max_it", C.c_int32),
                 ("coarse_rtol", C.c_double), ("coarse_restart", C.c_int32),
                 ("lambda_crit", C.c_double), ("max_levels", C.c_int32),
-                ("max_coarse_nodes", C.c_int64), ("filter_r", C.c_double), ("flags", C.c_int32)]
+                ("max_coarse_nodes", C.c_int64), ("filter_r", C.c_double), ("flags", C.c_int32),
+                ("proj_beta", C.c_double), ("proj_eta", C.c_double)]
 
 
 class st_info(C.Structure):
@@ -69,6 +70,8 @@ _SIGS = {
     "st_sensitivity": (C.c_int, [_P, _P, _P, _P]),
     "st_objective": (C.c_int, [_P, _P, C.POINTER(C.c_double)]),
     "st_load_vector": (C.c_int, [_P, _P]),
+    "st_pnorm": (C.c_int, [_P, _P, C.c_double, C.POINTER(C.c_double), _P]),
+    "st_volume": (C.c_int, [_P, C.c_double, C.POINTER(C.c_double), _P]),
     "st_filter": (C.c_int, [_P, _P, _P]),
     "st_hierarchy": (C.c_int, [_P, C.POINTER(st_info)]),
     "st_set_flags": (C.c_int, [_P, C.c_int32]),

@@ -46,7 +46,8 @@ struct st_handle {
     long long nde = 0;         // design entries
     // fine level data
     double* rho = nullptr;     // design copy
-    double* rho_phys = nullptr;
+    double* rho_phys = nullptr;  // physical design (filtered, projected)
+    double* rho_filt = nullptr;  // filtered design (== rho without a filter)
     double *k64 = nullptr, *c64 = nullptr, *dk = nullptr, *dc = nullptr;
     float *k32 = nullptr, *c32 = nullptr;
     double *f_full = nullptr, *f_m = nullptr;
@@ -169,7 +170,8 @@ size_t carve(st_handle* h, char* base) {
     const int si = o.smooth_its;
     const bool mixed = o.precision == ST_MIXED;
     h->rho = c.take<double>(h->nde);
-    h->rho_phys = o.filter_r > 0 ? c.take<double>(h->nde) : h->rho;
+    h->rho_filt = o.filter_r > 0 ? c.take<double>(h->nde) : h->rho;
+    h->rho_phys = o.proj_beta > 0 ? c.take<double>(h->nde) : h->rho_filt;
     h->k64 = c.take<double>(h->ne);
     h->dk = c.take<double>(h->ne);
     if (!h->cuniform) {
@@ -186,7 +188,7 @@ size_t carve(st_handle* h, char* base) {
     h->ic = c.take<double>((size_t)(h->grid.nx + 1) * (h->grid.ny + 1));
     h->src = c.take<double>(h->n0);
     h->adj_rhs = c.take<double>(h->n0);
-    h->gtmp = o.filter_r > 0 ? c.take<double>(h->nde) : nullptr;
+    h->gtmp = (o.filter_r > 0 || o.proj_beta > 0) ? c.take<double>(h->nde) : nullptr;
     h->ld0 = (h->n0 + 63) / 64 * 64;
     h->x64 = c.take<double>(h->n0);
     h->V = c.take<double>((size_t)(m + 1) * h->ld0);
@@ -260,6 +262,7 @@ st_status validate(const st_grid* g, const st_material* m, const st_opts* o) {
     if (o->coarse_max_it < 1 || o->max_it < 1) return ST_ERR_ARG;
     if (!(o->rtol >= 0) || !(o->smooth_rtol >= 0) || !(o->coarse_rtol >= 0)) return ST_ERR_ARG;
     if (!(o->filter_r >= 0)) return ST_ERR_ARG;
+    if (!(o->proj_beta >= 0) || !(o->proj_eta > 0 && o->proj_eta < 1)) return ST_ERR_ARG;
     return ST_OK;
 }
 
@@ -597,9 +600,12 @@ st_status build_operators(st_handle* h) {
     const st_grid& g = h->grid;
     st_status rc;
     if (h->opts.filter_r > 0) {
-        rc = filter_apply(h, h->rho, h->rho_phys);
+        rc = filter_apply(h, h->rho, h->rho_filt);
         if (rc != ST_OK) return rc;
     }
+    if (h->opts.proj_beta > 0)
+        launch_heaviside(s, h->nde, h->rho_filt, h->opts.proj_beta, h->opts.proj_eta, h->rho_phys,
+                         nullptr);
     launch_simp(s, h->ne, h->rho_phys, &h->mat, h->k64, h->c64, h->dk, h->dc, h->k32, h->c32,
                 h->cuniform);
     Coef cf{h->k64, h->c64, h->k32, h->c32};
@@ -829,6 +835,8 @@ void st_opts_default(st_opts* o) {
     o->max_coarse_nodes = 4096;
     o->filter_r = 0.0;
     o->flags = 0;
+    o->proj_beta = 0.0;
+    o->proj_eta = 0.5;
 }
 
 const char* st_status_string(st_status s) {
@@ -1014,16 +1022,31 @@ st_status st_adjoint_solve(st_handle* h, const double* g_dev, double* lambda_dev
     return rc;
 }
 
+// Chain rule from a design-layout sensitivity with respect to the physical
+// design (in src) back to the design variables (out): projection derivative
+// at the filtered design, then the filter.  src may be h->gtmp; out must not.
+st_status chain_to_design(st_handle* h, double* src, double* out) {
+    hipStream_t s = h->stream;
+    if (h->opts.proj_beta > 0)
+        launch_heaviside_chain(s, h->nde, h->rho_filt, h->opts.proj_beta, h->opts.proj_eta, src,
+                               h->opts.filter_r > 0 ? src : out);
+    if (h->opts.filter_r > 0) return filter_apply(h, src, out);
+    if (!(h->opts.proj_beta > 0) && src != out)
+        HIPCHK(hipMemcpyAsync(out, src, sizeof(double) * h->nde, hipMemcpyDeviceToDevice, s));
+    return ST_OK;
+}
+
 st_status st_sensitivity(st_handle* h, const double* T_dev, const double* lambda_dev,
                          double* dJdrho_dev) {
     if (!h || !T_dev || !lambda_dev || !dJdrho_dev) return ST_ERR_ARG;
     if (!h->setup_done) return ST_ERR_STATE;
     hipStream_t s = h->stream;
-    double* dst = h->opts.filter_r > 0 ? h->gtmp : dJdrho_dev;
+    const bool chain = h->opts.filter_r > 0 || h->opts.proj_beta > 0;
+    double* dst = chain ? h->gtmp : dJdrho_dev;
     launch_sensitivity(s, h->fg, h->grid.dx, h->grid.dt, T_dev, lambda_dev, h->dk, h->dc, dst,
                        h->rho_tv ? 0 : 1);
-    if (h->opts.filter_r > 0) {
-        st_status rc = filter_apply(h, h->gtmp, dJdrho_dev);
+    if (chain) {
+        st_status rc = chain_to_design(h, h->gtmp, dJdrho_dev);
         if (rc != ST_OK) return rc;
     }
     HIPCHK(hipStreamSynchronize(s));
@@ -1038,6 +1061,51 @@ st_status st_objective(st_handle* h, const double* T_dev, double* J_host) {
     HIPCHK(hipMemcpyAsync(h->hbuf, h->dscal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     *J_host = h->hbuf[0];
+    return ST_OK;
+}
+
+st_status st_pnorm(st_handle* h, const double* T_dev, double P, double* phi_host,
+                   double* dphi_dT_dev) {
+    if (!h || !T_dev || !phi_host || !(P > 0)) return ST_ERR_ARG;
+    hipStream_t s = h->stream;
+    // theta = sum_e T_avg^P into dscal[3]; the gradient kernel reads it there
+    launch_pnorm_theta(s, h->fg, T_dev, P, h->partials, h->dscal + 3);
+    if (dphi_dT_dev) launch_pnorm_grad(s, h->fg, T_dev, P, h->dscal + 3, dphi_dT_dev);
+    HIPCHK(hipMemcpyAsync(h->hbuf, h->dscal + 3, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    const double theta = h->hbuf[0];
+    if (!(theta == theta)) return ST_ERR_BREAKDOWN;
+    *phi_host = std::pow(theta, 1.0 / P);
+    return ST_OK;
+}
+
+st_status st_volume(st_handle* h, double vf, double* chi_host, double* dchi_drho_dev) {
+    if (!h || !chi_host || !(vf > 0)) return ST_ERR_ARG;
+    if (!h->setup_done) return ST_ERR_STATE;
+    hipStream_t s = h->stream;
+    // every design entry stands for (nt or 1) equal space-time elements of
+    // volume v_e; |Pi| = N_e v_e
+    const double ne = (double)h->grid.nx * h->grid.ny * h->grid.nt;
+    const double mult = h->rho_tv ? 1.0 : (double)h->grid.nt;
+    const double w = mult / (vf * ne);
+    // sum of the physical design: a dot product with ones held in the FGMRES
+    // basis buffer (free outside solves; it holds >= nodes > design entries)
+    launch_fill(s, h->nde, 0, h->V, 1.0);
+    launch_dot(s, h->nde, h->rho_phys, h->V, h->partials, h->dscal + 4);
+    if (dchi_drho_dev) {
+        if (h->gtmp) {
+            launch_fill(s, h->nde, 0, h->gtmp, w);
+            st_status rc = chain_to_design(h, h->gtmp, dchi_drho_dev);
+            if (rc != ST_OK) return rc;
+        } else {
+            launch_fill(s, h->nde, 0, dchi_drho_dev, w);
+        }
+    }
+    HIPCHK(hipMemcpyAsync(h->hbuf, h->dscal + 4, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    *chi_host = h->hbuf[0] * w - 1.0;
     return ST_OK;
 }
 

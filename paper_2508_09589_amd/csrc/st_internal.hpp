@@ -196,6 +196,14 @@ void launch_sensitivity(hipStream_t s, const FineGeom& g, double dx, double dt, 
                         const double* lam, const double* dk, const double* dc, double* out,
                         int sum_slabs);
 void launch_ic_lift_vector(hipStream_t s, const FineGeom& g, const double* ic, double* gvec);
+void launch_heaviside(hipStream_t s, long long n, const double* x, double beta, double eta,
+                      double* out, double* dout);
+void launch_heaviside_chain(hipStream_t s, long long n, const double* x, double beta, double eta,
+                            const double* g_in, double* g_out);
+void launch_pnorm_theta(hipStream_t s, const FineGeom& g, const double* T, double Pw,
+                        double* partials, double* theta);
+void launch_pnorm_grad(hipStream_t s, const FineGeom& g, const double* T, double Pw,
+                       const double* theta, double* out);
 void launch_cg_step(hipStream_t s, int step, long long n, double* x, double* r, double* z,
                     double* p, const double* q, const double* invd, double* partials,
                     double* scal, const int* skip);

@@ -123,6 +123,24 @@ class Problem:
         L.check("st_objective", self.lib.st_objective(self.h, _ptr(T), C.byref(J)))
         return J.value
 
+    def pnorm(self, T, P=20.0, grad=True):
+        """p-norm objective (§3.3.1) of the state T: (phi, dphi/dT or None)."""
+        T = _dev_f64(T, self.device)
+        phi = C.c_double(0.0)
+        g = self._new_nodal() if grad else None
+        L.check("st_pnorm", self.lib.st_pnorm(self.h, _ptr(T), float(P), C.byref(phi),
+                                              _ptr(g) if grad else None))
+        return phi.value, g
+
+    def volume(self, vf, grad=True):
+        """Volume constraint (§3.3.1) of the physical design: (chi, dchi/drho or
+        None), the gradient in the design's layout."""
+        chi = C.c_double(0.0)
+        g = torch.empty(self.design_shape, dtype=torch.float64, device=self.device) if grad else None
+        L.check("st_volume", self.lib.st_volume(self.h, float(vf), C.byref(chi),
+                                                _ptr(g) if grad else None))
+        return chi.value, g
+
     def load_vector(self):
         f = self._new_nodal()
         L.check("st_load_vector", self.lib.st_load_vector(self.h, _ptr(f)))
@@ -243,6 +261,30 @@ class STSolve(torch.autograd.Function):
         lam, _ = problem.adjoint(gT.contiguous())
         grad = problem.sensitivity(T, lam)
         return grad.reshape(problem.design_shape), None
+
+
+class STPNorm(torch.autograd.Function):
+    """phi = STPNorm.apply(rho, problem, P): design -> (filter, projection,
+    SIMP, Galerkin rebuild) -> state -> p-norm of the element-averaged
+    temperature (§3.3.1).  Backward: one adjoint solve with the right-hand
+    side dphi/dT, the sensitivity kernel and the chain rule (§3.3.3)."""
+
+    @staticmethod
+    def forward(ctx, rho, problem, P=20.0):
+        problem.update_density(rho.detach())
+        T, _ = problem.solve()
+        phi, dphi = problem.pnorm(T, P)
+        ctx.problem = problem
+        ctx.save_for_backward(T, dphi)
+        return torch.tensor(phi, dtype=torch.float64, device=rho.device)
+
+    @staticmethod
+    def backward(ctx, gphi):
+        problem = ctx.problem
+        T, dphi = ctx.saved_tensors
+        lam, _ = problem.adjoint(dphi)
+        grad = problem.sensitivity(T, lam)
+        return gphi * grad.reshape(problem.design_shape), None, None
 
 
 class STObjective(torch.autograd.Function):
