@@ -5,6 +5,9 @@ once; on each level the anisotropy lambda = D_eff * dt / dx^2 decides: below
 lambda_crit the next level halves the time resolution, otherwise it halves both
 spatial resolutions (§3.2.1).
 
+Full space-time coarsening (the comparison the paper makes in §4.2.2 and
+Figure 3c) halves all three resolutions on every level.
+
 Readings where the paper is silent:
   * the comparison is strict ("<"), so lambda == lambda_crit coarsens in space;
   * when the chosen direction cannot be halved (odd or unit element count) the
@@ -14,7 +17,7 @@ Readings where the paper is silent:
 """
 import math
 
-SPACE, TIME = "space", "time"
+SPACE, TIME, FULL = "space", "time", "full"
 
 
 def d_eff(k_con, k_ins, c_con, c_ins):
@@ -30,10 +33,13 @@ def _can_halve_time(nt):
 
 
 def build_hierarchy(nx, ny, nt, dx, dt, k_con, k_ins, c_con, c_ins,
-                    lambda_crit=0.5, n_levels=None, max_coarse_nodes=4096, max_levels=32):
+                    lambda_crit=0.5, n_levels=None, max_coarse_nodes=4096, max_levels=32,
+                    full=False):
     """Return a list of dicts, one per level (finest first), with keys
     nx, ny, nt, dx, dt, lam (anisotropy of that level) and how (how the level
-    was made from the one above it: None, 'space' or 'time')."""
+    was made from the one above it: None, 'space', 'time' or 'full').
+    full=True: full space-time coarsening while all three counts can be
+    halved (reading: the hierarchy stops when one of them cannot)."""
     D = d_eff(k_con, k_ins, c_con, c_ins)
     levels = [dict(nx=nx, ny=ny, nt=nt, dx=dx, dt=dt, how=None)]
     limit = n_levels if n_levels is not None else max_levels
@@ -42,6 +48,12 @@ def build_hierarchy(nx, ny, nt, dx, dt, k_con, k_ins, c_con, c_ins,
         L["lam"] = D * L["dt"] / L["dx"] ** 2
         if n_levels is None and (L["nx"] + 1) * (L["ny"] + 1) * (L["nt"] + 1) <= max_coarse_nodes:
             break
+        if full:
+            if not (_can_halve_space(L["nx"], L["ny"]) and _can_halve_time(L["nt"])):
+                break
+            levels.append(dict(nx=L["nx"] // 2, ny=L["ny"] // 2, nt=L["nt"] // 2,
+                               dx=2 * L["dx"], dt=2 * L["dt"], how=FULL))
+            continue
         want = TIME if L["lam"] < lambda_crit else SPACE
         order = (want, SPACE if want == TIME else TIME)
         how = None

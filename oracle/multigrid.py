@@ -13,7 +13,7 @@ Readings (the paper is silent on Dirichlet nodes inside the hierarchy):
 import numpy as np
 import scipy.sparse as sp
 
-from .hierarchy import SPACE, TIME
+from .hierarchy import SPACE, TIME, FULL
 
 
 def interp_1d(n_coarse_elems):
@@ -39,6 +39,9 @@ def prolongation(fine, how):
         return sp.kron(It, sp.kron(interp_1d(fine["ny"] // 2), interp_1d(fine["nx"] // 2))).tocsr()
     if how == TIME:
         return sp.kron(interp_1d(fine["nt"] // 2), sp.kron(Iy, Ix)).tocsr()
+    if how == FULL:
+        return sp.kron(interp_1d(fine["nt"] // 2),
+                       sp.kron(interp_1d(fine["ny"] // 2), interp_1d(fine["nx"] // 2))).tocsr()
     raise ValueError(how)
 
 

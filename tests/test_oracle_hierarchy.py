@@ -67,3 +67,33 @@ def test_printed_dof_counts():
             continue
         nx, ny, nt, dofs = (int(v) for v in line.split()[:4])
         assert (nx + 1) * (ny + 1) * (nt + 1) == dofs
+
+
+def test_full_coarsening_hierarchy_and_galerkin():
+    """Full space-time coarsening halves all three counts per level; its
+    masked P is the Kronecker product of the three 1-D interpolations, and
+    the Galerkin operators stay 27-point (coarse stencil radius 1)."""
+    import numpy as np
+    from oracle.assemble import assemble_matrix, apply_dirichlet, load_vector
+    from oracle.grid import Grid, dirichlet_mask
+    from oracle.multigrid import build_operators
+    lv = build_hierarchy(16, 16, 16, 1 / 16, 1 / 16, 1.0, 1e-3, 1.0, 1.0, full=True,
+                         max_coarse_nodes=200)
+    assert [(l["nx"], l["ny"], l["nt"], l["how"]) for l in lv] == [
+        (16, 16, 16, None), (8, 8, 8, "full"), (4, 4, 4, "full")]
+    g = Grid(16, 16, 16, 1 / 16, 1 / 16)
+    rng = np.random.default_rng(0)
+    k = rng.uniform(0.1, 1.0, (16, 16, 16))
+    mask = dirichlet_mask(g, [(0, 0.5, 0.2)])
+    Jm, _ = apply_dirichlet(assemble_matrix(g, k, np.ones_like(k)), load_vector(g), mask)
+    A, masks, Pm = build_operators(lv, Jm, mask)
+    for l in (1, 2):
+        L = lv[l]
+        Ac = A[l].tocoo()
+        shp = (L["nt"] + 1, L["ny"] + 1, L["nx"] + 1)
+        rn, rj, ri = np.unravel_index(Ac.row, shp)
+        cn, cj, ci = np.unravel_index(Ac.col, shp)
+        assert max(abs(rn - cn).max(), abs(rj - cj).max(), abs(ri - ci).max()) <= 1
+    # an odd count stops full coarsening
+    lv = build_hierarchy(12, 12, 6, 1 / 12, 1 / 6, 1.0, 1e-3, 1.0, 1.0, full=True, max_coarse_nodes=10)
+    assert [(l["nx"], l["nt"]) for l in lv] == [(12, 6), (6, 3)]
