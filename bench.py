@@ -370,6 +370,73 @@ def run_design(args):
             "dofs_per_s_both_solves": 2 * nodes * args.steps / elapsed}
 
 
+def run_coarsening(args):
+    """Semi- against full space-time coarsening on the paper's examples (§2.3)
+    at a reduced grid (default 160^2 x 320): per material variant (1B, 1D, 2B,
+    2C), design (uniform 0.3 start, binary tree) and coarsest-level solver
+    (exact, or the paper's Jacobi-GMRES), the FGMRES iterations and solve
+    times of the state solve and of the adjoint solve for the p-norm
+    objective (P = 20), at the paper's outer tolerance 1e-5.  The value is
+    the state + adjoint DOF throughput of the semi-coarsened, exact-coarse
+    runs."""
+    import numpy as np
+    import torch
+    from paper_2508_09589_amd import Problem
+    from paper_2508_09589_amd.inputs import example_design, example_problem
+    n, nt = args.example_n, 2 * args.example_n
+    rows = []
+    for variant in ("1B", "1D", "2B", "2C"):
+        kw = example_problem(variant, n, nt)
+        for design in ("uniform", "tree"):
+            rho = torch.tensor(example_design(design, n))
+            for coarse in ("direct", "gmres"):
+                for coarsening in ("semi", "full"):
+                    t0 = time.perf_counter()
+                    p = Problem(rho=rho, precision=args.precision, rtol=args.rtol, coarse=coarse,
+                                coarsening=coarsening, max_it=args.max_it,
+                                bf16_from_level=args.bf16_from_level, **kw)
+                    torch.cuda.synchronize()
+                    setup = time.perf_counter() - t0
+                    t0 = time.perf_counter()
+                    T, si = p.solve(allow_not_converged=True)
+                    torch.cuda.synchronize()
+                    ts = time.perf_counter() - t0
+                    _, dphi = p.pnorm(T, 20.0)
+                    t0 = time.perf_counter()
+                    lam, ai = p.adjoint(dphi, allow_not_converged=True)
+                    torch.cuda.synchronize()
+                    ta = time.perf_counter() - t0
+                    r = dict(variant=variant, design=design, coarse=coarse, coarsening=coarsening,
+                             levels=len(p.hierarchy()[0]), state_its=si.iterations,
+                             adjoint_its=ai.iterations, state_s=ts, adjoint_s=ta, setup_s=setup,
+                             state_rel_res=si.true_rel_res, adjoint_rel_res=ai.true_rel_res,
+                             dofs=p.n_nodes)
+                    rows.append(r)
+                    log(f"{variant} {design:7s} {coarse:6s} {coarsening}: levels {r['levels']}, "
+                        f"its {si.iterations}/{ai.iterations}, {ts:.3f}/{ta:.3f} s, "
+                        f"res {si.true_rel_res:.2e}/{ai.true_rel_res:.2e}")
+                    p.close()
+                    del T, lam, dphi
+    sel = [r for r in rows if r["coarse"] == "direct" and r["coarsening"] == "semi"]
+    secs = sum(r["state_s"] + r["adjoint_s"] for r in sel)
+    dofs = sum(2 * r["dofs"] for r in sel)
+
+    def mean_its(coarse, coarsening, key):
+        v = [r[key] for r in rows if r["coarse"] == coarse and r["coarsening"] == coarsening]
+        return float(np.mean(v))
+
+    summary = {f"{c}/{m}": {"state": mean_its(c, m, "state_its"), "adjoint": mean_its(c, m, "adjoint_its")}
+               for c in ("direct", "gmres") for m in ("semi", "full")}
+    return {"metric": "state + adjoint DOFs solved/s on the example problems (semi-coarsening)",
+            "value": dofs / secs, "unit": "DOF/s", "n_gpus": 1, "steps": len(sel), "warmup": 0,
+            "ms_per_step": secs / len(sel) * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+            "data": "synthetic",
+            "config": {"workload": "coarsening", "grid": [n, n, nt], "rtol": args.rtol,
+                       "variants": ["1B", "1D", "2B", "2C"], "designs": ["uniform", "tree"]},
+            "mean_iterations": summary, "runs": rows}
+
+
 def copy_calibration():
     """Three copies of a 1 GiB FP32 buffer: 1 GiB read and 1 GiB written per
     dispatch, the reference for scaling FETCH_SIZE / WRITE_SIZE counters."""
@@ -389,7 +456,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="medium",
-                    choices=["small", "medium", "large", "grad", "serving", "design"])
+                    choices=["small", "medium", "large", "grad", "serving", "design", "coarsening"])
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0)
@@ -400,6 +467,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare-fp64", action="store_true")
     ap.add_argument("--max-it", type=int, default=400)
+    ap.add_argument("--example-n", type=int, default=160,
+                    help="coarsening workload: spatial elements per side (nt = 2 n)")
+    ap.add_argument("--rtol", type=float, default=1e-5,
+                    help="coarsening workload: outer FGMRES tolerance (the paper's 1e-5)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the roofline kernel's HBM traffic summary from two rocprofv3 "
                          "--pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
@@ -416,7 +487,8 @@ def main():
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU time-slab sharding is a design only)", file=sys.stderr)
         sys.exit(2)
-    runner = {"serving": run_serving, "design": run_design}.get(args.workload, run)
+    runner = {"serving": run_serving, "design": run_design,
+              "coarsening": run_coarsening}.get(args.workload, run)
     print(json.dumps(runner(args)), flush=True)
     if args.copy_calibration:
         copy_calibration()

@@ -59,6 +59,9 @@ enum {
     ST_FLAG_TIME_KERNELS = 1,   /* record per-kernel-class GPU times in st_info;
                                    bits 8.. of flags select classes (0 = all)     */
     ST_FLAG_NO_PLANE_DEDUP = 2, /* keep every time level of coarse stencils       */
+    ST_FLAG_FULL_COARSENING = 8, /* full space-time coarsening on every level (the
+                                   paper's comparison to Algorithm 1, §4.2.2);
+                                   fixed at setup                                */
     ST_FLAG_COARSE_GMRES = 4    /* coarsest level: Jacobi-GMRES (coarse_max_it,
                                    coarse_rtol, coarse_restart) as in §3.2, instead
                                    of the default exact solve by block-tridiagonal
@@ -211,8 +214,8 @@ st_status st_filter(st_handle* h, const double* in_dev, double* out_dev);
 st_status st_set_stream(st_handle* h, void* hip_stream);
 
 /* Replace the option flags (ST_FLAG_TIME_KERNELS and its class mask,
- * ST_FLAG_COARSE_GMRES) of a built problem; ST_FLAG_NO_PLANE_DEDUP and the
- * other options are fixed at setup.  Switching to the exact coarse solve
+ * ST_FLAG_COARSE_GMRES) of a built problem; ST_FLAG_NO_PLANE_DEDUP,
+ * ST_FLAG_FULL_COARSENING and the other options are fixed at setup.  Switching to the exact coarse solve
  * factorises the coarsest operator on the next V-cycle. */
 st_status st_set_flags(st_handle* h, int32_t flags);
 

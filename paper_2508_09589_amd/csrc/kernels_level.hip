@@ -1,6 +1,7 @@
 // Coarse-level kernels of the space-time multigrid hierarchy (paper §3.2):
 // 27-point stencil application and its transpose, masked trilinear restriction
-// (P_m^T) and prolongation (P_m) for space and time semi-coarsening (§3.2.1),
+// (P_m^T) and prolongation (P_m) for space and time semi-coarsening (§3.2.1)
+// and for full space-time coarsening (how = 3, the paper's comparison),
 // coarse Dirichlet masks, and the pieces of the Galerkin construction
 // A_{l+1} = P_m^T A_l P_m by probing with 27 colours.
 //
@@ -103,13 +104,31 @@ __global__ void k_restrict(int how, int nxf, int nyf, int ntf, int nxc, int nyc,
                     acc += wc * (a == 0 ? 1.0 : 0.5) * (double)rf[f];
                 }
             }
-        } else {
+        } else if (how == 2) {
             for (int a = -1; a <= 1; ++a) {
                 const int fn = 2 * n + a;
                 if (fn < 0 || fn > ntf) continue;
                 const long long f = (long long)fn * Pf + r;
                 if (maskf[f]) continue;
                 acc += (a == 0 ? 1.0 : 0.5) * (double)rf[f];
+            }
+        } else {   // full space-time coarsening: the product of both
+            for (int d = -1; d <= 1; ++d) {
+                const int fn = 2 * n + d;
+                if (fn < 0 || fn > ntf) continue;
+                const double wd = d == 0 ? 1.0 : 0.5;
+                for (int c = -1; c <= 1; ++c) {
+                    const int fj = 2 * J + c;
+                    if (fj < 0 || fj > nyf) continue;
+                    const double wc = wd * (c == 0 ? 1.0 : 0.5);
+                    for (int a = -1; a <= 1; ++a) {
+                        const int fi = 2 * I + a;
+                        if (fi < 0 || fi > nxf) continue;
+                        const long long f = (long long)fn * Pf + (long long)fj * rowf + fi;
+                        if (maskf[f]) continue;
+                        acc += wc * (a == 0 ? 1.0 : 0.5) * (double)rf[f];
+                    }
+                }
             }
         }
         bc[idx] = (T)acc;
@@ -160,13 +179,22 @@ __global__ void k_prolong(int how, int nxf, int nyf, int ntf, int nxc, int nyc, 
                                 (double)ec[base + (long long)(j0 + 1) * rowc + i0] +
                                 (double)ec[base + (long long)(j0 + 1) * rowc + i0 + 1]);
                 }
-            } else {
+            } else if (how == 2) {
                 const int n0 = n >> 1;
                 if (!(n & 1))
                     v = (double)ec[(long long)n0 * Pc + r];
                 else
                     v = 0.5 * ((double)ec[(long long)n0 * Pc + r] +
                                (double)ec[(long long)(n0 + 1) * Pc + r]);
+            } else {   // full: trilinear, one or two coarse nodes per axis
+                const int kn = (n & 1) ? 2 : 1, kj = (j & 1) ? 2 : 1, ki = (i & 1) ? 2 : 1;
+                const double w = ((n & 1) ? 0.5 : 1.0) * ((j & 1) ? 0.5 : 1.0) * ((i & 1) ? 0.5 : 1.0);
+                for (int dn = 0; dn < kn; ++dn)
+                    for (int dj = 0; dj < kj; ++dj)
+                        for (int di = 0; di < ki; ++di)
+                            v += (double)ec[(long long)((n >> 1) + dn) * Pc +
+                                            (long long)((j >> 1) + dj) * rowc + (i >> 1) + di];
+                v *= w;
             }
         }
         if (accumulate)
@@ -207,12 +235,20 @@ __global__ void k_coarse_mask(int how, int nxf, int nyf, int ntf, int nxc, int n
                     if (fj < 0 || fj > nyf || fi < 0 || fi > nxf) continue;
                     any_free |= !maskf[(long long)n * Pf + (long long)fj * rowf + fi];
                 }
-        } else {
+        } else if (how == 2) {
             for (int a = -1; a <= 1; ++a) {
                 const int fn = 2 * n + a;
                 if (fn < 0 || fn > ntf) continue;
                 any_free |= !maskf[(long long)fn * Pf + r];
             }
+        } else {
+            for (int d = -1; d <= 1; ++d)
+                for (int c = -1; c <= 1; ++c)
+                    for (int a = -1; a <= 1; ++a) {
+                        const int fn = 2 * n + d, fj = 2 * J + c, fi = 2 * I + a;
+                        if (fn < 0 || fn > ntf || fj < 0 || fj > nyf || fi < 0 || fi > nxf) continue;
+                        any_free |= !maskf[(long long)fn * Pf + (long long)fj * rowf + fi];
+                    }
         }
         maskc[idx] = any_free ? 0 : 1;
     }

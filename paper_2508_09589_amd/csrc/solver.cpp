@@ -119,6 +119,7 @@ struct Carver {
 // Algorithm 1 (§3.2.1): lambda = D_eff dt / dx^2; below lambda_crit coarsen in
 // time, otherwise in space; when the chosen direction cannot be halved try the
 // other; stop at max_levels or once a level has <= max_coarse_nodes nodes.
+// With ST_FLAG_FULL_COARSENING every level halves all three counts instead.
 struct LevelDims {
     int nx, ny, nt, how;
     double dx, dt;
@@ -129,14 +130,21 @@ std::vector<LevelDims> build_hierarchy(const st_grid& g, const st_material& m, c
     L.push_back({g.nx, g.ny, g.nt, 0, g.dx, g.dt});
     const double D = std::sqrt(m.k_con * m.k_ins / (m.c_con * m.c_ins));
     const int maxl = std::max(1, std::min(o.max_levels, (int)ST_MAX_LEVELS));
+    const bool full = (o.flags & ST_FLAG_FULL_COARSENING) != 0;
     while ((int)L.size() < maxl) {
         const LevelDims c = L.back();
         const long long nodes = (long long)(c.nx + 1) * (c.ny + 1) * (c.nt + 1);
         if (nodes <= o.max_coarse_nodes) break;
-        const double lam = D * c.dt / (c.dx * c.dx);
-        const bool want_time = lam < o.lambda_crit;
         const bool can_s = c.nx % 2 == 0 && c.ny % 2 == 0 && c.nx >= 2 && c.ny >= 2;
         const bool can_t = c.nt % 2 == 0 && c.nt >= 2;
+        if (full) {
+            // full space-time coarsening: all three counts halve, while they can
+            if (!(can_s && can_t)) break;
+            L.push_back({c.nx / 2, c.ny / 2, c.nt / 2, 3, 2 * c.dx, 2 * c.dt});
+            continue;
+        }
+        const double lam = D * c.dt / (c.dx * c.dx);
+        const bool want_time = lam < o.lambda_crit;
         int how = 0;
         if (want_time) how = can_t ? 2 : (can_s ? 1 : 0);
         else how = can_s ? 1 : (can_t ? 2 : 0);
@@ -1134,8 +1142,9 @@ st_status st_set_stream(st_handle* h, void* hip_stream) {
 
 st_status st_set_flags(st_handle* h, int32_t flags) {
     if (!h) return ST_ERR_ARG;
-    const int keep = h->opts.flags & ST_FLAG_NO_PLANE_DEDUP;
-    h->opts.flags = (flags & ~ST_FLAG_NO_PLANE_DEDUP) | keep;
+    const int fixed = ST_FLAG_NO_PLANE_DEDUP | ST_FLAG_FULL_COARSENING;
+    const int keep = h->opts.flags & fixed;
+    h->opts.flags = (flags & ~fixed) | keep;
     h->timing = (flags & ST_FLAG_TIME_KERNELS) != 0;
     return ST_OK;
 }

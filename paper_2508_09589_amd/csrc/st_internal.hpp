@@ -80,7 +80,7 @@ struct Level {
     long long nn;           // nodes
     long long ld;           // basis stride: nn rounded up to 64 elements
     double dx, dt;
-    int how;                // 0 finest, 1 space-coarsened, 2 time-coarsened
+    int how;                // 0 finest, 1 space-coarsened, 2 time-coarsened, 3 both
     int nplanes;            // distinct stencil time levels
     int vprec;              // 0 = FP64 vectors, 1 = FP32 vectors in the V-cycle
     int sprec;              // stencil storage: 0 FP64, 1 FP32, 2 BF16

@@ -53,13 +53,18 @@ def test_fine_diagonal_mask_and_stencil(torch_cuda, nx, ny, nt, tv):
     p.close()
 
 
-@pytest.mark.parametrize("nx,ny,nt,tv", [(16, 16, 16, False), (16, 16, 16, True), (16, 12, 8, True),
-                                         (32, 32, 32, False)])
-def test_galerkin_hierarchy(torch_cuda, nx, ny, nt, tv):
+@pytest.mark.parametrize("nx,ny,nt,tv,full", [(16, 16, 16, False, False), (16, 16, 16, True, False),
+                                              (16, 12, 8, True, False), (32, 32, 32, False, False),
+                                              (16, 16, 16, True, True), (16, 12, 8, False, True),
+                                              (24, 20, 12, True, True)])
+def test_galerkin_hierarchy(torch_cuda, nx, ny, nt, tv, full):
     """Every coarse level: mask, stencil (P_m^T A P_m with identity rows),
-    inverse diagonal; and the transfers on every level pair."""
-    c = Case(nx, ny, nt, tv=tv, seed=5, max_coarse_nodes=200)
+    inverse diagonal; and the transfers on every level pair (semi-coarsening
+    by Algorithm 1, or full space-time coarsening)."""
+    c = Case(nx, ny, nt, tv=tv, seed=5, max_coarse_nodes=200, full=full)
     p = c.problem(max_coarse_nodes=200)
+    if full:
+        assert all(L["how"] == "full" for L in c.levels[1:]) and len(c.levels) > 1
     dims, planes = p.hierarchy()
     assert [(L["nx"], L["ny"], L["nt"]) for L in c.levels] == [tuple(d) for d in dims]
     A, masks, Pm = c.ops
@@ -166,9 +171,9 @@ def test_smoother_matches_oracle_gmres(torch_cuda, level):
 
 
 @pytest.mark.parametrize("tv", [False, True])
-@pytest.mark.parametrize("coarse", ["gmres", "direct"])
-def test_vcycle_matches_oracle(torch_cuda, tv, coarse):
-    c = Case(16, 16, 16, tv=tv, seed=11, max_coarse_nodes=200)
+@pytest.mark.parametrize("coarse,full", [("gmres", False), ("direct", False), ("direct", True)])
+def test_vcycle_matches_oracle(torch_cuda, tv, coarse, full):
+    c = Case(16, 16, 16, tv=tv, seed=11, max_coarse_nodes=200, full=full)
     p = c.problem(max_coarse_nodes=200, coarse=coarse)
     A, masks, Pm = c.ops
     rng = np.random.default_rng(5)

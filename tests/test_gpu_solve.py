@@ -85,3 +85,20 @@ def test_sink_free_closed_form(torch_cuda, n, nt, tv):
     err = np.max(np.abs(T.cpu().numpy() - expect[:, None, None])) / expect.max()
     assert err < 1e-10, err
     p.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_coarsening_solve_parity(torch_cuda, precision):
+    """Full space-time coarsening (the comparison hierarchy of §4.2.2): state
+    and adjoint still reach the direct solutions, and the level count is the
+    oracle's."""
+    c = Case(32, 32, 32, tv=True, seed=31, full=True)
+    p = c.problem(precision=precision, rtol=1e-12)
+    dims, _ = p.hierarchy()
+    assert [tuple(d) for d in dims] == [(L["nx"], L["ny"], L["nt"]) for L in c.levels]
+    T, info = p.solve()
+    assert info.true_rel_res <= 1e-12
+    assert rel(T.cpu().numpy(), solve_direct(c.Jm, c.fm)) <= 1e-10
+    lam, _ = p.adjoint(p.load_vector())
+    assert rel(lam.cpu().numpy(), solve_adjoint_direct(c.Jm, c.f, c.mask)) <= 1e-10
+    p.close()
