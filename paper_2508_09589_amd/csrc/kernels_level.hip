@@ -23,8 +23,8 @@ static inline unsigned grid_for(long long n, int threads = 256, long long cap = 
 //   v = A x;  if b: v = b - v;  if invd: v *= invd;  v *= scale.
 template <typename T, typename S, typename TC, bool TRANS>
 __global__ __launch_bounds__(256) void k_stencil_march(
-    int nx, int ny, int nt, int nplanes, const S* __restrict__ st, const int* __restrict__ pmap,
-    const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ b,
+    int nx, int ny, int nt, int nplanes, const S* __restrict__ st, const float* __restrict__ cen,
+    const int* __restrict__ pmap, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ b,
     const T* __restrict__ invd, const double* __restrict__ scale, const int* __restrict__ skip,
     int nchunk) {
     if (skip && *skip) return;
@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256) void k_stencil_march(
     if (n0 > nt) return;
     const int n1 = min(n0 + nchunk, nt + 1);
     const TC sc = scale ? (TC)(*scale) : (TC)1;
-    stencil_march_rows<T, S, TC, TRANS>(nx, ny, nt, nplanes, st, pmap, x, r, n0, n1,
+    stencil_march_rows<T, S, TC, TRANS>(nx, ny, nt, nplanes, st, cen, pmap, x, r, n0, n1,
                                         [&](int, long long idx, TC acc) {
                                             TC v = acc;
                                             if (b) v = (TC)b[idx] - v;
@@ -55,12 +55,12 @@ static void stencil_dispatch(hipStream_t s, const Level& L, const S* st, int tra
     const int gy = (L.nt + 1 + nchunk - 1) / nchunk;
     if (trans)
         hipLaunchKernelGGL((k_stencil_march<T, S, TC, true>), dim3(gx, gy), dim3(256), 0, s, L.nx,
-                           L.ny, L.nt, L.nplanes, st, L.plane_map, (const T*)x, (T*)y, (const T*)b,
-                           (const T*)invd, scale, skip, nchunk);
+                           L.ny, L.nt, L.nplanes, st, L.cen32, L.plane_map, (const T*)x, (T*)y,
+                           (const T*)b, (const T*)invd, scale, skip, nchunk);
     else
         hipLaunchKernelGGL((k_stencil_march<T, S, TC, false>), dim3(gx, gy), dim3(256), 0, s, L.nx,
-                           L.ny, L.nt, L.nplanes, st, L.plane_map, (const T*)x, (T*)y, (const T*)b,
-                           (const T*)invd, scale, skip, nchunk);
+                           L.ny, L.nt, L.nplanes, st, L.cen32, L.plane_map, (const T*)x, (T*)y,
+                           (const T*)b, (const T*)invd, scale, skip, nchunk);
 }
 
 void launch_stencil_apply(hipStream_t s, const Level& L, int prec, int trans, const void* x,
@@ -425,9 +425,49 @@ __global__ void k_stencil_cast(long long n, const double* __restrict__ in, float
     }
 }
 
+// Compensated FP32 centres of a BF16 stencil (layout in stencil_core.hpp):
+// per plane, node r and time offset g = dn + 1,
+//   rows:    cen[g]     = sum_q A_g,q(r)            - sum_{q != centre} bf16(A_g,q(r))
+//   columns: cen[3 + g] = sum_q A_g,8-q(r + off_q)  - sum_{q != centre} bf16(A_g,8-q(r + off_q))
+// where A_g,q(r) = st[g*9 + q][plane][r] and the column sum runs over the
+// in-domain neighbours r + off_q (their entries pointing back at r).
+__global__ void k_stencil_centres(int nx, int ny, int nplanes, const double* __restrict__ st,
+                                  float* __restrict__ cen) {
+    const int rowp = nx + 1;
+    const long long P = (long long)rowp * (ny + 1);
+    const long long DS = P * nplanes;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < DS;
+         t += (long long)gridDim.x * blockDim.x) {
+        const int pl = (int)(t / P);
+        const long long r = t - (long long)pl * P;
+        const int j = (int)(r / rowp), i = (int)(r - (long long)j * rowp);
+        const double* sp = st + (long long)pl * P;
+        for (int g = 0; g < 3; ++g) {
+            double rs = 0.0, rr = 0.0, cs = 0.0, cr = 0.0;
+            for (int q = 0; q < 9; ++q) {
+                const double a = sp[(long long)(g * 9 + q) * DS + r];
+                rs += a;
+                if (q != 4) rr += (double)bf16_to_f32(f32_to_bf16((float)a));
+                const int di = q % 3 - 1, dj = q / 3 - 1;
+                if (i + di < 0 || i + di > nx || j + dj < 0 || j + dj > ny) continue;
+                const double b = sp[(long long)(g * 9 + 8 - q) * DS + r + dj * rowp + di];
+                cs += b;
+                if (q != 4) cr += (double)bf16_to_f32(f32_to_bf16((float)b));
+            }
+            cen[(long long)g * DS + t] = (float)(rs - rr);
+            cen[(long long)(3 + g) * DS + t] = (float)(cs - cr);
+        }
+    }
+}
+
 void launch_stencil_cast(hipStream_t s, const Level& L, float* st32, uint16_t* st16) {
     const long long n = 27LL * L.nplanes * (L.nx + 1) * (L.ny + 1);
     hipLaunchKernelGGL(k_stencil_cast, dim3(grid_for(n)), dim3(256), 0, s, n, L.st64, st32, st16);
+    if (st16 && L.cen32) {
+        const long long m = (long long)L.nplanes * (L.nx + 1) * (L.ny + 1);
+        hipLaunchKernelGGL(k_stencil_centres, dim3(grid_for(m)), dim3(256), 0, s, L.nx, L.ny,
+                           L.nplanes, L.st64, L.cen32);
+    }
 }
 
 // ---------------------------------------------------------------------------

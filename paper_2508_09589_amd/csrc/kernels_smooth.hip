@@ -194,9 +194,10 @@ __global__ __launch_bounds__(SM_THREADS) void k_sm_scale(long long n, const T* _
 //          d <= j.
 template <typename T, typename S, typename TC, bool TRANS>
 __global__ __launch_bounds__(SM_THREADS) void k_sm_apply(
-    int nx, int ny, int nt, int nplanes, const S* __restrict__ st, const int* __restrict__ pmap,
-    const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ b,
-    const T* __restrict__ invd, const T* __restrict__ V, long long ld, int j, int phase,
+    int nx, int ny, int nt, int nplanes, const S* __restrict__ st, const float* __restrict__ cen,
+    const int* __restrict__ pmap, const T* __restrict__ x, T* __restrict__ y,
+    const T* __restrict__ b, const T* __restrict__ invd, const T* __restrict__ V, long long ld,
+    int j, int phase,
     KState* ks, const double* __restrict__ npart, int nbn, double* __restrict__ dpart,
     double* __restrict__ npart_out, int maxit, double rtol, int nchunk) {
     __shared__ double sums[1];
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_sm_apply(
     for (int d = 0; d < SMAX; ++d) acc[d] = 0.0;
     if (r < P && n0 <= nt) {
         stencil_march_rows<T, S, TC, TRANS>(
-            nx, ny, nt, nplanes, st, pmap, x, r, n0, n1, [&](int, long long idx, TC a) {
+            nx, ny, nt, nplanes, st, cen, pmap, x, r, n0, n1, [&](int, long long idx, TC a) {
                 TC v = a;
                 if (phase == 0) v = (TC)b[idx] - v;
                 v *= (TC)invd[idx];
@@ -444,12 +445,12 @@ static void sm_apply_launch(hipStream_t s, const Level& L, const S* st, int tran
                             int gy) {
     if (trans)
         hipLaunchKernelGGL((k_sm_apply<T, S, TC, true>), dim3(gx, gy), dim3(SM_THREADS), 0, s,
-                           L.nx, L.ny, L.nt, L.nplanes, st, L.plane_map, (const T*)x, (T*)y,
+                           L.nx, L.ny, L.nt, L.nplanes, st, L.cen32, L.plane_map, (const T*)x, (T*)y,
                            (const T*)b, (const T*)invd, (const T*)V, L.ld, j, phase, ks, npart,
                            nbn, dpart, npart_out, maxit, rtol, nchunk);
     else
         hipLaunchKernelGGL((k_sm_apply<T, S, TC, false>), dim3(gx, gy), dim3(SM_THREADS), 0, s,
-                           L.nx, L.ny, L.nt, L.nplanes, st, L.plane_map, (const T*)x, (T*)y,
+                           L.nx, L.ny, L.nt, L.nplanes, st, L.cen32, L.plane_map, (const T*)x, (T*)y,
                            (const T*)b, (const T*)invd, (const T*)V, L.ld, j, phase, ks, npart,
                            nbn, dpart, npart_out, maxit, rtol, nchunk);
 }

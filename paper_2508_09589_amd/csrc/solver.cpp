@@ -221,6 +221,8 @@ size_t carve(st_handle* h, char* base) {
             L.st64 = c.take<double>((size_t)27 * P * (L.nt + 1));
             L.st32 = (mixed && L.sprec == 1 && l > 0) ? c.take<float>((size_t)27 * P * (L.nt + 1)) : nullptr;
             L.st16 = (mixed && L.sprec == 2 && l > 0) ? c.take<uint16_t>((size_t)27 * P * (L.nt + 1)) : nullptr;
+            // (decided by the options, never by a pointer: sizing passes get null ones)
+            L.cen32 = (mixed && L.sprec == 2 && l > 0) ? c.take<float>((size_t)6 * P * (L.nt + 1)) : nullptr;
         }
         const bool coarsest = l == h->nlev - 1;
         L.x = (l > 0) ? (void*)c.take<char>(L.nn * vb) : nullptr;
@@ -370,6 +372,12 @@ int64_t fine_coef_bytes(const st_handle* h, int vb) {
 // Operator applications on a level.  Level 0 is matrix-free; coarse levels
 // use their Galerkin stencil.  prec: storage/arithmetic precision (0 FP64,
 // 1 the level's V-cycle precision when mixed).
+// Bytes of one stored stencil row: 27 coefficients in FP64 or FP32, or 24 in
+// BF16 plus three compensated FP32 centres.
+static int64_t stencil_row_bytes(const Level& L, int prec) {
+    return prec == 0 ? 27 * 8 : (L.sprec == 2 ? 24 * 2 + 3 * 4 : 27 * 4);
+}
+
 void level_apply(st_handle* h, int l, int prec, int trans, const void* x, void* y, const void* b,
                  const void* invd, const double* scale, const int* skip) {
     Level& L = h->lev[l];
@@ -382,11 +390,10 @@ void level_apply(st_handle* h, int l, int prec, int trans, const void* x, void* 
                     fine_coef_bytes(h, vbytes(v)));
         launch_fine_apply(h->stream, h->fg, cf, v, v, v == 0, trans, x, y, b, invd, scale, skip, 1, 1);
     } else {
-        const int sb = prec == 0 ? 8 : (L.sprec == 2 ? 2 : 4);
         Timed t(h, KC_STENCIL,
                 (int64_t)L.nn * (int64_t)(2 * vbytes(prec) + (b ? vbytes(prec) : 0) +
                                           (invd ? vbytes(prec) : 0)) +
-                    (int64_t)27 * sb * (L.nx + 1) * (L.ny + 1) * L.nplanes);
+                    stencil_row_bytes(L, prec) * (L.nx + 1) * (L.ny + 1) * L.nplanes);
         launch_stencil_apply(h->stream, L, prec, trans, x, y, b, invd, scale, skip);
     }
 }
@@ -411,8 +418,7 @@ void smooth(st_handle* h, int l, int prec, int trans, const void* b, void* x, in
     int nchunk, gx, gy;
     if (l > 0 && sm_fused_plan(L, &nchunk, &gx, &gy)) {
         // small coarse level: two kernels per iteration
-        const int64_t stb = (int64_t)27 * (prec == 0 ? 8 : (L.sprec == 2 ? 2 : 4)) *
-                            (L.nx + 1) * (L.ny + 1) * L.nplanes;
+        const int64_t stb = stencil_row_bytes(L, prec) * (L.nx + 1) * (L.ny + 1) * L.nplanes;
         int nbn = 0;
         {
             Timed t(h, zero_x0 ? kd : KC_STENCIL, zero_x0 ? n * (int64_t)(3 * vb) : n * (int64_t)(4 * vb) + stb);
@@ -937,7 +943,10 @@ st_status st_setup(const st_grid* grid, const st_material* mat, const double* rh
         delete h;
         return ST_ERR_OOM;
     }
-    carve(h, base);
+    if (carve(h, base) != need) {   // the sizing pass must lay out the same buffers
+        delete h;
+        return ST_ERR_OOM;
+    }
     h->ws = (char*)workspace_dev;
     h->ws_bytes = workspace_bytes;
     h->timing = (opts->flags & ST_FLAG_TIME_KERNELS) != 0;

@@ -5,7 +5,17 @@
 // A(node, node + (di, dj, dn)); plane = plane_map[n] so that time levels with
 // identical rows share storage.  Storage is FP64, FP32 or BF16 (upper half of
 // an FP32, round to nearest even).
+//
+// BF16 stencils keep their three in-plane centres (di = dj = 0, d = 4, 13, 22)
+// in FP32 instead, compensated so that rounding leaves the sums over each
+// time offset intact: cen[g][plane][r] (g = dn + 1) makes every row's sum over
+// the 9 entries of offset dn exact (forward apply), cen[3 + g][plane][r] makes
+// the matching column sums exact (transposed apply).  Those sums fix how the
+// operator acts on fields that are constant in space; an insulated domain has
+// near-null modes of that kind, which plain BF16 rounding would perturb.
 #pragma once
+#include <type_traits>
+
 #include "st_internal.hpp"
 
 namespace st {
@@ -41,9 +51,11 @@ template <> __device__ __forceinline__ double ldcoef<double, double>(const doubl
 template <typename T, typename S, typename TC, bool TRANS, typename Emit>
 __device__ __forceinline__ void stencil_march_rows(int nx, int ny, int nt, int nplanes,
                                                    const S* __restrict__ st,
+                                                   const float* __restrict__ cen,
                                                    const int* __restrict__ pmap,
                                                    const T* __restrict__ x, int r, int n0, int n1,
                                                    Emit&& emit) {
+    constexpr bool CEN = std::is_same<S, uint16_t>::value;   // compensated FP32 centres
     const int rowp = nx + 1;
     const int P = rowp * (ny + 1);
     const int j = r / rowp, i = r - j * rowp;
@@ -83,7 +95,12 @@ __device__ __forceinline__ void stencil_march_rows(int nx, int ny, int nt, int n
             if (!TRANS) {
                 const S* sp = st + (long long)pc * P + r;
 #pragma unroll
-                for (int d = 0; d < 27; ++d) c[d] = ldcoef<TC, S>(sp + (long long)d * DS);
+                for (int d = 0; d < 27; ++d) {
+                    if (CEN && d % 9 == 4)
+                        c[d] = (TC)cen[(long long)(d / 9) * DS + (long long)pc * P + r];
+                    else
+                        c[d] = ldcoef<TC, S>(sp + (long long)d * DS);
+                }
             } else {
 #pragma unroll
                 for (int dn = -1; dn <= 1; ++dn) {
@@ -91,9 +108,13 @@ __device__ __forceinline__ void stencil_march_rows(int nx, int ny, int nt, int n
 #pragma unroll
                     for (int q = 0; q < 9; ++q) {
                         const int d = (dn + 1) * 9 + q;
-                        c[d] = (pl >= 0 && ((valid >> q) & 1u))
-                                   ? ldcoef<TC, S>(st + (long long)(26 - d) * DS + (long long)pl * P + r + off[q])
-                                   : (TC)0;
+                        if (CEN && q == 4)
+                            c[d] = pl >= 0 ? (TC)cen[(long long)(4 - dn) * DS + (long long)pl * P + r]
+                                           : (TC)0;
+                        else
+                            c[d] = (pl >= 0 && ((valid >> q) & 1u))
+                                       ? ldcoef<TC, S>(st + (long long)(26 - d) * DS + (long long)pl * P + r + off[q])
+                                       : (TC)0;
                     }
                 }
             }

@@ -110,11 +110,43 @@ def test_bf16_rounding_reference():
                                               -2.5, 0.0])
 
 
+def _bf16_compensated(A, P, by_column):
+    """The BF16 storage model of a coarse operator: every entry rounded to
+    BF16 except the in-plane centre of each time offset (the entry coupling a
+    node to itself at time offset dn), which instead takes the exact sum of
+    its group minus the rounded rest.  The group is a row's entries of one
+    time offset (forward apply) or a column's (by_column, transposed apply),
+    so those sums survive the rounding exactly."""
+    import scipy.sparse as sp
+    C = sp.coo_matrix(A)
+    i, j, v = C.row, C.col, C.data
+    dn = j // P - i // P
+    centre = (j % P) == (i % P)
+    key = (j if by_column else i) * 3 + (dn + 1)
+    n = A.shape[0]
+    exact = np.zeros(3 * n)
+    rounded = np.zeros(3 * n)
+    np.add.at(exact, key, v)
+    np.add.at(rounded, key[~centre], _bf16_round(v[~centre]))
+    used = np.zeros(3 * n, dtype=bool)
+    used[key] = True
+    k = np.nonzero(used)[0]
+    node, g = k // 3, k % 3 - 1          # g = time of the column - time of the row
+    ci, cj = (node - g * P, node) if by_column else (node, node + g * P)
+    keep = ~centre
+    rows = np.concatenate([i[keep], ci])
+    cols = np.concatenate([j[keep], cj])
+    vals = np.concatenate([_bf16_round(v[keep]), exact[k] - rounded[k]])
+    return sp.csr_matrix((vals, (rows, cols)), shape=A.shape)
+
+
 @pytest.mark.parametrize("tv", [False, True])
 def test_bf16_stencil_applies(torch_cuda, tv):
-    """Levels >= 1 stored in BF16: the apply equals the oracle operator with
-    every coefficient rounded to BF16, to FP32 accuracy (1e-5), forward and
-    transposed; the level-0 apply is unchanged."""
+    """Levels >= 1 stored in BF16: the apply equals the oracle operator under
+    the BF16 storage model (off-centre entries rounded, compensated FP32
+    centres), to FP32 accuracy (1e-5), forward and transposed; and the
+    compensation keeps the action on fields constant in space exact to FP32
+    rounding, where plain BF16 rounding is off by about 1e-3."""
     import scipy.sparse as sp
     c = Case(16, 16, 16, tv=tv, seed=17, max_coarse_nodes=200)
     p = c.problem(max_coarse_nodes=200, precision="mixed", bf16_from_level=1)
@@ -122,12 +154,20 @@ def test_bf16_stencil_applies(torch_cuda, tv):
     rng = np.random.default_rng(6)
     for l in range(1, len(c.levels)):
         Al = sp.csr_matrix(A[l])
-        Ab = sp.csr_matrix((_bf16_round(Al.data), Al.indices, Al.indptr), shape=Al.shape)
+        P = (c.levels[l]["nx"] + 1) * (c.levels[l]["ny"] + 1)
+        nt1 = Al.shape[0] // P
         x = rng.standard_normal(Al.shape[0])
+        xt = np.repeat(rng.standard_normal(nt1), P)          # constant in space
         for trans in (False, True):
-            y = p.debug_apply(l, _t(x).reshape(p.level_shape(l)), transpose=trans, mixed=True)
-            ref = (Ab.T if trans else Ab) @ x
-            assert rel(y.cpu().numpy(), ref) < 1e-5, (l, trans, rel(y.cpu().numpy(), ref))
+            Ab = _bf16_compensated(Al, P, by_column=trans)
+            for v in (x, xt):
+                y = p.debug_apply(l, _t(v).reshape(p.level_shape(l)), transpose=trans, mixed=True)
+                ref = (Ab.T if trans else Ab) @ v
+                assert rel(y.cpu().numpy(), ref) < 1e-5, (l, trans, rel(y.cpu().numpy(), ref))
+            exact = (Al.T if trans else Al) @ xt
+            y = p.debug_apply(l, _t(xt).reshape(p.level_shape(l)), transpose=trans, mixed=True)
+            assert np.max(np.abs(y.cpu().numpy().ravel() - exact)) <= 1e-5 * np.max(np.abs(Al.data)) * \
+                np.max(np.abs(xt))
     p.close()
 
 
