@@ -60,7 +60,7 @@ enum {
                                    bits 8.. of flags select classes (0 = all)     */
     ST_FLAG_NO_PLANE_DEDUP = 2, /* keep every time level of coarse stencils       */
     ST_FLAG_FULL_COARSENING = 8, /* full space-time coarsening on every level (the
-                                   paper's comparison to Algorithm 1, §4.2.2);
+                                   paper's comparison to Algorithm 1, §5.1.2);
                                    fixed at setup                                */
     ST_FLAG_COARSE_GMRES = 4    /* coarsest level: Jacobi-GMRES (coarse_max_it,
                                    coarse_rtol, coarse_restart) as in §3.2, instead

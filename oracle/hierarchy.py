@@ -5,8 +5,9 @@ once; on each level the anisotropy lambda = D_eff * dt / dx^2 decides: below
 lambda_crit the next level halves the time resolution, otherwise it halves both
 spatial resolutions (§3.2.1).
 
-Full space-time coarsening (the comparison the paper makes in §4.2.2 and
-Figure 3c) halves all three resolutions on every level.
+Full space-time coarsening (the comparison the paper makes in §5.1.2, drawn
+beside the two semi-coarsenings in §3.2.1) halves all three resolutions on
+every level.
 
 Readings where the paper is silent:
   * the comparison is strict ("<"), so lambda == lambda_crit coarsens in space;

@@ -99,7 +99,7 @@ def serving_requests(n_requests=256, rate=50.0, seed=4,
 # Default SIMP endpoints and penalties of §2.2 (physical units).
 PAPER_MATERIAL = dict(k_ins=0.03, k_con=3.0, p_k=3.0, c_ins=0.5, c_con=1.0, p_c=2.0)
 
-# Material variants of §5.1.3 and §5.2.3: B = defaults, C/D = more conductive
+# Material variants of §5.1.3 and §5.2.2: B = defaults, C/D = more conductive
 # or more capacitive conductive phase.  Example 1D also raises p_c to 4.
 EXAMPLE_VARIANTS = {
     "1B": dict(example=1),

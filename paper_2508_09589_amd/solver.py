@@ -29,7 +29,7 @@ class Problem:
     coarse: "direct" (exact block-tridiagonal solve on the coarsest level) or
     "gmres" (the paper's Jacobi-GMRES coarse solve, §3.2).
     coarsening: "semi" (Algorithm 1) or "full" (every level halves space and
-    time, the comparison of §4.2.2).
+    time, the comparison of §5.1.2).
     """
 
     def __init__(self, nx, ny, nt, rho, dx=None, dt=None, k_ins=1e-3, k_con=1.0, p_k=3.0,

@@ -89,7 +89,7 @@ def test_sink_free_closed_form(torch_cuda, n, nt, tv):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_full_coarsening_solve_parity(torch_cuda, precision):
-    """Full space-time coarsening (the comparison hierarchy of §4.2.2): state
+    """Full space-time coarsening (the comparison hierarchy of §5.1.2): state
     and adjoint still reach the direct solutions, and the level count is the
     oracle's."""
     c = Case(32, 32, 32, tv=True, seed=31, full=True)
