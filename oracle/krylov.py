@@ -18,7 +18,8 @@ Readings (the paper gives only the parameters above):
   * the outer FGMRES uses classical Gram-Schmidt with one re-orthogonalisation
     pass and stops on ||f - J s||_2 <= rtol ||f||_2.
 The V-cycle can also solve the coarsest level exactly (sparse LU), the
-variant the GPU library uses by default.
+variant the GPU library uses by default, and smooth with the s-step form of
+the same GMRES minimisation (gmres_jacobi_sstep).
 """
 import numpy as np
 import scipy.sparse as sp
@@ -93,17 +94,72 @@ def gmres_jacobi(A, b, x0=None, maxit=10, rtol=1e-6, restart=None, dinv=None):
     return x, its, beta / beta0
 
 
+def gmres_jacobi_sstep(A, b, x0=None, maxit=10, rtol=1e-6, dinv=None):
+    """The Jacobi-GMRES smoother's minimisation written without Arnoldi:
+    over x in x0 + K_m(M, r0), M = D^{-1} A, r0 = D^{-1}(b - A x0), minimise
+    ||D^{-1}(b - A x)||_2.  With w_0 = r0 and w_{j+1} = M w_j (monomial
+    basis) and x = x0 + sum_{j<m} y_j w_j the preconditioned residual is
+    w_0 - sum_{j<m} y_j w_{j+1}, so y solves the normal equations
+    G[1:m+1, 1:m+1] y = G[1:m+1, 0] of the Gram matrix G = W^T W and the
+    squared residual is G[0,0] - y . G[1:m+1, 0].  m is the smallest count
+    whose residual is <= rtol ||r0|| (the GMRES stopping rule), else maxit.
+    In exact arithmetic this is GMRES(maxit) without restart, stopped by the
+    same test.  A non-positive Cholesky pivot (the basis became dependent:
+    the Krylov space is invariant and the residual is already minimal) stops
+    at the vectors before it.
+
+    Returns (x, m, residual / ||r0||)."""
+    n = b.shape[0]
+    if dinv is None:
+        dinv = 1.0 / A.diagonal()
+    x0 = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+    W = np.zeros((maxit + 1, n))
+    W[0] = dinv * (b - A @ x0)
+    for j in range(maxit):
+        W[j + 1] = dinv * (A @ W[j])
+    G = W @ W.T
+    g00 = G[0, 0]
+    if g00 == 0.0:
+        return x0, 0, 0.0
+    # the equations are solved in the basis scaled to unit length (the
+    # monomial vectors grow like the spectral radius of M)
+    sc = np.zeros(maxit + 1)
+    nz = np.diag(G) > 0
+    sc[nz] = 1.0 / np.sqrt(np.diag(G)[nz])
+    Gs = G * np.outer(sc, sc)
+    m_best, y_best, res_best = 0, np.zeros(0), 1.0
+    for m in range(1, maxit + 1):
+        Gm = Gs[1:m + 1, 1:m + 1]
+        if not nz[m]:
+            break
+        try:
+            np.linalg.cholesky(Gm)
+        except np.linalg.LinAlgError:
+            break
+        ys = np.linalg.solve(Gm, Gs[1:m + 1, 0])
+        res2 = max(1.0 - ys @ Gs[1:m + 1, 0], 0.0)
+        m_best, y_best, res_best = m, ys * sc[1:m + 1] / sc[0], np.sqrt(res2)
+        if res2 <= rtol * rtol:
+            break
+    return x0 + y_best @ W[:m_best], m_best, res_best
+
+
 class VCycle:
     """One classical V-cycle over the Galerkin hierarchy (§3.2).
 
     coarse="gmres": the coarsest level is solved with Jacobi-GMRES as in §3.2;
     coarse="direct": it is solved exactly (sparse LU of the coarsest operator).
+    smoother="gmres": Jacobi-GMRES by Arnoldi; "sstep": the same minimisation
+    through the Gram matrix of the monomial Krylov basis (gmres_jacobi_sstep).
     """
 
     def __init__(self, A, Pm, smooth_its=10, smooth_rtol=1e-6, coarse_its=200,
-                 coarse_rtol=1e-6, coarse_restart=30, coarse="gmres"):
+                 coarse_rtol=1e-6, coarse_restart=30, coarse="gmres", smoother="gmres"):
         if coarse not in ("gmres", "direct"):
             raise ValueError(coarse)
+        if smoother not in ("gmres", "sstep"):
+            raise ValueError(smoother)
+        self.smoother = smoother
         self.A, self.Pm = A, Pm
         self.dinv = [1.0 / a.diagonal() for a in A]
         self.si, self.sr = smooth_its, smooth_rtol
@@ -119,11 +175,16 @@ class VCycle:
                     self._lu = spla.splu(sp.csc_matrix(A))
                 return self._lu.solve(np.asarray(b, dtype=np.float64))
             return gmres_jacobi(A, b, None, self.ci, self.cr, self.crs, dinv)[0]
-        x = gmres_jacobi(A, b, None, self.si, self.sr, None, dinv)[0]
+        x = self._smooth(A, b, None, dinv)
         r = b - A @ x
         xc = self(self.Pm[l].T @ r, l + 1)
         x = x + self.Pm[l] @ xc
-        return gmres_jacobi(A, b, x, self.si, self.sr, None, dinv)[0]
+        return self._smooth(A, b, x, dinv)
+
+    def _smooth(self, A, b, x0, dinv):
+        if self.smoother == "sstep":
+            return gmres_jacobi_sstep(A, b, x0, self.si, self.sr, dinv)[0]
+        return gmres_jacobi(A, b, x0, self.si, self.sr, None, dinv)[0]
 
 
 def fgmres(A, b, prec, m=30, rtol=1e-8, maxit=1000, x0=None):

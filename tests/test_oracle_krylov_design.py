@@ -185,3 +185,67 @@ def test_fgmres_direct_coarse_matches_direct_solution():
     assert rel2 <= 1e-10
     assert np.linalg.norm(x2 - xs) <= 1e-8 * np.linalg.norm(xs)
     assert abs(its1 - its2) <= 1
+
+
+@pytest.mark.parametrize("kit", [1, 3, 6])
+def test_sstep_smoother_minimises_over_krylov_space(kit):
+    """The s-step form of the smoother gives the same minimiser as the
+    explicit orthonormal-basis least-squares problem (QR of the Krylov
+    vectors), and so the same x as Arnoldi GMRES."""
+    from oracle.krylov import gmres_jacobi_sstep
+    g, A, b, _ = _system(4, 4, seed=1)
+    rng = np.random.default_rng(2)
+    x0 = rng.standard_normal(b.size) * 0.01
+    dinv = 1.0 / A.diagonal()
+    x, m, _ = gmres_jacobi_sstep(A, b, x0, maxit=kit, rtol=0.0, dinv=dinv)
+    assert m == kit
+    B = dinv[:, None] * A.toarray()
+    r = dinv * (b - A @ x0)
+    K = [r]
+    for _ in range(kit - 1):
+        K.append(B @ K[-1])
+    Q, _ = np.linalg.qr(np.array(K).T)
+    y, *_ = np.linalg.lstsq(B @ Q, r, rcond=None)
+    x_ls = x0 + Q @ y
+    assert np.linalg.norm(x - x_ls) <= 1e-9 * np.linalg.norm(x_ls)
+    xg, _, _ = gmres_jacobi(A, b, x0, maxit=kit, rtol=0.0, dinv=dinv)
+    assert np.linalg.norm(x - xg) <= 1e-9 * np.linalg.norm(xg)
+
+
+def test_sstep_smoother_stops_where_gmres_stops():
+    """With a tolerance reached before the cap both forms stop after the same
+    number of steps; the preconditioned residuals they reach agree (the
+    Gram route loses digits of x as the monomial basis grows ill-conditioned,
+    about 1e-6 at nine vectors, but not of the residual it minimises)."""
+    from oracle.krylov import gmres_jacobi_sstep
+    g, A, b, _ = _system(6, 6, seed=5)
+    dinv = 1.0 / A.diagonal()
+    r0 = np.linalg.norm(dinv * b)
+    for rtol, tol_x in ((0.7, 1e-12), (0.5, 1e-12), (0.3, 1e-10), (0.2, 1e-5)):
+        xg, ig, eg = gmres_jacobi(A, b, None, maxit=10, rtol=rtol, dinv=dinv)
+        xs, ms, es = gmres_jacobi_sstep(A, b, None, maxit=10, rtol=rtol, dinv=dinv)
+        assert ig < 10 and ms == ig, (rtol, ig, ms)
+        tg = np.linalg.norm(dinv * (b - A @ xg)) / r0
+        ts = np.linalg.norm(dinv * (b - A @ xs)) / r0
+        assert ts == pytest.approx(tg, rel=1e-8) and tg <= rtol
+        assert es == pytest.approx(ts, rel=1e-5)
+        assert np.linalg.norm(xs - xg) <= tol_x * np.linalg.norm(xg)
+
+
+def test_sstep_smoother_vcycle_same_outer_iterations():
+    """FGMRES with s-step-smoothed V-cycles converges like the Arnoldi-smoothed
+    ones on the small workload (same count) and reaches the direct solution."""
+    from paper_2508_09589_amd.inputs import uniform_density
+    rho = uniform_density(32, seed=0)
+    g = Grid(32, 32, 32, 1 / 32, 1 / 32)
+    k = 1e-3 + (1 - 1e-3) * rho ** 3
+    mask = dirichlet_mask(g, PATCH)
+    Jm, fm = apply_dirichlet(assemble_matrix(g, k, np.ones_like(k)), load_vector(g, 1.0), mask)
+    lv = build_hierarchy(32, 32, 32, 1 / 32, 1 / 32, 1.0, 1e-3, 1.0, 1.0)
+    A, masks, Pm = build_operators(lv, Jm, mask)
+    _, its_g, _ = fgmres(Jm, fm, VCycle(A, Pm, coarse="direct"), m=30, rtol=1e-10)
+    x, its_s, rel = fgmres(Jm, fm, VCycle(A, Pm, coarse="direct", smoother="sstep"), m=30,
+                           rtol=1e-10)
+    assert its_s == its_g and rel <= 1e-10
+    xs = solve_direct(Jm, fm)
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
