@@ -34,7 +34,8 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def workload_problem(name, precision, time_kernels, bf16_from_level=0, max_it=1000):
+def workload_problem(name, precision, time_kernels, bf16_from_level=0, max_it=1000,
+                     smoother="gmres"):
     import torch
     from paper_2508_09589_amd import Problem
     from paper_2508_09589_amd.inputs import WORKLOADS, workload_density
@@ -44,6 +45,7 @@ def workload_problem(name, precision, time_kernels, bf16_from_level=0, max_it=10
     t0 = time.perf_counter()
     p = Problem(w["nx"], w["ny"], w["nt"], torch.tensor(rho), precision=precision, restart=restart,
                 rtol=1e-8, time_kernels=time_kernels, bf16_from_level=bf16_from_level,
+                smoother=smoother,
                 max_it=max_it)
     torch.cuda.synchronize()
     log(f"{name} {precision}: setup {time.perf_counter() - t0:.2f} s, {p.n_nodes} nodes, "
@@ -180,7 +182,7 @@ def run(args):
     from paper_2508_09589_amd import _lib as L
 
     p, t_setup, restart = workload_problem(args.workload, args.precision, True,
-                                           args.bf16_from_level, args.max_it)
+                                           args.bf16_from_level, args.max_it, args.smoother)
     n_nodes = p.n_nodes
     # Warm-up solves time every kernel class to find the dominant one.
     warm = []
@@ -229,7 +231,7 @@ def run(args):
                    "levels": last["levels"], "iterations": last["iterations"],
                    "true_rel_res": last["true_rel_res"], "setup_s": t_setup,
                    "converged": last["true_rel_res"] <= 1e-8,
-                   "bf16_from_level": args.bf16_from_level},
+                   "bf16_from_level": args.bf16_from_level, "smoother": args.smoother},
         "roofline": {"bound": "hbm", "kernel_class": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": recorded_traffic(args.workload, args.precision),
@@ -243,7 +245,7 @@ def run(args):
     del T
     torch.cuda.empty_cache()
     if args.compare_fp64 and args.precision != "fp64":
-        q, ts, _ = workload_problem(args.workload, "fp64", False, 0, args.max_it)
+        q, ts, _ = workload_problem(args.workload, "fp64", False, 0, args.max_it, args.smoother)
         Tq, iq = q.solve(allow_not_converged=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -279,7 +281,7 @@ def run_serving(args):
         srv = Server(int(args.hbm_budget_gb * (1 << 30)), slots=args.slots, keep_outputs=False)
         # warm-up: one request of each shape class is not timed
         stream = [(Request(r["id"], r["n"], r["nt"], dens[r["id"]], adjoint=r["adjoint"],
-                           precision=prec), r["t_arrive"]) for r in specs]
+                           precision=prec, smoother=args.smoother), r["t_arrive"]) for r in specs]
         torch.cuda.synchronize()
         torch.cuda.reset_peak_memory_stats()
         out, makespan = run_stream(stream, srv)
@@ -327,7 +329,8 @@ def run_design(args):
     rho = torch.tensor(workload_density("grad"), dtype=torch.float64, device="cuda")
     n = rho.shape[-1]
     p = Problem(n, n, rho.shape[0], rho, filter_r=1.5, proj_beta=32.0, proj_eta=0.5,
-                precision=args.precision, rtol=1e-8, bf16_from_level=args.bf16_from_level)
+                precision=args.precision, rtol=1e-8, bf16_from_level=args.bf16_from_level,
+                smoother=args.smoother)
     T = lam = None
     rec = []
 
@@ -394,7 +397,8 @@ def run_coarsening(args):
                     t0 = time.perf_counter()
                     p = Problem(rho=rho, precision=args.precision, rtol=args.rtol, coarse=coarse,
                                 coarsening=coarsening, max_it=args.max_it,
-                                bf16_from_level=args.bf16_from_level, **kw)
+                                bf16_from_level=args.bf16_from_level, smoother=args.smoother,
+                                **kw)
                     torch.cuda.synchronize()
                     setup = time.perf_counter() - t0
                     t0 = time.perf_counter()
@@ -464,6 +468,9 @@ def main():
     ap.add_argument("--bf16-from-level", type=int, default=1,
                     help="mixed precision: store coarse stencils of levels >= this in BF16 "
                          "(0 = FP32 everywhere)")
+    ap.add_argument("--smoother", default="sstep", choices=["gmres", "sstep"],
+                    help="Jacobi-GMRES smoothing in s-step form (one Gram pass) or by "
+                         "Arnoldi steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare-fp64", action="store_true")
     ap.add_argument("--max-it", type=int, default=400)

@@ -62,6 +62,10 @@ enum {
     ST_FLAG_FULL_COARSENING = 8, /* full space-time coarsening on every level (the
                                    paper's comparison to Algorithm 1, §5.1.2);
                                    fixed at setup                                */
+    ST_FLAG_SSTEP_SMOOTHER = 16, /* smoothing in s-step form: the same GMRES
+                                   minimisation from a monomial Krylov basis and
+                                   its Gram matrix (one pass for all inner
+                                   products instead of Arnoldi's growing ones) */
     ST_FLAG_COARSE_GMRES = 4    /* coarsest level: Jacobi-GMRES (coarse_max_it,
                                    coarse_rtol, coarse_restart) as in §3.2, instead
                                    of the default exact solve by block-tridiagonal
@@ -214,7 +218,7 @@ st_status st_filter(st_handle* h, const double* in_dev, double* out_dev);
 st_status st_set_stream(st_handle* h, void* hip_stream);
 
 /* Replace the option flags (ST_FLAG_TIME_KERNELS and its class mask,
- * ST_FLAG_COARSE_GMRES) of a built problem; ST_FLAG_NO_PLANE_DEDUP,
+ * ST_FLAG_COARSE_GMRES, ST_FLAG_SSTEP_SMOOTHER) of a built problem; ST_FLAG_NO_PLANE_DEDUP,
  * ST_FLAG_FULL_COARSENING and the other options are fixed at setup.  Switching to the exact coarse solve
  * factorises the coarsest operator on the next V-cycle. */
 st_status st_set_flags(st_handle* h, int32_t flags);

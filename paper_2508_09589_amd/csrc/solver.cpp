@@ -72,6 +72,7 @@ struct st_handle {
     int* cd_perm = nullptr;
     int* cd_status = nullptr;
     double* partials = nullptr;
+    double* gram_part = nullptr;  // s-step smoother: Gram partials
     double* dscal = nullptr;   // device scalars
     int* neq = nullptr;        // plane comparison flags
     // filter
@@ -203,6 +204,7 @@ size_t carve(st_handle* h, char* base) {
     h->Z = mixed ? (void*)c.take<float>((size_t)m * h->ld0) : (void*)c.take<double>((size_t)m * h->ld0);
     h->ks_outer = c.take<KState>(1);
     h->partials = c.take<double>((size_t)RED_BLOCKS * KMAX + 2 * KMAX);
+    h->gram_part = c.take<double>(gram_partials_doubles());
     h->dscal = c.take<double>(64);
     int maxnt = 0;
     for (int l = 0; l < h->nlev; ++l) maxnt = std::max(maxnt, h->lev[l].nt);
@@ -404,6 +406,8 @@ const void* level_invd(st_handle* h, int l, int prec) {
 
 // One Jacobi-GMRES smoothing (Saad & Schultz; left Jacobi, CGS, no restart):
 // x = x0 + V_k y_k, x0 = 0 when zero_x0.  All scalar work on the device.
+// ST_FLAG_SSTEP_SMOOTHER: the same minimisation in s-step form (monomial
+// basis by plain applies, one Gram pass, scaled normal equations).
 void smooth(st_handle* h, int l, int prec, int trans, const void* b, void* x, int zero_x0, int its,
             double rtol, void* Vbuf, KState* ks) {
     Level& L = h->lev[l];
@@ -415,6 +419,23 @@ void smooth(st_handle* h, int l, int prec, int trans, const void* b, void* x, in
     auto Vj = [&](int j) { return (void*)(V + (size_t)j * ld * vb); };
     const void* invd = level_invd(h, l, prec);
     const int kd = l == 0 ? KC_DOT : KC_DOT_C, ka = l == 0 ? KC_AXPY : KC_AXPY_C;
+    if (h->opts.flags & ST_FLAG_SSTEP_SMOOTHER) {
+        if (zero_x0) {
+            Timed t(h, kd, n * (int64_t)(3 * vb));
+            launch_scale_norm(s, n, prec, b, invd, Vj(0), h->partials, ks, FIN_INIT_SELF, its, rtol, 1);
+        } else {
+            level_apply(h, l, prec, trans, x, Vj(0), b, invd, nullptr, nullptr);
+        }
+        for (int j = 0; j < its; ++j)
+            level_apply(h, l, prec, trans, Vj(j), Vj(j + 1), nullptr, invd, nullptr, nullptr);
+        {
+            Timed t(h, kd, n * (int64_t)vb * (its + 1));
+            launch_sstep_coefficients(s, n, prec, V, ld, its + 1, rtol, h->gram_part, ks);
+        }
+        Timed t(h, KC_UPDATE, n * (int64_t)vb * (its + 2));
+        launch_update(s, n, prec, prec, x, V, ld, ks, zero_x0, SMAX);
+        return;
+    }
     int nchunk, gx, gy;
     if (l > 0 && sm_fused_plan(L, &nchunk, &gx, &gy)) {
         // small coarse level: two kernels per iteration

@@ -168,6 +168,12 @@ void launch_sm_iteration(hipStream_t s, const Level& L, int prec, int trans, con
 void launch_sm_update(hipStream_t s, const Level& L, int prec, void* x, const void* V, KState* ks,
                       const double* part, int nbn, int its, int zero_x0);
 
+// s-step Jacobi-GMRES smoother: Gram matrix of the basis V[0..nv-1] and the
+// coefficients y, k of KState (nv <= SMAX), partials of gram_partials_doubles().
+size_t gram_partials_doubles();
+void launch_sstep_coefficients(hipStream_t s, long long n, int prec, const void* V, long long ld,
+                               int nv, double rtol, double* part, KState* ks);
+
 // Exact coarsest-level solve by block-tridiagonal factorisation in time.
 constexpr int CD_MAX_PLANE = 2048;        // largest (nx + 1)(ny + 1) it is used for
 constexpr size_t CD_LDS_MAX = 56 * 1024;  // Gauss-Jordan matrix in LDS up to this size

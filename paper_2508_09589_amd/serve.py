@@ -29,8 +29,10 @@ from .solver import Problem
 
 
 class Request:
-    def __init__(self, rid, n, nt, rho, adjoint=False, t_arrive=None, precision="mixed"):
+    def __init__(self, rid, n, nt, rho, adjoint=False, t_arrive=None, precision="mixed",
+                 smoother="sstep"):
         self.id = rid
+        self.smoother = smoother
         self.n, self.nt = int(n), int(nt)
         self.rho = rho                      # host array [nt, n, n] or [n, n]
         self.adjoint = bool(adjoint)
@@ -64,7 +66,7 @@ def footprint(n, nt, time_varying, precision):
 def _gpu_problem(req, device, stream):
     rho = torch.as_tensor(req.rho, dtype=torch.float64)
     return Problem(req.n, req.n, req.nt, rho, precision=req.precision, device=device,
-                   stream=stream)
+                   stream=stream, smoother=req.smoother)
 
 
 class Server:

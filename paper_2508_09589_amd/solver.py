@@ -30,12 +30,15 @@ class Problem:
     "gmres" (the paper's Jacobi-GMRES coarse solve, §3.2).
     coarsening: "semi" (Algorithm 1) or "full" (every level halves space and
     time, the comparison of §5.1.2).
+    smoother: "gmres" (Jacobi-GMRES by Arnoldi, §3.2) or "sstep" (the same
+    minimisation from the Gram matrix of the monomial Krylov basis).
     """
 
     def __init__(self, nx, ny, nt, rho, dx=None, dt=None, k_ins=1e-3, k_con=1.0, p_k=3.0,
                  c_ins=1.0, c_con=1.0, p_c=1.0, patches=((0, 0.5, 0.05),), q0=1.0, ic=None,
                  source=None, precision="fp64", filter_r=0.0, device="cuda", stream=None,
-                 time_kernels=False, coarse="direct", coarsening="semi", **opt_overrides):
+                 time_kernels=False, coarse="direct", coarsening="semi", smoother="gmres",
+                 **opt_overrides):
         self.lib = L.load()
         self.device = torch.device(device)
         self.nx, self.ny, self.nt = int(nx), int(ny), int(nt)
@@ -65,6 +68,10 @@ class Problem:
             raise ValueError(f"coarsening must be 'semi' or 'full', not {coarsening!r}")
         if coarsening == "full":
             self.opts.flags |= L.ST_FLAG_FULL_COARSENING
+        if smoother not in ("gmres", "sstep"):
+            raise ValueError(f"smoother must be 'gmres' or 'sstep', not {smoother!r}")
+        if smoother == "sstep":
+            self.opts.flags |= L.ST_FLAG_SSTEP_SMOOTHER
         for k, v in opt_overrides.items():
             if not hasattr(self.opts, k):
                 raise KeyError(k)

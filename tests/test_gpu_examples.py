@@ -52,12 +52,15 @@ def test_example_state_pnorm_adjoint(torch_cuda, variant, full):
     p.close()
 
 
+@pytest.mark.parametrize("smoother", ["gmres", "sstep"])
 @pytest.mark.parametrize("variant", ["1B", "2B"])
-def test_example_mixed_precision_and_uniform_design(torch_cuda, variant):
+def test_example_mixed_precision_and_uniform_design(torch_cuda, variant, smoother):
     """Mixed precision (FP32 V-cycle, BF16 coarse stencils) on the uniform
-    start design still reaches the direct solution."""
+    start design still reaches the direct solution, with either form of the
+    smoother."""
     c = _case(variant, 24, 48, False, design="uniform")
-    p = c.problem(max_coarse_nodes=200, rtol=1e-12, precision="mixed", bf16_from_level=1)
+    p = c.problem(max_coarse_nodes=200, rtol=1e-12, precision="mixed", bf16_from_level=1,
+                  smoother=smoother)
     T, info = p.solve()
     assert rel(T.cpu().numpy(), solve_direct(c.Jm, c.fm)) <= 1e-10
     p.close()

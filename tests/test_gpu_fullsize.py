@@ -1,6 +1,7 @@
 """Full-size GPU checks, in the configuration the benchmark times (mixed
-precision, FGMRES(30) on the medium grid, FGMRES(20) on the large one, relative
-residual 1e-8).  The FP64 oracle recomputes the residual of the GPU solution
+precision with BF16 coarse stencils from level 1, s-step smoothing,
+FGMRES(30) on the medium grid, FGMRES(20) on the large one, relative residual
+1e-8).  The FP64 oracle recomputes the residual of the GPU solution
 from its own element matrices: at every node of the medium grid (256^2 x 256,
 17M nodes), at sampled nodes of the large one (512^2 x 1024, 269M nodes),
 where a full oracle sweep would not fit a test's time."""
@@ -32,7 +33,8 @@ def _workload(name, **kw):
     rho = workload_density(name)
     g = Grid(w["nx"], w["ny"], w["nt"], 1.0 / w["nx"], 1.0 / w["nt"])
     p = Problem(w["nx"], w["ny"], w["nt"], torch.tensor(rho), precision="mixed",
-                restart=20 if name == "large" else 30, rtol=1e-8, **kw)
+                restart=20 if name == "large" else 30, rtol=1e-8, bf16_from_level=1,
+                smoother="sstep", **kw)
     return p, g, rho
 
 

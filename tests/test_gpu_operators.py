@@ -210,6 +210,40 @@ def test_smoother_matches_oracle_gmres(torch_cuda, level):
     p.close()
 
 
+@pytest.mark.parametrize("level", [0, 1, 2])
+def test_sstep_smoother_matches_oracle(torch_cuda, level):
+    """One smoothing in s-step form (10 monomial Krylov vectors, Gram matrix,
+    scaled normal equations) on a level, from zero and from x0, forward and
+    transposed: the preconditioned residual it reaches is the minimum that
+    Arnoldi GMRES reaches over the same space (1e-7 relative: the minimum is
+    a well-conditioned quantity), while x itself agrees with the oracle's
+    s-step smoother only as far as the conditioning of the monomial Gram
+    matrix allows (about 2e-5 measured here; bound 1e-3)."""
+    from oracle.krylov import gmres_jacobi_sstep
+    c = Case(16, 16, 16, tv=True, seed=9, max_coarse_nodes=200)
+    p = c.problem(max_coarse_nodes=200, smoother="sstep")
+    A, masks, Pm = c.ops
+    rng = np.random.default_rng(4)
+    b = rng.standard_normal(A[level].shape[0])
+    b[masks[level]] = 0.0
+    x0 = rng.standard_normal(A[level].shape[0]) * 0.1
+    shp = p.level_shape(level)
+    for trans in (False, True):
+        Al = A[level].T.tocsr() if trans else A[level]
+        dinv = 1.0 / Al.diagonal()
+        for start in (None, x0):
+            xg = p.debug_smooth(level, _t(b).reshape(shp),
+                                None if start is None else _t(start).reshape(shp), 10, 1e-6,
+                                trans).cpu().numpy().ravel()
+            xa, _, _ = gmres_jacobi(Al, b, start, 10, 1e-6)
+            xs, _, _ = gmres_jacobi_sstep(Al, b, start, 10, 1e-6)
+            ra = np.linalg.norm(dinv * (b - Al @ xa))
+            rg = np.linalg.norm(dinv * (b - Al @ xg))
+            assert abs(rg - ra) <= 1e-7 * ra, (trans, rg, ra)
+            assert rel(xg, xs) < 1e-3, (trans, rel(xg, xs))
+    p.close()
+
+
 @pytest.mark.parametrize("tv", [False, True])
 @pytest.mark.parametrize("coarse,full", [("gmres", False), ("direct", False), ("direct", True)])
 def test_vcycle_matches_oracle(torch_cuda, tv, coarse, full):

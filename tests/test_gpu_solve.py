@@ -102,3 +102,22 @@ def test_full_coarsening_solve_parity(torch_cuda, precision):
     lam, _ = p.adjoint(p.load_vector())
     assert rel(lam.cpu().numpy(), solve_adjoint_direct(c.Jm, c.f, c.mask)) <= 1e-10
     p.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("tv", [False, True])
+def test_sstep_smoother_solve_parity(torch_cuda, precision, tv):
+    """FGMRES with s-step-smoothed V-cycles reaches the direct solution (state
+    and adjoint) in the iterations the Arnoldi-smoothed solver needs (+-1)."""
+    c = Case(32, 32, 32, tv=tv, seed=41)
+    p = c.problem(precision=precision, rtol=1e-12, smoother="sstep")
+    T, info = p.solve()
+    assert info.true_rel_res <= 1e-12
+    assert rel(T.cpu().numpy(), solve_direct(c.Jm, c.fm)) <= 1e-10
+    lam, _ = p.adjoint(p.load_vector())
+    assert rel(lam.cpu().numpy(), solve_adjoint_direct(c.Jm, c.f, c.mask)) <= 1e-10
+    q = c.problem(precision=precision, rtol=1e-12)
+    _, ref = q.solve()
+    assert abs(info.iterations - ref.iterations) <= 1, (info.iterations, ref.iterations)
+    p.close()
+    q.close()
