@@ -17,7 +17,8 @@ constexpr int GR_MAXNV = SMAX + 1;
 constexpr int GR_MAXP = GR_MAXNV * (GR_MAXNV + 1) / 2;
 constexpr long long GR_MAX_BLOCKS = 1024;
 
-size_t gram_partials_doubles() { return (size_t)GR_MAX_BLOCKS * GR_MAXP; }
+// [GR_MAXP][GR_MAX_BLOCKS] workgroup partials, then GR_MAXP summed entries.
+size_t gram_partials_doubles() { return (size_t)GR_MAX_BLOCKS * GR_MAXP + GR_MAXP; }
 
 static unsigned gram_grid(long long n) {
     long long nb = (n + 8LL * GR_THREADS - 1) / (8LL * GR_THREADS);
@@ -36,7 +37,8 @@ template <typename T> struct GrVec;
 template <> struct GrVec<float> { using type = float4; };
 template <> struct GrVec<double> { using type = double4; };
 
-// part[block][p], p = index of the pair (a <= b) in row-major upper order.
+// part[p][block] (row stride GR_MAX_BLOCKS), p = index of the pair (a <= b)
+// in row-major upper order.
 // Four consecutive elements per thread per step when the basis is aligned
 // (ld a multiple of 4, base 16-byte aligned), a scalar tail after them.
 template <typename T, int NV>
@@ -91,78 +93,135 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram(long long n, const T* __res
         double s = 0.0;
 #pragma unroll
         for (int q = 0; q < GR_THREADS / 64; ++q) s += red[q][p];
-        part[(long long)blockIdx.x * NP + p] = s;
+        part[(long long)p * GR_MAX_BLOCKS + blockIdx.x] = s;
     }
 }
 
-// Sum the partials (each pair by one thread, in workgroup order), then thread
-// 0 picks the number m of vectors and the coefficients y:
+// One workgroup per pair p sums its partials (thread t adds workgroups t,
+// t + 256, ... in order, then a fixed tree) into gsum[p]; the last workgroup
+// to arrive (KState::counter) takes the serial part on its thread 0: it picks
+// the number m of vectors and the coefficients y:
 //   scale s_d = 1/sqrt(G_dd); Gs = S G S;
 //   for m = 1..k: extend the Cholesky factor of Gs[1..m][1..m] by one row
 //   (stop before a pivot <= 0 or a zero vector); z = L^{-1} Gs[1..m][0];
 //   res^2 = 1 - |z|^2; stop at the first m with res^2 <= rtol^2;
 //   y_i = yhat_i s_{i+1} / s_0 with L^T yhat = z.
+// The serial part is unrolled for the basis size NV so that G, the factor, z
+// and y stay in registers (a dependent chain through memory would cost tens
+// of microseconds).
+template <int NV>
 __global__ __launch_bounds__(GR_THREADS) void k_sstep_solve(const double* __restrict__ part,
-                                                            int nb, int nv, double rtol,
-                                                            KState* ks) {
-    __shared__ double G[GR_MAXP];
-    __shared__ double Lf[GR_MAXNV][GR_MAXNV];
-    __shared__ double sc[GR_MAXNV], z[GR_MAXNV], gs0[GR_MAXNV];
-    const int np = nv * (nv + 1) / 2;
-    for (int p = threadIdx.x; p < np; p += blockDim.x) {
-        double s = 0.0;
-        for (int b = 0; b < nb; ++b) s += part[(long long)b * np + p];
-        G[p] = s;
+                                                            int nb, double rtol, KState* ks,
+                                                            double* gsum) {
+    constexpr int NP = NV * (NV + 1) / 2, K = NV - 1;
+    __shared__ double red[GR_THREADS / 64];
+    __shared__ int amlast;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    {
+        const int p = blockIdx.x;
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < (int)(GR_MAX_BLOCKS / GR_THREADS); ++q) {
+            const int b = threadIdx.x + GR_THREADS * q;
+            if (b < nb) v += part[(long long)p * GR_MAX_BLOCKS + b];
+        }
+        v = gr_wave_sum(v);
+        if (lane == 0) red[wv] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < GR_THREADS / 64; ++q) t += red[q];
+            gsum[p] = t;
+        }
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned prev = atomicAdd(&ks->counter, 1u);
+        amlast = (prev == gridDim.x - 1);
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    auto gidx = [&](int a, int b) {   // a <= b
-        return a * nv - a * (a - 1) / 2 + (b - a);
-    };
+    if (!amlast || threadIdx.x != 0) return;
+    __threadfence();
+    ks->counter = 0u;
+    double G[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) G[p] = gsum[p];
+    auto gidx = [](int a, int b) { return a * NV - a * (a - 1) / 2 + (b - a); };   // a <= b
     const double g00 = G[0];
     int bad = !isfinite(g00);
     int m = 0;
     double res2 = 1.0;
+    double y[K > 0 ? K : 1];
+#pragma unroll
+    for (int i = 0; i < K; ++i) y[i] = 0.0;
     if (g00 > 0.0 && !bad) {
-        for (int d = 0; d < nv; ++d) {
+        double sc[NV];
+#pragma unroll
+        for (int d = 0; d < NV; ++d) {
             const double gd = G[gidx(d, d)];
             if (!isfinite(gd)) bad = 1;
             sc[d] = gd > 0.0 ? 1.0 / sqrt(gd) : 0.0;
         }
-        for (int d = 1; d < nv; ++d) gs0[d - 1] = G[gidx(0, d)] * sc[0] * sc[d];
+        double Lf[K > 0 ? K : 1][K > 0 ? K : 1], z[K > 0 ? K : 1];
+        bool stop = bad != 0;
         double zz = 0.0;
-        for (int r = 0; r < nv - 1 && !bad; ++r) {
-            const int dr = r + 1;
-            if (sc[dr] == 0.0) break;
-            // row r of L: L[r][c] = (Gs[r][c] - sum_{e<c} L[r][e] L[c][e]) / L[c][c]
-            for (int c = 0; c < r; ++c) {
-                double v = G[gidx(c + 1, dr)] * sc[c + 1] * sc[dr];
-                for (int e = 0; e < c; ++e) v -= Lf[r][e] * Lf[c][e];
-                Lf[r][c] = v / Lf[c][c];
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            if (!stop) {
+                if (sc[r + 1] == 0.0) {
+                    stop = true;
+                } else {
+#pragma unroll
+                    for (int c = 0; c < r; ++c) {
+                        double v = G[gidx(c + 1, r + 1)] * sc[c + 1] * sc[r + 1];
+#pragma unroll
+                        for (int e = 0; e < c; ++e) v -= Lf[r][e] * Lf[c][e];
+                        Lf[r][c] = v / Lf[c][c];
+                    }
+                    double piv = 1.0;   // Gs[r][r] = 1 by the scaling
+#pragma unroll
+                    for (int e = 0; e < r; ++e) piv -= Lf[r][e] * Lf[r][e];
+                    if (!(piv > 0.0)) {
+                        stop = true;
+                    } else {
+                        Lf[r][r] = sqrt(piv);
+                        double v = G[gidx(0, r + 1)] * sc[0] * sc[r + 1];
+#pragma unroll
+                        for (int e = 0; e < r; ++e) v -= Lf[r][e] * z[e];
+                        z[r] = v / Lf[r][r];
+                        zz += z[r] * z[r];
+                        m = r + 1;
+                        res2 = fmax(1.0 - zz, 0.0);
+                        if (res2 <= rtol * rtol) stop = true;
+                    }
+                }
             }
-            double piv = 1.0;   // Gs[r][r] = 1 by the scaling
-            for (int e = 0; e < r; ++e) piv -= Lf[r][e] * Lf[r][e];
-            if (!(piv > 0.0)) break;
-            Lf[r][r] = sqrt(piv);
-            double v = gs0[r];
-            for (int e = 0; e < r; ++e) v -= Lf[r][e] * z[e];
-            z[r] = v / Lf[r][r];
-            zz += z[r] * z[r];
-            m = r + 1;
-            res2 = fmax(1.0 - zz, 0.0);
-            if (res2 <= rtol * rtol) break;
         }
-        // back substitution L^T yhat = z, unscaled into ks->y
-        for (int i = m - 1; i >= 0; --i) {
-            double v = z[i];
-            for (int c = i + 1; c < m; ++c) v -= Lf[c][i] * ks->y[c];
-            ks->y[i] = v / Lf[i][i];
+        // back substitution L^T yhat = z over the first m rows, unscaled
+#pragma unroll
+        for (int i = K - 1; i >= 0; --i) {
+            if (i < m) {
+                double v = z[i];
+#pragma unroll
+                for (int c = i + 1; c < K; ++c)
+                    if (c < m) v -= Lf[c][i] * y[c];
+                y[i] = v / Lf[i][i];
+            }
         }
-        for (int i = 0; i < m; ++i) ks->y[i] *= sc[i + 1] / sc[0];
-        for (int i = 0; i < m; ++i)
-            if (!isfinite(ks->y[i])) bad = 1;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            if (i < m) {
+                y[i] *= sc[i + 1] / sc[0];
+                if (!isfinite(y[i])) bad = 1;
+            }
+        }
     }
     if (bad) m = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        if (i < m) ks->y[i] = y[i];
     ks->k = m;
     ks->beta = sqrt(g00);
     ks->est = sqrt(res2) * sqrt(g00);
@@ -197,7 +256,18 @@ void launch_sstep_coefficients(hipStream_t s, long long n, int prec, const void*
         gram_dispatch<float>(s, nb, n, (const float*)V, ld, vec, nv, part);
     else
         gram_dispatch<double>(s, nb, n, (const double*)V, ld, vec, nv, part);
-    hipLaunchKernelGGL(k_sstep_solve, dim3(1), dim3(GR_THREADS), 0, s, part, (int)nb, nv, rtol, ks);
+#define ST_SOLVE_CASE(NVV)                                                                     \
+    case NVV:                                                                                  \
+        hipLaunchKernelGGL((k_sstep_solve<NVV>), dim3(NVV * (NVV + 1) / 2), dim3(GR_THREADS), 0, \
+                           s, part, (int)nb, rtol, ks, part + GR_MAX_BLOCKS * GR_MAXP);       \
+        break;
+    switch (nv) {
+        ST_SOLVE_CASE(2) ST_SOLVE_CASE(3) ST_SOLVE_CASE(4) ST_SOLVE_CASE(5) ST_SOLVE_CASE(6)
+        ST_SOLVE_CASE(7) ST_SOLVE_CASE(8) ST_SOLVE_CASE(9) ST_SOLVE_CASE(10) ST_SOLVE_CASE(11)
+        ST_SOLVE_CASE(12) ST_SOLVE_CASE(13) ST_SOLVE_CASE(14) ST_SOLVE_CASE(15) ST_SOLVE_CASE(16)
+        default: break;
+    }
+#undef ST_SOLVE_CASE
 }
 
 }  // namespace st
