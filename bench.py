@@ -35,17 +35,18 @@ def log(msg):
 
 
 def workload_problem(name, precision, time_kernels, bf16_from_level=0, max_it=1000,
-                     smoother="gmres"):
+                     smoother="gmres", restart=None, coarse="direct"):
     import torch
     from paper_2508_09589_amd import Problem
     from paper_2508_09589_amd.inputs import WORKLOADS, workload_density
     w = WORKLOADS[name]
     rho = workload_density(name)
-    restart = 20 if name == "large" else 30
+    if restart is None:
+        restart = 20 if name == "large" else 30
     t0 = time.perf_counter()
     p = Problem(w["nx"], w["ny"], w["nt"], torch.tensor(rho), precision=precision, restart=restart,
                 rtol=1e-8, time_kernels=time_kernels, bf16_from_level=bf16_from_level,
-                smoother=smoother,
+                smoother=smoother, coarse=coarse,
                 max_it=max_it)
     torch.cuda.synchronize()
     log(f"{name} {precision}: setup {time.perf_counter() - t0:.2f} s, {p.n_nodes} nodes, "
@@ -182,7 +183,8 @@ def run(args):
     from paper_2508_09589_amd import _lib as L
 
     p, t_setup, restart = workload_problem(args.workload, args.precision, True,
-                                           args.bf16_from_level, args.max_it, args.smoother)
+                                           args.bf16_from_level, args.max_it, args.smoother,
+                                           args.restart, args.coarse)
     n_nodes = p.n_nodes
     # Warm-up solves time every kernel class to find the dominant one.
     warm = []
@@ -231,7 +233,8 @@ def run(args):
                    "levels": last["levels"], "iterations": last["iterations"],
                    "true_rel_res": last["true_rel_res"], "setup_s": t_setup,
                    "converged": last["true_rel_res"] <= 1e-8,
-                   "bf16_from_level": args.bf16_from_level, "smoother": args.smoother},
+                   "bf16_from_level": args.bf16_from_level, "smoother": args.smoother,
+                   "coarse": args.coarse},
         "roofline": {"bound": "hbm", "kernel_class": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": recorded_traffic(args.workload, args.precision),
@@ -245,7 +248,8 @@ def run(args):
     del T
     torch.cuda.empty_cache()
     if args.compare_fp64 and args.precision != "fp64":
-        q, ts, _ = workload_problem(args.workload, "fp64", False, 0, args.max_it, args.smoother)
+        q, ts, _ = workload_problem(args.workload, "fp64", False, 0, args.max_it, args.smoother,
+                                    args.restart, args.coarse)
         Tq, iq = q.solve(allow_not_converged=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -471,6 +475,10 @@ def main():
     ap.add_argument("--smoother", default="sstep", choices=["gmres", "sstep"],
                     help="Jacobi-GMRES smoothing in s-step form (one Gram pass) or by "
                          "Arnoldi steps")
+    ap.add_argument("--restart", type=int, default=None,
+                    help="FGMRES restart length (default 30; 20 for the large workload)")
+    ap.add_argument("--coarse", default="direct", choices=["direct", "gmres"],
+                    help="coarsest-level solve: exact, or the paper's Jacobi-GMRES")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare-fp64", action="store_true")
     ap.add_argument("--max-it", type=int, default=400)
