@@ -586,6 +586,68 @@ __global__ __launch_bounds__(VEC_THREADS) void k_maxpy4(long long n, TW* __restr
     block_finish<1>(acc, 1, partials, ks, mode, j, nullptr);
 }
 
+// CGS2 middle passes in one stream (FP64 outer basis): w' = w - sum_d coef_d
+// V_d with the first projections, stored, and the second projections V_d . w'
+// accumulated from the stored values -- the same sums, in the same order, as
+// a maxpy followed by a separate multi-dot over w'.
+template <int MAXD>
+__global__ __launch_bounds__(VEC_THREADS) void k_maxpy_mdot4(long long n, double* __restrict__ w,
+                                                             const double* __restrict__ V,
+                                                             long long ldv, int nd,
+                                                             double* __restrict__ partials,
+                                                             KState* ks, int j) {
+    if (ks->done) return;
+    __shared__ double c[MAXD];
+    if (threadIdx.x < MAXD) c[threadIdx.x] = (int)threadIdx.x < nd ? ks->coef[threadIdx.x] : 0.0;
+    __syncthreads();
+    double acc[MAXD];
+#pragma unroll
+    for (int d = 0; d < MAXD; ++d) acc[d] = 0.0;
+    const long long n4 = n >> 2;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n4; q += stride) {
+        double wv[4];
+        ld4(w + 4 * q, wv);
+#pragma unroll
+        for (int d = 0; d < MAXD; ++d)
+            if (d < nd) {
+                double vv[4];
+                ld4(V + (long long)d * ldv + 4 * q, vv);
+                const double cd = c[d];
+                wv[0] -= cd * vv[0]; wv[1] -= cd * vv[1]; wv[2] -= cd * vv[2]; wv[3] -= cd * vv[3];
+            }
+        st4(w + 4 * q, wv);
+#pragma unroll
+        for (int d = 0; d < MAXD; ++d)
+            if (d < nd) {
+                double vv[4];
+                ld4(V + (long long)d * ldv + 4 * q, vv);
+                acc[d] += vv[0] * wv[0] + vv[1] * wv[1] + vv[2] * wv[2] + vv[3] * wv[3];
+            }
+    }
+    for (long long i = 4 * n4 + blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += stride) {
+        double wv = w[i];
+#pragma unroll
+        for (int d = 0; d < MAXD; ++d)
+            if (d < nd) wv -= c[d] * V[(long long)d * ldv + i];
+        w[i] = wv;
+#pragma unroll
+        for (int d = 0; d < MAXD; ++d)
+            if (d < nd) acc[d] += V[(long long)d * ldv + i] * wv;
+    }
+    block_finish<MAXD>(acc, nd, partials, ks, FIN_PROJ2, j, nullptr);
+}
+
+bool launch_maxpy_mdot(hipStream_t s, long long n, double* w, const double* V, long long ldv,
+                       int nd, double* partials, KState* ks, int j) {
+    if (!(ldv % 4 == 0 && al4(w, 8) && al4(V, 8)) || nd > KMAX) return false;
+    const unsigned nb4 = red_grid4(n);
+    hipLaunchKernelGGL((k_maxpy_mdot4<KMAX>), dim3(nb4), dim3(VEC_THREADS), 0, s, n, w, V, ldv,
+                       nd, partials, ks, j);
+    finish<KMAX>(s, nb4, nd, partials, ks, FIN_PROJ2, j, nullptr);
+    return true;
+}
+
 template <int MAXD>
 static void mdot_dispatch(hipStream_t s, long long n, int pw, int pv, const void* w,
                           const void* V, long long ldv, int nd, double* partials, KState* ks,

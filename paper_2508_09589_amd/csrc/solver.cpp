@@ -774,17 +774,16 @@ st_status fgmres(st_handle* h, const double* f, const double* fnorm_dev, double*
                 launch_mdot(s, n, 0, 0, Vj(j + 1), h->V, ld, j + 1, h->partials, ks, FIN_PROJ1, j, KMAX);
             }
             {
-                // CGS2: subtract the first projections, project again, subtract
-                // the corrections and take the norm (three streaming passes).
-                // (A second pass only where the DGKS test asks for one saved
-                // nothing: with a good preconditioner the first pass cancels
-                // most of w at every iteration, so the test always asks.)
+                // CGS2: subtract the first projections and project again in one
+                // pass, then subtract the corrections and take the norm.
+                // (A second projection only where the DGKS test asks for one
+                // saved nothing: with a good preconditioner the first pass
+                // cancels most of w at every iteration, so the test always asks.)
                 Timed t(h, KC_OUTER, n * 8 * (j + 3));
-                launch_maxpy(s, n, 0, 0, Vj(j + 1), h->V, ld, j + 1, h->partials, ks, FIN_NONE, j, KMAX);
-            }
-            {
-                Timed t(h, KC_OUTER, n * 8 * (j + 2));
-                launch_mdot(s, n, 0, 0, Vj(j + 1), h->V, ld, j + 1, h->partials, ks, FIN_PROJ2, j, KMAX);
+                if (!launch_maxpy_mdot(s, n, Vj(j + 1), h->V, ld, j + 1, h->partials, ks, j)) {
+                    launch_maxpy(s, n, 0, 0, Vj(j + 1), h->V, ld, j + 1, h->partials, ks, FIN_NONE, j, KMAX);
+                    launch_mdot(s, n, 0, 0, Vj(j + 1), h->V, ld, j + 1, h->partials, ks, FIN_PROJ2, j, KMAX);
+                }
             }
             {
                 Timed t(h, KC_OUTER, n * 8 * (j + 3));

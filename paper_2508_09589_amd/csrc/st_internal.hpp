@@ -147,6 +147,9 @@ void launch_mdot(hipStream_t s, long long n, int prec_w, int prec_v, const void*
                  int j, int maxd);
 void launch_maxpy(hipStream_t s, long long n, int prec_w, int prec_v, void* w, const void* V,
                   long long ldv, int nd, double* partials, KState* ks, int mode, int j, int maxd);
+// Fused CGS2 middle passes (FP64): false when the layout does not allow it.
+bool launch_maxpy_mdot(hipStream_t s, long long n, double* w, const double* V, long long ldv,
+                       int nd, double* partials, KState* ks, int j);
 void launch_update(hipStream_t s, long long n, int prec_x, int prec_v, void* x, const void* V,
                    long long ldv, KState* ks, int zero_x0, int maxd);
 void launch_init_state(hipStream_t s, KState* ks, int maxit, double rtol, int scale_update,
