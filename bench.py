@@ -242,6 +242,10 @@ def run(args):
                      "avg_launch_ms": ms / launches if launches else None,
                      "bytes_per_launch": nbytes / launches if launches else None},
         "kernel_classes_warmup_ms": {c: round(v["ms"], 3) for c, v in kern.items()},
+        # algorithmic bytes / GPU time of every kernel class in the warm-up
+        # solve (GB/s; against the 8 TB/s HBM peak)
+        "kernel_classes_warmup_gbs": {c: round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1)
+                                      for c, v in kern.items() if v["ms"] > 0 and v["bytes"] > 0},
         "coarse_solve_share": kern.get("coarse_solve", {}).get("ms", 0.0) / total_ms if total_ms else None,
     }
     p.close()
