@@ -65,7 +65,10 @@ enum {
     ST_FLAG_SSTEP_SMOOTHER = 16, /* smoothing in s-step form: the same GMRES
                                    minimisation from a monomial Krylov basis and
                                    its Gram matrix (one pass for all inner
-                                   products instead of Arnoldi's growing ones) */
+                                   products instead of Arnoldi's growing ones);
+                                   smoothings of more than 10 iterations keep
+                                   the Arnoldi form (the monomial basis is too
+                                   ill-conditioned beyond that)                 */
     ST_FLAG_COARSE_GMRES = 4    /* coarsest level: Jacobi-GMRES (coarse_max_it,
                                    coarse_rtol, coarse_restart) as in §3.2, instead
                                    of the default exact solve by block-tridiagonal

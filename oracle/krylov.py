@@ -94,6 +94,10 @@ def gmres_jacobi(A, b, x0=None, maxit=10, rtol=1e-6, restart=None, dinv=None):
     return x, its, beta / beta0
 
 
+SSTEP_MIN_PIVOT = 1e-11
+SSTEP_MAX_ITS = 10      # longer smoothings keep the Arnoldi form
+
+
 def gmres_jacobi_sstep(A, b, x0=None, maxit=10, rtol=1e-6, dinv=None):
     """The Jacobi-GMRES smoother's minimisation written without Arnoldi:
     over x in x0 + K_m(M, r0), M = D^{-1} A, r0 = D^{-1}(b - A x0), minimise
@@ -104,9 +108,13 @@ def gmres_jacobi_sstep(A, b, x0=None, maxit=10, rtol=1e-6, dinv=None):
     squared residual is G[0,0] - y . G[1:m+1, 0].  m is the smallest count
     whose residual is <= rtol ||r0|| (the GMRES stopping rule), else maxit.
     In exact arithmetic this is GMRES(maxit) without restart, stopped by the
-    same test.  A non-positive Cholesky pivot (the basis became dependent:
-    the Krylov space is invariant and the residual is already minimal) stops
-    at the vectors before it.
+    same test.  The normal equations are factored one row at a time in the
+    basis scaled to unit length; the pivot of row m is the squared sine of
+    the angle between w_m and the earlier vectors.  A pivot below
+    SSTEP_MIN_PIVOT stops at the vectors before it: either the space is
+    invariant (the residual is already minimal) or the monomial basis has
+    become too ill-conditioned for the equations to carry information (the
+    pivots fall about tenfold per vector; below ~1e-11 they are rounding).
 
     Returns (x, m, residual / ||r0||)."""
     n = b.shape[0]
@@ -127,21 +135,28 @@ def gmres_jacobi_sstep(A, b, x0=None, maxit=10, rtol=1e-6, dinv=None):
     nz = np.diag(G) > 0
     sc[nz] = 1.0 / np.sqrt(np.diag(G)[nz])
     Gs = G * np.outer(sc, sc)
-    m_best, y_best, res_best = 0, np.zeros(0), 1.0
-    for m in range(1, maxit + 1):
-        Gm = Gs[1:m + 1, 1:m + 1]
-        if not nz[m]:
+    # Cholesky factor L of Gs[1:, 1:], extended by one row per vector, and
+    # z = L^{-1} Gs[1:, 0]; the squared residual with m vectors is 1 - |z[:m]|^2
+    L = np.zeros((maxit, maxit))
+    z = np.zeros(maxit)
+    m, res2 = 0, 1.0
+    for r in range(maxit):
+        if not nz[r + 1]:
             break
-        try:
-            np.linalg.cholesky(Gm)
-        except np.linalg.LinAlgError:
+        for c in range(r):
+            L[r, c] = (Gs[r + 1, c + 1] - L[r, :c] @ L[c, :c]) / L[c, c]
+        piv = Gs[r + 1, r + 1] - L[r, :r] @ L[r, :r]
+        if not piv > SSTEP_MIN_PIVOT:
             break
-        ys = np.linalg.solve(Gm, Gs[1:m + 1, 0])
-        res2 = max(1.0 - ys @ Gs[1:m + 1, 0], 0.0)
-        m_best, y_best, res_best = m, ys * sc[1:m + 1] / sc[0], np.sqrt(res2)
+        L[r, r] = np.sqrt(piv)
+        z[r] = (Gs[r + 1, 0] - L[r, :r] @ z[:r]) / L[r, r]
+        m = r + 1
+        res2 = max(1.0 - z[:m] @ z[:m], 0.0)
         if res2 <= rtol * rtol:
             break
-    return x0 + y_best @ W[:m_best], m_best, res_best
+    ys = np.linalg.solve(L[:m, :m].T, z[:m]) if m else np.zeros(0)
+    y = ys * sc[1:m + 1] / sc[0]
+    return x0 + y @ W[:m], m, np.sqrt(res2)
 
 
 class VCycle:
@@ -150,7 +165,8 @@ class VCycle:
     coarse="gmres": the coarsest level is solved with Jacobi-GMRES as in §3.2;
     coarse="direct": it is solved exactly (sparse LU of the coarsest operator).
     smoother="gmres": Jacobi-GMRES by Arnoldi; "sstep": the same minimisation
-    through the Gram matrix of the monomial Krylov basis (gmres_jacobi_sstep).
+    through the Gram matrix of the monomial Krylov basis (gmres_jacobi_sstep)
+    for smoothings of at most SSTEP_MAX_ITS iterations, Arnoldi beyond.
     """
 
     def __init__(self, A, Pm, smooth_its=10, smooth_rtol=1e-6, coarse_its=200,
@@ -182,7 +198,7 @@ class VCycle:
         return self._smooth(A, b, x, dinv)
 
     def _smooth(self, A, b, x0, dinv):
-        if self.smoother == "sstep":
+        if self.smoother == "sstep" and self.si <= SSTEP_MAX_ITS:
             return gmres_jacobi_sstep(A, b, x0, self.si, self.sr, dinv)[0]
         return gmres_jacobi(A, b, x0, self.si, self.sr, None, dinv)[0]
 

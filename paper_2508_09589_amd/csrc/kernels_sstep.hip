@@ -16,6 +16,12 @@ constexpr int GR_THREADS = 256;
 constexpr int GR_MAXNV = SMAX + 1;
 constexpr int GR_MAXP = GR_MAXNV * (GR_MAXNV + 1) / 2;
 constexpr long long GR_MAX_BLOCKS = 1024;
+// Smallest accepted pivot of the scaled normal equations (the squared sine
+// of the angle between a new basis vector and the earlier ones).  The
+// monomial basis loses about a decade per vector; below ~1e-11 the pivot is
+// rounding and the equations no longer carry information, so the basis is cut
+// before that vector.
+constexpr double SSTEP_MIN_PIVOT = 1e-11;
 
 // [GR_MAXP][GR_MAX_BLOCKS] workgroup partials, then GR_MAXP summed entries.
 size_t gram_partials_doubles() { return (size_t)GR_MAX_BLOCKS * GR_MAXP + GR_MAXP; }
@@ -103,7 +109,8 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram(long long n, const T* __res
 // the number m of vectors and the coefficients y:
 //   scale s_d = 1/sqrt(G_dd); Gs = S G S;
 //   for m = 1..k: extend the Cholesky factor of Gs[1..m][1..m] by one row
-//   (stop before a pivot <= 0 or a zero vector); z = L^{-1} Gs[1..m][0];
+//   (stop before a pivot <= SSTEP_MIN_PIVOT or a zero vector);
+//   z = L^{-1} Gs[1..m][0];
 //   res^2 = 1 - |z|^2; stop at the first m with res^2 <= rtol^2;
 //   y_i = yhat_i s_{i+1} / s_0 with L^T yhat = z.
 // The serial part is unrolled for the basis size NV so that G, the factor, z
@@ -183,7 +190,7 @@ __global__ __launch_bounds__(GR_THREADS) void k_sstep_solve(const double* __rest
                     double piv = 1.0;   // Gs[r][r] = 1 by the scaling
 #pragma unroll
                     for (int e = 0; e < r; ++e) piv -= Lf[r][e] * Lf[r][e];
-                    if (!(piv > 0.0)) {
+                    if (!(piv > SSTEP_MIN_PIVOT)) {
                         stop = true;
                     } else {
                         Lf[r][r] = sqrt(piv);

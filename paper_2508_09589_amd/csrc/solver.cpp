@@ -419,7 +419,9 @@ void smooth(st_handle* h, int l, int prec, int trans, const void* b, void* x, in
     auto Vj = [&](int j) { return (void*)(V + (size_t)j * ld * vb); };
     const void* invd = level_invd(h, l, prec);
     const int kd = l == 0 ? KC_DOT : KC_DOT_C, ka = l == 0 ? KC_AXPY : KC_AXPY_C;
-    if (h->opts.flags & ST_FLAG_SSTEP_SMOOTHER) {
+    // The monomial basis stays usable for about ten vectors (its Gram pivots
+    // fall a decade per vector); longer smoothings take the Arnoldi form.
+    if ((h->opts.flags & ST_FLAG_SSTEP_SMOOTHER) && its <= SSTEP_MAX_ITS) {
         if (zero_x0) {
             Timed t(h, kd, n * (int64_t)(3 * vb));
             launch_scale_norm(s, n, prec, b, invd, Vj(0), h->partials, ks, FIN_INIT_SELF, its, rtol, 1);

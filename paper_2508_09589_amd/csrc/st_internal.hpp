@@ -174,6 +174,7 @@ void launch_sm_update(hipStream_t s, const Level& L, int prec, void* x, const vo
 // s-step Jacobi-GMRES smoother: Gram matrix of the basis V[0..nv-1] and the
 // coefficients y, k of KState (nv <= SMAX), partials of gram_partials_doubles().
 size_t gram_partials_doubles();
+constexpr int SSTEP_MAX_ITS = 10;   // longer smoothings use the Arnoldi form
 void launch_sstep_coefficients(hipStream_t s, long long n, int prec, const void* V, long long ld,
                                int nv, double rtol, double* part, KState* ks);
 

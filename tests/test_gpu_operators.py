@@ -244,6 +244,33 @@ def test_sstep_smoother_matches_oracle(torch_cuda, level):
     p.close()
 
 
+@pytest.mark.parametrize("its,tol", [(1, 1e-12), (2, 1e-11), (10, 1e-7), (15, 1e-10)])
+def test_sstep_smoother_basis_sizes(torch_cuda, its, tol):
+    """The smallest and largest s-step bases (2 and 11 vectors): the residual
+    reached is Arnoldi GMRES's minimum; 15 iterations are beyond the monomial
+    basis and take the Arnoldi form (so match Arnoldi to rounding); a zero
+    right-hand side from a zero start gives exactly zero."""
+    c = Case(12, 12, 8, tv=True, seed=13, max_coarse_nodes=200)
+    p = c.problem(max_coarse_nodes=200, smoother="sstep")
+    A, masks, Pm = c.ops
+    rng = np.random.default_rng(3)
+    level = 1
+    b = rng.standard_normal(A[level].shape[0])
+    b[masks[level]] = 0.0
+    shp = p.level_shape(level)
+    Al = A[level]
+    dinv = 1.0 / Al.diagonal()
+    xg = p.debug_smooth(level, _t(b).reshape(shp), None, its, 0.0).cpu().numpy().ravel()
+    xa, ia, _ = gmres_jacobi(Al, b, None, its, 0.0)
+    assert ia == its
+    ra = np.linalg.norm(dinv * (b - Al @ xa))
+    rg = np.linalg.norm(dinv * (b - Al @ xg))
+    assert abs(rg - ra) <= tol * ra, (its, rg, ra)
+    z = p.debug_smooth(level, _t(np.zeros_like(b)).reshape(shp), None, its, 1e-6).cpu().numpy()
+    assert np.all(z == 0.0)
+    p.close()
+
+
 @pytest.mark.parametrize("tv", [False, True])
 @pytest.mark.parametrize("coarse,full", [("gmres", False), ("direct", False), ("direct", True)])
 def test_vcycle_matches_oracle(torch_cuda, tv, coarse, full):

@@ -249,3 +249,19 @@ def test_sstep_smoother_vcycle_same_outer_iterations():
     assert its_s == its_g and rel <= 1e-10
     xs = solve_direct(Jm, fm)
     assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+
+
+def test_sstep_smoother_cuts_an_ill_conditioned_basis():
+    """Past about ten monomial vectors the scaled Gram pivots reach rounding
+    (SSTEP_MIN_PIVOT): the s-step form stops there and returns the minimiser
+    over the vectors it kept -- the residual of Arnoldi GMRES with that many
+    steps -- instead of amplifying rounding."""
+    from oracle.krylov import gmres_jacobi_sstep
+    g, A, b, _ = _system(6, 6, seed=5)
+    dinv = 1.0 / A.diagonal()
+    xs, m, _ = gmres_jacobi_sstep(A, b, None, maxit=15, rtol=0.0, dinv=dinv)
+    assert 8 <= m < 15
+    xg, _, _ = gmres_jacobi(A, b, None, maxit=m, rtol=0.0, dinv=dinv)
+    rs = np.linalg.norm(dinv * (b - A @ xs))
+    rg = np.linalg.norm(dinv * (b - A @ xg))
+    assert rs == pytest.approx(rg, rel=1e-3)   # the last kept pivot is ~1e-11
