@@ -149,6 +149,125 @@ __device__ void kstate_finalize(KState* ks, int mode, int j, const double* sums,
         }
         break;
     }
+    case FIN_DCGS2: {
+        // sums = [s_0..s_{KMAX-1}, t_0..t_{KMAX-1}, alpha, beta, gamma] for
+        // the current vector u (stored times scale[j]) and w = A z_j:
+        // s = Q^T u, t = Q^T w (entries below j), alpha = u.u, beta = u.w,
+        // gamma = w.w.
+        const double* sv = sums;
+        const double* tv = sums + KMAX;
+        const double alpha = sums[2 * KMAX], beta = sums[2 * KMAX + 1], gamma = sums[2 * KMAX + 2];
+        double ss = 0.0, st = 0.0, tt = 0.0;
+        for (int i = 0; i < j; ++i) {
+            ss += sv[i] * sv[i];
+            st += sv[i] * tv[i];
+            tt += tv[i] * tv[i];
+        }
+        const double nu = sqrt(fmax(alpha - ss, 0.0));
+        bool bad = !isfinite(nu) || !(nu > 0.0) || !isfinite(gamma);
+        const double nuinv = bad ? 0.0 : 1.0 / nu;
+        // column j-1 becomes final: u = (w_{j-1} orthogonalised once) / eta,
+        // and u = nu q_j + Q s, so H[0..j-1][j-1] += eta s, H[j][j-1] = eta nu
+        if (j >= 1) {
+            double col[KMAX + 1];
+            for (int i = 0; i < j; ++i) col[i] = ks->hcol[i] + ks->d_eta * sv[i];
+            col[j] = ks->d_eta * nu;
+            for (int i = 0; i < j - 1; ++i) {
+                const double a = col[i], b = col[i + 1];
+                col[i] = ks->cs[i] * a + ks->sn[i] * b;
+                col[i + 1] = -ks->sn[i] * a + ks->cs[i] * b;
+            }
+            const double r = hypot(col[j - 1], col[j]);
+            double c = 1.0, sn = 0.0;
+            if (r != 0.0) {
+                c = col[j - 1] / r;
+                sn = col[j] / r;
+            }
+            col[j - 1] = r;
+            for (int i = 0; i < j; ++i) ks->H[i][j - 1] = col[i];
+            ks->cs[j - 1] = c;
+            ks->sn[j - 1] = sn;
+            const double gj = ks->g[j - 1];
+            ks->g[j] = -sn * gj;
+            ks->g[j - 1] = c * gj;
+        }
+        // column j, provisional: t, c = q_j . w, eta from Pythagoras
+        const double cj = (beta - st) * nuinv;
+        for (int i = 0; i < j; ++i) {
+            ks->hcol[i] = tv[i];
+            ks->ds[i] = sv[i];
+        }
+        ks->hcol[j] = cj;
+        const double eta = sqrt(fmax(gamma - tt - cj * cj, 0.0));
+        const bool brk = !(eta > 1e-14 * sqrt(gamma));
+        // provisional residual estimate with column j as it stands
+        double p0 = cj, p1 = eta;
+        {
+            double col[KMAX + 1];
+            for (int i = 0; i < j; ++i) col[i] = tv[i];
+            col[j] = cj;
+            for (int i = 0; i < j; ++i) {
+                const double a = col[i], b = col[i + 1];
+                col[i] = ks->cs[i] * a + ks->sn[i] * b;
+                col[i + 1] = -ks->sn[i] * a + ks->cs[i] * b;
+            }
+            p0 = col[j];
+        }
+        const double r = hypot(p0, p1);
+        const double est = r != 0.0 ? fabs(p1 / r * ks->g[j]) : fabs(ks->g[j]);
+        ks->est = est;
+        ks->k = j + 1;
+        ks->d_nuinv = nuinv;
+        ks->d_c = cj;
+        ks->d_eta = eta;
+        ks->d_etainv = brk ? 0.0 : 1.0 / eta;
+        ks->d_brk = brk ? 1 : 0;
+        ks->scale[j + 1] = 1.0;   // the update pass stores u_{j+1} normalised
+        bad = bad || !isfinite(est);
+        ks->bad |= bad;
+        ks->pending = (est <= ks->rtol * ks->ref || brk || bad || j + 1 >= ks->maxit) ? 1 : 0;
+        break;
+    }
+    case FIN_DCGS2_LAST: {
+        // sums = [s'_0..s'_j, alpha'] of u_{j+1} against q_0..q_j: column j final
+        double col[KMAX + 2];
+        for (int i = 0; i <= j; ++i) col[i] = ks->hcol[i];
+        if (ks->d_brk) {
+            col[j + 1] = 0.0;
+        } else {
+            double ss = 0.0;
+            for (int i = 0; i <= j; ++i) {
+                col[i] += ks->d_eta * sums[i];
+                ss += sums[i] * sums[i];
+            }
+            col[j + 1] = ks->d_eta * sqrt(fmax(sums[j + 1] - ss, 0.0));
+        }
+        for (int i = 0; i < j; ++i) {
+            const double a = col[i], b = col[i + 1];
+            col[i] = ks->cs[i] * a + ks->sn[i] * b;
+            col[i + 1] = -ks->sn[i] * a + ks->cs[i] * b;
+        }
+        const double r = hypot(col[j], col[j + 1]);
+        double c = 1.0, sn = 0.0;
+        if (r != 0.0) {
+            c = col[j] / r;
+            sn = col[j + 1] / r;
+        }
+        col[j] = r;
+        for (int i = 0; i <= j; ++i) ks->H[i][j] = col[i];
+        ks->cs[j] = c;
+        ks->sn[j] = sn;
+        const double gj = ks->g[j];
+        ks->g[j + 1] = -sn * gj;
+        ks->g[j] = c * gj;
+        ks->est = fabs(ks->g[j + 1]);
+        ks->bad |= !isfinite(ks->est);
+        ks->k = j + 1;
+        ks->done = 1;
+        ks->pending = 0;
+        kstate_solve_y(ks);
+        break;
+    }
     default:
         break;
     }
@@ -279,7 +398,7 @@ __device__ void block_finish(double (&acc)[MAXD], int nd, double* __restrict__ p
     if (gridDim.x > FUSE_MAX) return;   // uniform over the grid
     __threadfence();
     __syncthreads();
-    unsigned* counter = ks ? &ks->counter : (unsigned*)(partials + (long long)RED_BLOCKS * KMAX + KMAX);
+    unsigned* counter = ks ? &ks->counter : (unsigned*)(partials + PARTIALS_COUNTER);
     if (threadIdx.x == 0) {
         const unsigned prev = atomicAdd(counter, 1u);
         amlast = (prev == gridDim.x - 1);
@@ -636,6 +755,129 @@ __global__ __launch_bounds__(VEC_THREADS) void k_maxpy_mdot4(long long n, double
             if (d < nd) acc[d] += V[(long long)d * ldv + i] * wv;
     }
     block_finish<MAXD>(acc, nd, partials, ks, FIN_PROJ2, j, nullptr);
+}
+
+// Delayed CGS2 (outer FGMRES, FP64 basis).  Step j holds clean q_0..q_{j-1}
+// in V[0..j-1], the current vector u (once orthogonalised, not yet cleaned;
+// its value is V[j] * scale[j]) and w = A z_j in V[j+1].  One pass forms all
+// inner products that step needs; after the finalisation the second pass
+// writes q_j = (u - Q s) / nu over V[j] and u_{j+1} = (w - Q t - c q_j) / eta
+// over V[j+1].  Step j thereby re-orthogonalises q_j (lagging by one step)
+// and orthogonalises w once: two streams over the basis instead of the three
+// of classical CGS2.
+constexpr int DC_MAXD = 2 * KMAX + 3;
+static_assert(DC_MAXD <= RED_WIDTH, "reduction width");
+
+__global__ __launch_bounds__(VEC_THREADS) void k_dcgs2_dots(long long n, const double* __restrict__ V,
+                                                           long long ldv, int j,
+                                                           double* __restrict__ partials,
+                                                           KState* ks) {
+    if (ks->done) return;
+    const double us = ks->scale[j];
+    double acc[DC_MAXD];
+#pragma unroll
+    for (int d = 0; d < DC_MAXD; ++d) acc[d] = 0.0;
+    const double* U = V + (long long)j * ldv;
+    const double* W = V + (long long)(j + 1) * ldv;
+    const long long n4 = n >> 2;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n4; q += stride) {
+        double uv[4], wv[4];
+        ld4(U + 4 * q, uv);
+        ld4(W + 4 * q, wv);
+        uv[0] *= us; uv[1] *= us; uv[2] *= us; uv[3] *= us;
+#pragma unroll
+        for (int d = 0; d < KMAX; ++d)
+            if (d < j) {
+                double qv[4];
+                ld4(V + (long long)d * ldv + 4 * q, qv);
+                acc[d] += qv[0] * uv[0] + qv[1] * uv[1] + qv[2] * uv[2] + qv[3] * uv[3];
+                acc[KMAX + d] += qv[0] * wv[0] + qv[1] * wv[1] + qv[2] * wv[2] + qv[3] * wv[3];
+            }
+        acc[2 * KMAX] += uv[0] * uv[0] + uv[1] * uv[1] + uv[2] * uv[2] + uv[3] * uv[3];
+        acc[2 * KMAX + 1] += uv[0] * wv[0] + uv[1] * wv[1] + uv[2] * wv[2] + uv[3] * wv[3];
+        acc[2 * KMAX + 2] += wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2] + wv[3] * wv[3];
+    }
+    for (long long i = 4 * n4 + blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double u = U[i] * us, w = W[i];
+#pragma unroll
+        for (int d = 0; d < KMAX; ++d)
+            if (d < j) {
+                const double qv = V[(long long)d * ldv + i];
+                acc[d] += qv * u;
+                acc[KMAX + d] += qv * w;
+            }
+        acc[2 * KMAX] += u * u;
+        acc[2 * KMAX + 1] += u * w;
+        acc[2 * KMAX + 2] += w * w;
+    }
+    // layout [s_0..s_{KMAX-1}, t_0..t_{KMAX-1}, alpha, beta, gamma] (zeros past j)
+    block_finish<DC_MAXD>(acc, DC_MAXD, partials, ks, FIN_DCGS2, j, nullptr);
+}
+
+void launch_dcgs2_dots(hipStream_t s, long long n, const double* V, long long ldv, int j,
+                       double* partials, KState* ks) {
+    const unsigned nb4 = red_grid4(n);
+    hipLaunchKernelGGL(k_dcgs2_dots, dim3(nb4), dim3(VEC_THREADS), 0, s, n, V, ldv, j, partials, ks);
+    finish<DC_MAXD>(s, nb4, DC_MAXD, partials, ks, FIN_DCGS2, j, nullptr);
+}
+
+__global__ __launch_bounds__(VEC_THREADS) void k_dcgs2_update(long long n, double* __restrict__ V,
+                                                             long long ldv, int j, KState* ks) {
+    if (ks->done) return;
+    __shared__ double cs_[KMAX], ct_[KMAX];
+    if (threadIdx.x < KMAX) {
+        cs_[threadIdx.x] = (int)threadIdx.x < j ? ks->ds[threadIdx.x] : 0.0;
+        ct_[threadIdx.x] = (int)threadIdx.x < j ? ks->hcol[threadIdx.x] : 0.0;
+    }
+    __syncthreads();
+    const double us = ks->scale[j] * ks->d_nuinv;   // q_j = (us u_stored - Q s nuinv) ...
+    const double nuinv = ks->d_nuinv, c = ks->d_c, etainv = ks->d_etainv;
+    double* U = V + (long long)j * ldv;
+    double* W = V + (long long)(j + 1) * ldv;
+    const long long n4 = n >> 2;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n4; q += stride) {
+        double uv[4], wv[4];
+        ld4(U + 4 * q, uv);
+        ld4(W + 4 * q, wv);
+        double qs[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int d = 0; d < KMAX; ++d)
+            if (d < j) {
+                double qv[4];
+                ld4(V + (long long)d * ldv + 4 * q, qv);
+                const double a = cs_[d], b = ct_[d];
+                qs[0] += a * qv[0]; qs[1] += a * qv[1]; qs[2] += a * qv[2]; qs[3] += a * qv[3];
+                wv[0] -= b * qv[0]; wv[1] -= b * qv[1]; wv[2] -= b * qv[2]; wv[3] -= b * qv[3];
+            }
+        double qj[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            qj[e] = uv[e] * us - qs[e] * nuinv;
+            wv[e] = (wv[e] - c * qj[e]) * etainv;
+        }
+        st4(U + 4 * q, qj);
+        st4(W + 4 * q, wv);
+    }
+    for (long long i = 4 * n4 + blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += stride) {
+        double qs = 0.0, w = W[i];
+#pragma unroll
+        for (int d = 0; d < KMAX; ++d)
+            if (d < j) {
+                const double qv = V[(long long)d * ldv + i];
+                qs += cs_[d] * qv;
+                w -= ct_[d] * qv;
+            }
+        const double qj = U[i] * us - qs * nuinv;
+        U[i] = qj;
+        W[i] = (w - c * qj) * etainv;
+    }
+}
+
+void launch_dcgs2_update(hipStream_t s, long long n, double* V, long long ldv, int j, KState* ks) {
+    const unsigned nb4 = red_grid4(n);
+    hipLaunchKernelGGL(k_dcgs2_update, dim3(nb4), dim3(VEC_THREADS), 0, s, n, V, ldv, j, ks);
 }
 
 bool launch_maxpy_mdot(hipStream_t s, long long n, double* w, const double* V, long long ldv,

@@ -203,7 +203,7 @@ size_t carve(st_handle* h, char* base) {
     h->V = c.take<double>((size_t)(m + 1) * h->ld0);
     h->Z = mixed ? (void*)c.take<float>((size_t)m * h->ld0) : (void*)c.take<double>((size_t)m * h->ld0);
     h->ks_outer = c.take<KState>(1);
-    h->partials = c.take<double>((size_t)RED_BLOCKS * KMAX + 2 * KMAX);
+    h->partials = c.take<double>(PARTIALS_DOUBLES);
     h->gram_part = c.take<double>(gram_partials_doubles());
     h->dscal = c.take<double>(64);
     int maxnt = 0;
@@ -771,6 +771,36 @@ st_status fgmres(st_handle* h, const double* f, const double* fnorm_dev, double*
                 launch_fine_apply(s, h->fg, cf, zp, 0, 1, trans, Zj(j), Vj(j + 1), nullptr, nullptr,
                                   nullptr, nullptr, 1, 1);
             }
+            if (!(o.flags & ST_FLAG_OUTER_CGS2)) {
+                // delayed CGS2: one pass for all inner products of the step,
+                // one pass writing q_j (re-orthogonalised) and u_{j+1}
+                {
+                    Timed t(h, KC_OUTER, n * 8 * (j + 2));
+                    launch_dcgs2_dots(s, n, h->V, ld, j, h->partials, ks);
+                }
+                {
+                    Timed t(h, KC_OUTER, n * 8 * (j + 4));
+                    launch_dcgs2_update(s, n, h->V, ld, j, ks);
+                }
+                HIPCHK(hipMemcpyAsync(h->hbuf, &ks->est, 4 * sizeof(double) + 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                ++its;
+                k = j + 1;
+                const int* iv = (const int*)(h->hbuf + 2);   // k, done, maxit, bad, counter, -, pending
+                if (iv[3]) { bad = true; break; }
+                if (iv[6]) {
+                    // last column of the cycle: clean u_{j+1} against q_0..q_j
+                    Timed t(h, KC_OUTER, n * 8 * (j + 2));
+                    launch_mdot(s, n, 0, 0, Vj(j + 1), h->V, ld, j + 2, h->partials, ks, FIN_DCGS2_LAST, j, KMAX);
+                    HIPCHK(hipMemcpyAsync(h->hbuf, &ks->est, 4 * sizeof(double) + 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+                    HIPCHK(hipStreamSynchronize(s));
+                }
+                est = h->hbuf[0] / (fnorm > 0 ? fnorm : 1.0);
+                if (info && info->n_hist < ST_MAX_HIST) info->res_hist[info->n_hist++] = est;
+                if (iv[3]) { bad = true; break; }
+                if (iv[1]) break;
+                continue;
+            }
             {
                 Timed t(h, KC_OUTER, n * 8 * (j + 2));
                 launch_mdot(s, n, 0, 0, Vj(j + 1), h->V, ld, j + 1, h->partials, ks, FIN_PROJ1, j, KMAX);
@@ -977,7 +1007,7 @@ st_status st_setup(const st_grid* grid, const st_material* mat, const double* rh
         return ST_ERR_HIP;
     }
     hipStream_t s = h->stream;
-    launch_fill(s, (long long)RED_BLOCKS * KMAX + 2 * KMAX, 0, h->partials, 0.0);
+    launch_fill(s, (long long)PARTIALS_DOUBLES, 0, h->partials, 0.0);
     launch_fill(s, 64, 0, h->dscal, 0.0);
     launch_fill(s, (long long)(sizeof(KState) / sizeof(int)), 2, h->ks_outer, 0.0);
     for (int l = 0; l < h->nlev; ++l)

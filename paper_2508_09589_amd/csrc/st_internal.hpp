@@ -16,6 +16,11 @@ namespace st {
 constexpr int KMAX = 32;          // largest Krylov basis (FGMRES / coarse restart)
 constexpr int SMAX = 16;          // largest smoother basis
 constexpr int RED_BLOCKS = 2048;  // most blocks of a grid-stride reduction kernel
+constexpr int RED_WIDTH = 2 * 32 + 4;   // most accumulators per block (delayed CGS2: 2j + 3)
+// Reduction scratch: [RED_BLOCKS][RED_WIDTH] block partials, then the arrival
+// counter of reductions without a KState.
+constexpr size_t PARTIALS_DOUBLES = (size_t)RED_BLOCKS * RED_WIDTH + 64;
+constexpr size_t PARTIALS_COUNTER = (size_t)RED_BLOCKS * RED_WIDTH + 32;
 constexpr int VEC_THREADS = 256;
 
 // Device-resident state of one GMRES / FGMRES cycle.  Every small scalar step
@@ -39,9 +44,15 @@ struct KState {
     int bad;                    // NaN or Inf seen
     unsigned counter;           // arrival counter of the last-block reduction
     int scale_update;           // 1: y_d multiplied by scale_d (unnormalised basis)
-    int pad[2];
+    int pending;                // delayed CGS2: the cycle ends after this column
+    int pad1;
     double gcarry[2];           // fused smoother: unrotated g of the next column,
                                 // alternating by column parity
+    // delayed CGS2 (outer FGMRES): re-orthogonalisation coefficients of the
+    // current vector, its norm, and the scalars of the update pass
+    double ds[KMAX];
+    double d_nuinv, d_c, d_eta, d_etainv;
+    int d_brk, d_pad;
 };
 
 // Finalisation modes of the fused reduction kernels.
@@ -52,7 +63,10 @@ enum FinMode {
     FIN_PROJ2 = 3,       // re-orthogonalisation projections (CGS2)
     FIN_GIVENS = 4,      // norm of the new vector, Givens update, convergence test
     FIN_SUM = 5,         // plain sums to out[]
-    FIN_NONE = 6         // maxpy only: subtract, no reduction
+    FIN_NONE = 6,        // maxpy only: subtract, no reduction
+    FIN_DCGS2 = 7,       // delayed CGS2 step: [s, t, alpha, beta, gamma] -> column j-1 final,
+                         // column j provisional, update coefficients
+    FIN_DCGS2_LAST = 8   // last column of a cycle: [s', alpha'] -> final column, y
 };
 
 // T = 0 patches translated to index ranges.
@@ -147,6 +161,11 @@ void launch_mdot(hipStream_t s, long long n, int prec_w, int prec_v, const void*
                  int j, int maxd);
 void launch_maxpy(hipStream_t s, long long n, int prec_w, int prec_v, void* w, const void* V,
                   long long ldv, int nd, double* partials, KState* ks, int mode, int j, int maxd);
+// Delayed CGS2 for the FP64 outer basis: one reduction pass (launch_dcgs2_dots)
+// and one update pass (launch_dcgs2_update) per FGMRES step.
+void launch_dcgs2_dots(hipStream_t s, long long n, const double* V, long long ldv, int j,
+                       double* partials, KState* ks);
+void launch_dcgs2_update(hipStream_t s, long long n, double* V, long long ldv, int j, KState* ks);
 // Fused CGS2 middle passes (FP64): false when the layout does not allow it.
 bool launch_maxpy_mdot(hipStream_t s, long long n, double* w, const double* V, long long ldv,
                        int nd, double* partials, KState* ks, int j);

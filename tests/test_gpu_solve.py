@@ -121,3 +121,30 @@ def test_sstep_smoother_solve_parity(torch_cuda, precision, tv):
     assert abs(info.iterations - ref.iterations) <= 1, (info.iterations, ref.iterations)
     p.close()
     q.close()
+
+
+@pytest.mark.parametrize("restart", [30, 5])
+def test_delayed_cgs2_matches_classical_cgs2(torch_cuda, restart):
+    """The outer FGMRES orthogonalises with delayed CGS2 (one reduction and one
+    update pass per step, the re-orthogonalisation of each basis vector lagging
+    by one step); classical CGS2 gives the same iterates in exact arithmetic.
+    Both reach the direct solution, state and adjoint, with the same iteration
+    counts (+-1), also across restarts."""
+    from paper_2508_09589_amd import _lib as L
+    c = Case(24, 24, 32, tv=True, seed=37)
+    out = {}
+    for name, flags in (("delayed", 0), ("classical", L.ST_FLAG_OUTER_CGS2)):
+        p = c.problem(rtol=1e-12, restart=restart)
+        p.set_flags(flags)
+        T, info = p.solve()
+        lam, ainfo = p.adjoint(p.load_vector())
+        out[name] = (T.cpu().numpy(), info.iterations, lam.cpu().numpy(), ainfo.iterations)
+        assert info.true_rel_res <= 1e-12 and ainfo.true_rel_res <= 1e-12
+        p.close()
+    s = solve_direct(c.Jm, c.fm)
+    la = solve_adjoint_direct(c.Jm, c.f, c.mask)
+    for name in out:
+        assert rel(out[name][0], s) <= 1e-10, name
+        assert rel(out[name][2], la) <= 1e-10, name
+    assert abs(out["delayed"][1] - out["classical"][1]) <= 1
+    assert abs(out["delayed"][3] - out["classical"][3]) <= 1
