@@ -11,8 +11,9 @@ from tests._cases import Case, rel, maxrel
 
 pytestmark = pytest.mark.gpu
 
+# (64 q + 1 node columns -- nx = 64, 128 -- take the 65-wide last tile column)
 SHAPES = [(3, 2, 2, False), (3, 2, 2, True), (8, 6, 5, True), (12, 12, 8, False),
-          (32, 32, 32, False), (16, 16, 16, True)]
+          (32, 32, 32, False), (16, 16, 16, True), (64, 20, 6, True), (128, 9, 5, False)]
 
 
 def _t(x):
@@ -37,6 +38,14 @@ def test_fine_apply_and_transpose(torch_cuda, nx, ny, nt, tv):
         y = p.debug_apply(0, _t(x), transpose=trans).cpu().numpy()
         ref = (c.Jm.T if trans else c.Jm) @ x.ravel()
         assert maxrel(y, ref) < 1e-13, (trans, maxrel(y, ref))
+    p.close()
+    # the FP32 apply of the V-cycle (same tiling)
+    p = c.problem(max_coarse_nodes=10 ** 9, precision="mixed")
+    for trans in (False, True):
+        x = rng.standard_normal(shp)
+        y = p.debug_apply(0, _t(x), transpose=trans, mixed=True).cpu().numpy()
+        ref = (c.Jm.T if trans else c.Jm) @ x.ravel()
+        assert rel(y, ref) < 1e-5, (trans, rel(y, ref))
     p.close()
 
 
