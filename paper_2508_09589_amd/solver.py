@@ -32,13 +32,15 @@ class Problem:
     time, the comparison of §5.1.2).
     smoother: "gmres" (Jacobi-GMRES by Arnoldi, §3.2) or "sstep" (the same
     minimisation from the Gram matrix of the monomial Krylov basis).
+    orthogonalisation: outer FGMRES basis by "delayed" CGS2 (two passes per
+    step) or "classical" CGS2 (three).
     """
 
     def __init__(self, nx, ny, nt, rho, dx=None, dt=None, k_ins=1e-3, k_con=1.0, p_k=3.0,
                  c_ins=1.0, c_con=1.0, p_c=1.0, patches=((0, 0.5, 0.05),), q0=1.0, ic=None,
                  source=None, precision="fp64", filter_r=0.0, device="cuda", stream=None,
                  time_kernels=False, coarse="direct", coarsening="semi", smoother="gmres",
-                 **opt_overrides):
+                 orthogonalisation="delayed", **opt_overrides):
         self.lib = L.load()
         self.device = torch.device(device)
         self.nx, self.ny, self.nt = int(nx), int(ny), int(nt)
@@ -72,6 +74,11 @@ class Problem:
             raise ValueError(f"smoother must be 'gmres' or 'sstep', not {smoother!r}")
         if smoother == "sstep":
             self.opts.flags |= L.ST_FLAG_SSTEP_SMOOTHER
+        if orthogonalisation not in ("delayed", "classical"):
+            raise ValueError("orthogonalisation must be 'delayed' or 'classical', "
+                             f"not {orthogonalisation!r}")
+        if orthogonalisation == "classical":
+            self.opts.flags |= L.ST_FLAG_OUTER_CGS2
         for k, v in opt_overrides.items():
             if not hasattr(self.opts, k):
                 raise KeyError(k)
