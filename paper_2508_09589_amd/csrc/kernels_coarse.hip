@@ -17,6 +17,15 @@
 //     J^T x = b:  w_s = b_s - G_{s-1}^T w_{s-1},
 //                 x_s = D'_s^{-T} (w_s - L_{s+1}^T x_{s+1}).
 // One workgroup does each; the factors (2 P^2 per time level, FP64) stay in L2.
+//
+// Small planes (P <= CD_FAST_P, whole vector in LDS) take a faster solve: the
+// factorisation also forms H_s = D'_s^{-1} L_s and M_s = D'_s^{-T} L_{s+1}^T,
+// so every step of a sweep is one dense product whose matrix rows are loaded
+// into registers a step ahead and whose vector lives in LDS:
+//     J x = b:    z_s = D'_s^{-1} b_s - H_s z_{s-1},  x_s = z_s - G_s x_{s+1}
+//     J^T x = b:  w_s = b_s - G_{s-1}^T w_{s-1},
+//                 x_s = D'_s^{-T} w_s - M_s x_{s+1}.
+// (one barrier per time level instead of a chain of dependent global loads).
 #include "st_internal.hpp"
 
 namespace st {
@@ -74,8 +83,9 @@ __device__ int cd_pivot(const double* A, int P, int k, double* rv, int* ri) {
 }
 
 // Factorisation (one workgroup).  A: P x P working matrix (LDS when it fits,
-// else global); Dinv: [nt + 1][P][P]; G: [nt][P][P]; colk: P doubles of scratch
-// (global); status: set to 1 when a pivot is zero.
+// else global); Dinv: [nt + 1][P][P]; G: [nt][P][P]; H, M: [nt + 1][P][P] or
+// null (H_0 and M_nt unused); colk: P doubles of scratch (global); status:
+// set to 1 when a pivot is zero.
 template <bool ALDS>
 __global__ __launch_bounds__(CDT) void k_coarse_factor(int nx, int ny, int nt, int nplanes,
                                                        const double* __restrict__ st,
@@ -83,6 +93,8 @@ __global__ __launch_bounds__(CDT) void k_coarse_factor(int nx, int ny, int nt, i
                                                        double* __restrict__ Ag,
                                                        double* __restrict__ Dinv,
                                                        double* __restrict__ G,
+                                                       double* __restrict__ H,
+                                                       double* __restrict__ M,
                                                        double* __restrict__ colk,
                                                        int* __restrict__ perm, int* status) {
     extern __shared__ double dyn[];
@@ -182,6 +194,49 @@ __global__ __launch_bounds__(CDT) void k_coarse_factor(int nx, int ny, int nt, i
                     }
                 }
                 Gs[e] = v;
+            }
+        }
+        // H_s = D'_s^{-1} L_s: L_s[b][c] is the (dn = -1) entry of row b towards
+        // node c of level s - 1.  M_s = (L_{s+1} D'_s^{-1})^T: L_{s+1}[c][b] is
+        // the (dn = -1) entry of row c of level s + 1 towards node b of level s.
+        if (H && s > 0) {
+            double* Hs = H + (long long)s * PP;
+            for (long long e = tid; e < PP; e += CDT) {
+                const int a = (int)(e / P), c = (int)(e - (long long)a * P);
+                const int jc = c / row, ic = c - jc * row;
+                double v = 0.0;
+                for (int qj = -1; qj <= 1; ++qj) {
+                    const int jb = jc + qj;
+                    if (jb < 0 || jb > ny) continue;
+                    for (int qi = -1; qi <= 1; ++qi) {
+                        const int ib = ic + qi;
+                        if (ib < 0 || ib > nx) continue;
+                        const int b = jb * row + ib;
+                        const double l = cd_entry(st, pmap, DS, P, s, b, -1, -qj, -qi);
+                        if (l != 0.0) v += A[(long long)a * P + b] * l;
+                    }
+                }
+                Hs[e] = v;
+            }
+        }
+        if (M && s < nt) {
+            double* Ms = M + (long long)s * PP;
+            for (long long e = tid; e < PP; e += CDT) {
+                const int a = (int)(e / P), c = (int)(e - (long long)a * P);
+                const int jc = c / row, ic = c - jc * row;
+                double v = 0.0;
+                for (int qj = -1; qj <= 1; ++qj) {
+                    const int jb = jc + qj;
+                    if (jb < 0 || jb > ny) continue;
+                    for (int qi = -1; qi <= 1; ++qi) {
+                        const int ib = ic + qi;
+                        if (ib < 0 || ib > nx) continue;
+                        const int b = jb * row + ib;
+                        const double l = cd_entry(st, pmap, DS, P, s + 1, c, -1, qj, qi);
+                        if (l != 0.0) v += l * A[(long long)b * P + a];
+                    }
+                }
+                Ms[e] = v;
             }
         }
         __syncthreads();
@@ -294,24 +349,128 @@ __global__ __launch_bounds__(CDT) void k_coarse_direct(int nx, int ny, int nt, i
     for (long long i = tid; i < n; i += CDT) x[i] = (TIO)work[i];
 }
 
+// Fast solve (P <= CD_FAST_P, 2 (nt + 1) P doubles of LDS).  Thread t owns row
+// r = t / 8 of each product and its columns c = t % 8 + 8 k; the row slices of
+// the next step's matrices are loaded while the current step reduces and
+// waits at the barrier.  Bv holds b, Zv the sweeps' vectors.
+constexpr int CD_NC = CD_FAST_P / CD_SEG;
+template <typename TIO>
+__global__ __launch_bounds__(CDT) void k_coarse_direct_fast(int P, int nt,
+                                                            const double* __restrict__ Dinv,
+                                                            const double* __restrict__ G,
+                                                            const double* __restrict__ H,
+                                                            const double* __restrict__ M,
+                                                            const TIO* __restrict__ b,
+                                                            TIO* __restrict__ x, int trans) {
+    extern __shared__ double dyn[];
+    const int n = (nt + 1) * P;
+    double* Bv = dyn;
+    double* Zv = dyn + n;
+    const long long PP = (long long)P * P;
+    const int tid = threadIdx.x, r = tid / CD_SEG, q = tid & (CD_SEG - 1);
+    const bool own = r < P && q == 0;
+    for (int i = tid; i < n; i += CDT) Bv[i] = (double)b[i];
+    double m1[CD_NC], m2[CD_NC];
+    // Row r (tr = 0) or column r (tr = 1) of Mx, this thread's columns.
+    auto load = [&](double (&m)[CD_NC], const double* Mx, int tr) {
+#pragma unroll
+        for (int k = 0; k < CD_NC; ++k) {
+            const int c = q + CD_SEG * k;
+            m[k] = (r < P && c < P) ? (tr ? Mx[(long long)c * P + r] : Mx[(long long)r * P + c]) : 0.0;
+        }
+    };
+    auto dot = [&](const double (&m)[CD_NC], const double* v) {
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < CD_NC; ++k) {
+            const int c = q + CD_SEG * k;
+            if (c < P) a += m[k] * v[c];
+        }
+#pragma unroll
+        for (int o = CD_SEG / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+        return a;
+    };
+    if (!trans) {
+        load(m1, Dinv, 0);
+        __syncthreads();
+        for (int s = 0; s <= nt; ++s) {   // z_s = D'^{-1}_s b_s - H_s z_{s-1}
+            double a = dot(m1, Bv + (long long)s * P);
+            if (s > 0) a -= dot(m2, Zv + (long long)(s - 1) * P);
+            if (s < nt) {
+                load(m1, Dinv + (long long)(s + 1) * PP, 0);
+                load(m2, H + (long long)(s + 1) * PP, 0);
+            } else if (nt > 0) {
+                load(m1, G + (long long)(nt - 1) * PP, 0);
+            }
+            if (own) Zv[(long long)s * P + r] = a;
+            __syncthreads();
+        }
+        for (int s = nt - 1; s >= 0; --s) {   // x_s = z_s - G_s x_{s+1}
+            const double a = dot(m1, Zv + (long long)(s + 1) * P);
+            if (s > 0) load(m1, G + (long long)(s - 1) * PP, 0);
+            if (own) Zv[(long long)s * P + r] -= a;
+            __syncthreads();
+        }
+        for (int i = tid; i < n; i += CDT) x[i] = (TIO)Zv[i];
+    } else {
+        if (nt > 0) load(m1, G, 1);
+        __syncthreads();
+        for (int i = tid; i < P; i += CDT) Zv[i] = Bv[i];
+        __syncthreads();
+        for (int s = 1; s <= nt; ++s) {   // w_s = b_s - G_{s-1}^T w_{s-1}
+            const double a = dot(m1, Zv + (long long)(s - 1) * P);
+            if (s < nt) load(m1, G + (long long)s * PP, 1);
+            if (own) Zv[(long long)s * P + r] = Bv[(long long)s * P + r] - a;
+            __syncthreads();
+        }
+        load(m1, Dinv + (long long)nt * PP, 1);
+        for (int s = nt; s >= 0; --s) {   // x_s = D'^{-T}_s w_s - M_s x_{s+1}, into Bv
+            double a = dot(m1, Zv + (long long)s * P);
+            if (s < nt) a -= dot(m2, Bv + (long long)(s + 1) * P);
+            if (s > 0) {
+                load(m1, Dinv + (long long)(s - 1) * PP, 1);
+                load(m2, M + (long long)(s - 1) * PP, 0);
+            }
+            // slot s of Bv (b_s) was last read in the first sweep
+            if (own) Bv[(long long)s * P + r] = a;
+            __syncthreads();
+        }
+        for (int i = tid; i < n; i += CDT) x[i] = (TIO)Bv[i];
+    }
+}
+
 size_t coarse_direct_lds(int P) { return (size_t)P * P * sizeof(double); }
+bool coarse_direct_fast(int P, int nt) {
+    return P <= CD_FAST_P && (long long)(nt + 1) * P <= CD_FAST_NODES;
+}
 bool coarse_direct_fits(int P) { return P <= CD_MAX_PLANE; }
 
 void launch_coarse_factor(hipStream_t s, const Level& L, double* Ag, double* Dinv, double* G,
-                          double* colk, int* perm, int* status) {
+                          double* H, double* M, double* colk, int* perm, int* status) {
     const int P = (L.nx + 1) * (L.ny + 1);
     const size_t lds = coarse_direct_lds(P);
     if (lds <= CD_LDS_MAX)
         hipLaunchKernelGGL(k_coarse_factor<true>, dim3(1), dim3(CDT), lds, s, L.nx, L.ny, L.nt,
-                           L.nplanes, L.st64, L.plane_map, Ag, Dinv, G, colk, perm, status);
+                           L.nplanes, L.st64, L.plane_map, Ag, Dinv, G, H, M, colk, perm, status);
     else
         hipLaunchKernelGGL(k_coarse_factor<false>, dim3(1), dim3(CDT), 0, s, L.nx, L.ny, L.nt,
-                           L.nplanes, L.st64, L.plane_map, Ag, Dinv, G, colk, perm, status);
+                           L.nplanes, L.st64, L.plane_map, Ag, Dinv, G, H, M, colk, perm, status);
 }
 
 void launch_coarse_direct(hipStream_t s, const Level& L, int prec_io, int trans, const void* b,
-                          void* x, const double* Dinv, const double* G, double* work) {
+                          void* x, const double* Dinv, const double* G, const double* H,
+                          const double* M, double* work) {
     const int P = (L.nx + 1) * (L.ny + 1);
+    if (H && M) {
+        const size_t lds = (size_t)2 * P * (L.nt + 1) * sizeof(double);
+        if (prec_io == 0)
+            hipLaunchKernelGGL(k_coarse_direct_fast<double>, dim3(1), dim3(CDT), lds, s, P, L.nt,
+                               Dinv, G, H, M, (const double*)b, (double*)x, trans);
+        else
+            hipLaunchKernelGGL(k_coarse_direct_fast<float>, dim3(1), dim3(CDT), lds, s, P, L.nt,
+                               Dinv, G, H, M, (const float*)b, (float*)x, trans);
+        return;
+    }
     const size_t lds = (size_t)2 * P * sizeof(double);
     if (prec_io == 0)
         hipLaunchKernelGGL(k_coarse_direct<double>, dim3(1), dim3(CDT), lds, s, L.nx, L.ny, L.nt,

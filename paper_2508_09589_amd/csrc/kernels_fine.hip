@@ -73,8 +73,8 @@ void launch_simp(hipStream_t s, long long ne, const double* rho, const st_materi
 // and marches through a chunk of time levels.  Per level the tile's x window
 // (10 x 66 values, halo included) and per slab its coefficient window (9 x 65
 // elements) are loaded once, coalesced, into LDS; the loads of level s + 2 and
-// slab s + 2 are issued before the arithmetic of slab s, and those of b and
-// invd of level s + 1 after its outputs, so every load has one iteration to
+// slab s + 2 are issued before the arithmetic of slab s, and those of b of
+// level s + 1 after its outputs, so every load has one iteration to
 // arrive (three x buffers, two coefficient buffers, one barrier per level).  A thread reads its 3 x 4 stencil window of the two levels of a slab
 // from LDS and produces 2 outputs of one column.  Workgroups are numbered so
 // that the eight XCDs (separate L2 caches) each get a contiguous range of
@@ -107,7 +107,7 @@ constexpr int FA_TX = 64, FA_RY = 2, FA_TY = 4 * FA_RY;
 template <typename TIN, typename TOUT, typename TC, bool TRANS, bool TCONST, bool CUNI>
 __global__ __launch_bounds__(256) void k_fine_apply(
     FineGeom g, const TC* __restrict__ kc, const TC* __restrict__ cc, const TIN* __restrict__ x,
-    TOUT* __restrict__ y, const TOUT* __restrict__ b, const TOUT* __restrict__ invd,
+    TOUT* __restrict__ y, const TOUT* __restrict__ b, int jacobi,
     const double* __restrict__ scale, const int* __restrict__ skip, int gx, int gy, int nchunk,
     int per_xcd, int mask_in, int dir_rows) {
     constexpr int RY = FA_RY, TX = FA_TX, TY = FA_TY;
@@ -268,35 +268,40 @@ __global__ __launch_bounds__(256) void k_fine_apply(
     unsigned oo[RY];
 #pragma unroll
     for (int m = 0; m < RY; ++m) oo[m] = ((own >> m) & 1u) ? (unsigned)((jb + ry0 + m) * rowp + i) : 0u;
-    // b, invd and (Dirichlet rows) x of the own outputs of one level, loaded
-    // an iteration before they are used.
+    // b and (Dirichlet rows) x of the own outputs of one level, loaded an
+    // iteration before they are used.
     // Every load is issued unconditionally (straight-line code lets the
-    // compiler wait for exactly the loads a use needs): an absent b or invd
-    // is a zero-size buffer, and a row that is not a Dirichlet row reads x at
-    // an offset past the end of the buffer -- both read as zero without a
-    // memory access.
-    TOUT bv[RY], dv[RY];
+    // compiler wait for exactly the loads a use needs): an absent b is a
+    // zero-size buffer, and a row that is not a Dirichlet row reads x at an
+    // offset past the end of the buffer -- both read as zero without a memory
+    // access.
+    TOUT bv[RY];
     TIN xd[RY];
     constexpr unsigned OOB = 0x7FFFFFF0u;
     auto fetch_bd = [&](int n) {
         const auto rb = buf_rsrc(b + (long long)n * P, b ? P * (long long)sizeof(TOUT) : 0);
-        const auto rd = buf_rsrc(invd + (long long)n * P, invd ? P * (long long)sizeof(TOUT) : 0);
         const auto rx = buf_rsrc(x + (long long)n * P, P * (long long)sizeof(TIN));
         const bool ic = dir_rows && g.ic_dir && n == 0;
 #pragma unroll
         for (int m = 0; m < RY; ++m) {
             bv[m] = buf_ld<TOUT>(rb, oo[m] * (unsigned)sizeof(TOUT));
-            dv[m] = buf_ld<TOUT>(rd, oo[m] * (unsigned)sizeof(TOUT));
             const bool dr = ic || (dir_rows && ((opatch >> m) & 1u));
             xd[m] = buf_ld<TIN>(rx, dr ? oo[m] * (unsigned)sizeof(TIN) : OOB);
         }
     };
-    auto emit = [&](int n, int m, TC v) {
+    // jacobi: the output is scaled by the inverse diagonal of the operator,
+    // formed here from the coefficients already staged for the apply (per
+    // element A_aa = 2 dt / 9 k and, on the element's upper time face,
+    // B_aa = dx^2 / 9 C; App. A) instead of being streamed from memory:
+    //   diag(s) = 8 kt (Sk(s - 1) + Sk(s)) + 4 mw Sc(s - 1),
+    // Sk, Sc = sums over the four elements around the node in a slab; a
+    // Dirichlet row has the unit diagonal.
+    auto emit = [&](int n, int m, TC v, TC diag) {
         if (!((own >> m) & 1u)) return;
         const bool dir = dir_rows && ((g.ic_dir && n == 0) || ((opatch >> m) & 1u));
         TC val = dir ? (TC)xd[m] : v;
         if (b) val = (TC)bv[m] - val;
-        if (invd) val *= (TC)dv[m];
+        if (jacobi && !dir) val /= diag;
         buf_st<TOUT>((TOUT)(val * sc), buf_rsrc(y + (long long)n * P, P * (long long)sizeof(TOUT)),
                      oo[m] * (unsigned)sizeof(TOUT));
     };
@@ -304,7 +309,7 @@ __global__ __launch_bounds__(256) void k_fine_apply(
     const int sa = max(n0 - 1, 0);
     const int sb = min(n1 - 1, nt - 1);
     TC ulo[RY + 2][3], uhi[RY + 2][3];
-    TC Plo[RY], Rlo[RY], acc[RY];
+    TC Plo[RY], Rlo[RY], acc[RY], dacc[RY];
     fetch_x(sa);
     put_x(sa);
     fetch_c(sa);
@@ -317,6 +322,7 @@ __global__ __launch_bounds__(256) void k_fine_apply(
 #pragma unroll
     for (int m = 0; m < RY; ++m) {
         acc[m] = 0;
+        dacc[m] = 0;
         Plo[m] = 0;
         Rlo[m] = 0;
     }
@@ -352,43 +358,56 @@ __global__ __launch_bounds__(256) void k_fine_apply(
                 const TC Rv = TCONST ? Rlo[m] : mw * mass(ulo, m);
                 top += Sv - Rv;
             }
-            if (s >= n0) emit(s, m, acc[m] + bottom);
+            const TC sk = ke[m][0] + ke[m][1] + ke[m + 1][0] + ke[m + 1][1];
+            const TC sc4 = ce[m][0] + ce[m][1] + ce[m + 1][0] + ce[m + 1][1];
+            const TC dlo = (TC)8 * kt * sk;
+            if (s >= n0) emit(s, m, acc[m] + bottom, dacc[m] + dlo);
             acc[m] = top;
+            dacc[m] = dlo + (TC)4 * mw * sc4;
             if (TCONST) {
                 Plo[m] = Qv;
                 Rlo[m] = Sv;
             }
         }
         if (!TCONST && s + 1 <= sb) read_c(s + 1);
-        // b / invd of the next level: issued after this level's outputs, so
+        // b of the next level: issued after this level's outputs, so
         // waiting for them never waits for the x / coefficient loads above
         fetch_bd(s + 1);
     }
     if (sb + 1 == nt && nt >= n0 && nt < n1) {
 #pragma unroll
-        for (int m = 0; m < RY; ++m) emit(nt, m, acc[m]);
+        for (int m = 0; m < RY; ++m) emit(nt, m, acc[m], dacc[m]);
     }
 }
 
 template <typename TIN, typename TOUT, typename TC>
 static void fine_dispatch(hipStream_t s, const FineGeom& g, const TC* kc, const TC* cc, int trans,
-                          const void* x, void* y, const void* b, const void* invd,
+                          const void* x, void* y, const void* b, int jacobi,
                           const double* scale, const int* skip, int mask_in, int dir_rows) {
     const int gx = (g.nx + 1 + FA_TX - 1) / FA_TX, gy = (g.ny + 1 + FA_TY - 1) / FA_TY;
     const long long tiles = (long long)gx * gy;
+    // Time levels per workgroup: 32 when the grid is many times the 2048
+    // workgroups the chip holds at once (256 CUs x 8); otherwise the fewest
+    // chunks that still fill those 2048 slots, split evenly (a grid of 1.4
+    // rounds leaves most of the chip idle in its second round), at least 8.
+    const int nl = g.nt + 1;
     int nchunk = 32;
-    while (nchunk > 8 && tiles * ((g.nt + 1 + nchunk - 1) / nchunk) < 2048) nchunk /= 2;
+    if (tiles * ((nl + 31) / 32) < 4 * 2048) {
+        const long long gzw = (2048 + tiles - 1) / tiles;
+        nchunk = (int)((nl + gzw - 1) / gzw);
+        if (nchunk > 32) nchunk = 32;
+        if (nchunk < 8) nchunk = 8;
+    }
     const long long gz = (g.nt + 1 + nchunk - 1) / nchunk;
     const long long per_xcd = (tiles * gz + 7) / 8;
     dim3 grid((unsigned)(8 * per_xcd)), block(64, 4);
     const TIN* xi = (const TIN*)x;
     TOUT* yo = (TOUT*)y;
     const TOUT* bi = (const TOUT*)b;
-    const TOUT* di = (const TOUT*)invd;
     const int px = (int)per_xcd;
 #define FA_LAUNCH(TR, TCN, CU)                                                                  \
     hipLaunchKernelGGL((k_fine_apply<TIN, TOUT, TC, TR, TCN, CU>), grid, block, 0, s, g, kc, cc, \
-                       xi, yo, bi, di, scale, skip, gx, gy, nchunk, px, mask_in, dir_rows)
+                       xi, yo, bi, jacobi, scale, skip, gx, gy, nchunk, px, mask_in, dir_rows)
     const bool cu = g.cuniform != 0;
     if (g.tconst) {
         if (trans) {
@@ -410,20 +429,20 @@ static void fine_dispatch(hipStream_t s, const FineGeom& g, const TC* kc, const 
 // coefficients in FP64 (else FP32).
 void launch_fine_apply(hipStream_t s, const FineGeom& g, const Coef& cf, int prec_in, int prec_out,
                        int compute64, int trans, const void* x, void* y, const void* b,
-                       const void* invd, const double* scale, const int* skip, int mask_in,
+                       int jacobi, const double* scale, const int* skip, int mask_in,
                        int dir_rows) {
     if (compute64) {
         if (prec_in == 0 && prec_out == 0)
-            fine_dispatch<double, double, double>(s, g, cf.k64, cf.c64, trans, x, y, b, invd,
+            fine_dispatch<double, double, double>(s, g, cf.k64, cf.c64, trans, x, y, b, jacobi,
                                                   scale, skip, mask_in, dir_rows);
         else if (prec_in == 1 && prec_out == 0)
-            fine_dispatch<float, double, double>(s, g, cf.k64, cf.c64, trans, x, y, b, invd, scale,
+            fine_dispatch<float, double, double>(s, g, cf.k64, cf.c64, trans, x, y, b, jacobi, scale,
                                                  skip, mask_in, dir_rows);
         else
-            fine_dispatch<double, float, double>(s, g, cf.k64, cf.c64, trans, x, y, b, invd, scale,
+            fine_dispatch<double, float, double>(s, g, cf.k64, cf.c64, trans, x, y, b, jacobi, scale,
                                                  skip, mask_in, dir_rows);
     } else {
-        fine_dispatch<float, float, float>(s, g, cf.k32, cf.c32, trans, x, y, b, invd, scale, skip,
+        fine_dispatch<float, float, float>(s, g, cf.k32, cf.c32, trans, x, y, b, jacobi, scale, skip,
                                            mask_in, dir_rows);
     }
 }

@@ -69,6 +69,7 @@ struct st_handle {
     bool cd_ok = false;        // ... and no zero pivot met
     bool cd_factored = false;  // factors match the current coarse operator
     double *cd_Dinv = nullptr, *cd_G = nullptr, *cd_A = nullptr, *cd_colk = nullptr;
+    double *cd_H = nullptr, *cd_M = nullptr;   // fast-solve products (small planes)
     int* cd_perm = nullptr;
     int* cd_status = nullptr;
     double* partials = nullptr;
@@ -242,6 +243,10 @@ size_t carve(st_handle* h, char* base) {
         if (h->cd_fit) {
             h->cd_Dinv = c.take<double>((size_t)P * P * (Lc.nt + 1));
             h->cd_G = c.take<double>((size_t)P * P * Lc.nt);
+            if (coarse_direct_fast((int)P, Lc.nt)) {
+                h->cd_H = c.take<double>((size_t)P * P * (Lc.nt + 1));
+                h->cd_M = c.take<double>((size_t)P * P * (Lc.nt + 1));
+            }
             h->cd_A = coarse_direct_lds((int)P) > CD_LDS_MAX ? c.take<double>((size_t)P * P) : nullptr;
             h->cd_colk = c.take<double>((size_t)P);
             h->cd_perm = c.take<int>((size_t)P);
@@ -386,11 +391,14 @@ void level_apply(st_handle* h, int l, int prec, int trans, const void* x, void* 
     if (l == 0) {
         Coef cf{h->k64, h->c64, h->k32, h->c32};
         const int v = prec;
-        // x, y, optional b and invd per node, k (and C unless uniform) per element.
+        // x, y, optional b per node, k (and C unless uniform) per element; the
+        // Jacobi scaling (invd given) is formed from the coefficients in the
+        // kernel, the stored diagonal is not read.
         Timed t(h, v == 0 ? KC_FINE64 : KC_FINEV,
-                (int64_t)L.nn * (int64_t)(2 * vbytes(v) + (b ? vbytes(v) : 0) + (invd ? vbytes(v) : 0)) +
+                (int64_t)L.nn * (int64_t)(2 * vbytes(v) + (b ? vbytes(v) : 0)) +
                     fine_coef_bytes(h, vbytes(v)));
-        launch_fine_apply(h->stream, h->fg, cf, v, v, v == 0, trans, x, y, b, invd, scale, skip, 1, 1);
+        launch_fine_apply(h->stream, h->fg, cf, v, v, v == 0, trans, x, y, b, invd != nullptr, scale,
+                          skip, 1, 1);
     } else {
         Timed t(h, KC_STENCIL,
                 (int64_t)L.nn * (int64_t)(2 * vbytes(prec) + (b ? vbytes(prec) : 0) +
@@ -486,7 +494,7 @@ void smooth(st_handle* h, int l, int prec, int trans, const void* b, void* x, in
 st_status coarse_factor(st_handle* h) {
     const Level& L = h->lev[h->nlev - 1];
     hipStream_t s = h->stream;
-    launch_coarse_factor(s, L, h->cd_A, h->cd_Dinv, h->cd_G, h->cd_colk, h->cd_perm,
+    launch_coarse_factor(s, L, h->cd_A, h->cd_Dinv, h->cd_G, h->cd_H, h->cd_M, h->cd_colk, h->cd_perm,
                          h->cd_status);
     int st = 0;
     HIPCHK(hipGetLastError());
@@ -511,7 +519,8 @@ void vcycle(st_handle* h, int l, const void* b, void* x, int trans) {
             (void)coarse_factor(h);   // flags changed after the operator build
         Timed t(h, KC_COARSE, 0);
         if (!(o.flags & ST_FLAG_COARSE_GMRES) && h->cd_ok)
-            launch_coarse_direct(s, L, p, trans, b, x, h->cd_Dinv, h->cd_G, h->coarseWork);
+            launch_coarse_direct(s, L, p, trans, b, x, h->cd_Dinv, h->cd_G, h->cd_H, h->cd_M,
+                                 h->coarseWork);
         else
             launch_coarse_solve(s, L, p, trans, b, x, h->coarseV, h->coarseWork, o.coarse_max_it,
                                 o.coarse_restart, o.coarse_rtol, 1);
@@ -702,7 +711,7 @@ st_status build_rhs(st_handle* h, bool have_src, bool have_ic) {
     if (have_ic) {
         launch_ic_lift_vector(s, h->fg, h->ic, gv);
         Coef cf{h->k64, h->c64, h->k32, h->c32};
-        launch_fine_apply(s, h->fg, cf, 0, 0, 1, 0, gv, Jg, nullptr, nullptr, nullptr, nullptr, 0, 0);
+        launch_fine_apply(s, h->fg, cf, 0, 0, 1, 0, gv, Jg, nullptr, 0, nullptr, nullptr, 0, 0);
     } else {
         launch_fill(s, h->n0, 0, gv, 0.0);
         launch_fill(s, h->n0, 0, Jg, 0.0);
@@ -745,7 +754,7 @@ st_status fgmres(st_handle* h, const double* f, const double* fnorm_dev, double*
         {
             Coef cf{h->k64, h->c64, h->k32, h->c32};
             Timed t(h, KC_FINE64, n * 24 + fine_coef_bytes(h, 8));
-            launch_fine_apply(s, h->fg, cf, 0, 0, 1, trans, x, Vj(0), f, nullptr, nullptr, nullptr, 1, 1);
+            launch_fine_apply(s, h->fg, cf, 0, 0, 1, trans, x, Vj(0), f, 0, nullptr, nullptr, 1, 1);
         }
         launch_mdot(s, n, 0, 0, Vj(0), Vj(0), ld, 1, h->partials, ks, FIN_INIT_REF, 0, 1);
         HIPCHK(hipMemcpyAsync(h->hbuf, &ks->est, 4 * sizeof(double) + 4 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -768,7 +777,7 @@ st_status fgmres(st_handle* h, const double* f, const double* fnorm_dev, double*
             {
                 Coef cf{h->k64, h->c64, h->k32, h->c32};
                 Timed t(h, KC_FINE64, n * (8 + zb) + fine_coef_bytes(h, 8));
-                launch_fine_apply(s, h->fg, cf, zp, 0, 1, trans, Zj(j), Vj(j + 1), nullptr, nullptr,
+                launch_fine_apply(s, h->fg, cf, zp, 0, 1, trans, Zj(j), Vj(j + 1), nullptr, 0,
                                   nullptr, nullptr, 1, 1);
             }
             if (!(o.flags & ST_FLAG_OUTER_CGS2)) {
@@ -840,7 +849,7 @@ st_status fgmres(st_handle* h, const double* f, const double* fnorm_dev, double*
         // true residual
         {
             Coef cf{h->k64, h->c64, h->k32, h->c32};
-            launch_fine_apply(s, h->fg, cf, 0, 0, 1, trans, x, Vj(0), f, nullptr, nullptr, nullptr, 1, 1);
+            launch_fine_apply(s, h->fg, cf, 0, 0, 1, trans, x, Vj(0), f, 0, nullptr, nullptr, 1, 1);
         }
         launch_dot(s, n, Vj(0), Vj(0), h->partials, h->dscal + 9);
         HIPCHK(hipMemcpyAsync(h->hbuf, h->dscal + 9, sizeof(double), hipMemcpyDeviceToHost, s));

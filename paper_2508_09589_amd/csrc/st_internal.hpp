@@ -127,7 +127,7 @@ void launch_simp(hipStream_t s, long long ne, const double* rho, const st_materi
                  double* k, double* c, double* dk, double* dc, float* k32, float* c32, int cuniform);
 void launch_fine_apply(hipStream_t s, const FineGeom& g, const Coef& cf, int prec_in, int prec_out,
                        int compute64, int trans, const void* x, void* y, const void* b,
-                       const void* invd, const double* scale, const int* skip, int mask_in,
+                       int jacobi, const double* scale, const int* skip, int mask_in,
                        int dir_rows);
 void launch_fine_invdiag(hipStream_t s, const FineGeom& g, const Coef& cf, double dx, double dt,
                          double* invd64, float* invd32, uint8_t* mask);
@@ -200,12 +200,16 @@ void launch_sstep_coefficients(hipStream_t s, long long n, int prec, const void*
 // Exact coarsest-level solve by block-tridiagonal factorisation in time.
 constexpr int CD_MAX_PLANE = 2048;        // largest (nx + 1)(ny + 1) it is used for
 constexpr size_t CD_LDS_MAX = 56 * 1024;  // Gauss-Jordan matrix in LDS up to this size
+constexpr int CD_FAST_P = 128;            // fast solve: plane size bound (8 | CD_FAST_P)
+constexpr int CD_FAST_NODES = 3072;       // fast solve: whole level in 2 x 24 KB of LDS
 bool coarse_direct_fits(int P);
+bool coarse_direct_fast(int P, int nt);
 size_t coarse_direct_lds(int P);
 void launch_coarse_factor(hipStream_t s, const Level& L, double* Ag, double* Dinv, double* G,
-                          double* colk, int* perm, int* status);
+                          double* H, double* M, double* colk, int* perm, int* status);
 void launch_coarse_direct(hipStream_t s, const Level& L, int prec_io, int trans, const void* b,
-                          void* x, const double* Dinv, const double* G, double* work);
+                          void* x, const double* Dinv, const double* G, const double* H,
+                          const double* M, double* work);
 
 // Right-hand side, objective, sensitivities, filter.
 void launch_load_uniform(hipStream_t s, const FineGeom& g, double q0, double dx, double dt,

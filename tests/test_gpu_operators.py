@@ -302,7 +302,9 @@ def test_vcycle_matches_oracle(torch_cuda, tv, coarse, full):
 def test_direct_coarse_solve_is_exact(torch_cuda, nx, ny, nt, tv):
     """A one-level hierarchy makes the V-cycle the coarsest-level solve: the
     block-tridiagonal factorisation must reproduce the oracle's direct solve,
-    forward and transposed (12 x 12 runs the Gauss-Jordan step out of LDS)."""
+    forward and transposed (12 x 12 runs the Gauss-Jordan step out of LDS and
+    its plane of 169 nodes is past the LDS-resident fast solve, which the
+    others take)."""
     from oracle.solve import solve_direct, solve_adjoint_direct
     c = Case(nx, ny, nt, tv=tv, seed=nx + 3 * ny + 7 * nt,
              patches=((0, 0.5 * ny / max(nx, ny), 0.2), (3, 0.4, 0.3)))

@@ -148,3 +148,28 @@ def test_delayed_cgs2_matches_classical_cgs2(torch_cuda, restart):
         assert rel(out[name][2], la) <= 1e-10, name
     assert abs(out["delayed"][1] - out["classical"][1]) <= 1
     assert abs(out["delayed"][3] - out["classical"][3]) <= 1
+
+
+def test_repeated_solves_are_bitwise_identical(torch_cuda):
+    """Every reduction on the path is a fixed tree (no floating-point
+    atomics), so two solves of one problem, and the solve of a second problem
+    set up from the same input, return the same iterate bit for bit after the
+    same number of iterations.  64^2 x 128 elements, time-varying density,
+    the benchmark's mixed configuration with FGMRES(20): enough restarts for a
+    rounding difference anywhere to change the count."""
+    import torch
+    from paper_2508_09589_amd import Problem
+    from paper_2508_09589_amd.inputs import smooth_density
+    rho = torch.tensor(smooth_density(64, 64, 128, seed=5))
+    kw = dict(precision="mixed", restart=20, rtol=1e-10, bf16_from_level=1, smoother="sstep")
+    p = Problem(64, 64, 128, rho, **kw)
+    T1, i1 = p.solve()
+    T1 = T1.clone()
+    T2, i2 = p.solve()
+    q = Problem(64, 64, 128, rho, **kw)
+    T3, i3 = q.solve()
+    print(f"iterations {i1.iterations} {i2.iterations} {i3.iterations}", flush=True)
+    assert i1.iterations == i2.iterations == i3.iterations
+    assert torch.equal(T1, T2) and torch.equal(T1, T3)
+    p.close()
+    q.close()
