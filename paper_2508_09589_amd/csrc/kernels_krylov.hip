@@ -11,6 +11,7 @@
 // them into the orthonormal v_d inside the scalar coefficients, so no pass is
 // spent on normalising a vector.
 #include "st_internal.hpp"
+#include "reduce_core.hpp"
 
 namespace st {
 
@@ -377,24 +378,12 @@ constexpr int FUSE_MAX = 16;
 template <int MAXD>
 __device__ void block_finish(double (&acc)[MAXD], int nd, double* __restrict__ partials,
                              KState* ks, int mode, int j, double* out) {
-    __shared__ double red[VEC_THREADS / 64][MAXD];
+    __shared__ double bsum[MAXD];
     __shared__ double sums[MAXD];
     __shared__ int amlast;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int d = 0; d < MAXD; ++d) {
-        if (d < nd) {
-            const double v = wave_sum(acc[d]);
-            if (lane == 0) red[wave][d] = v;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < nd) {
-        double v = 0.0;
-#pragma unroll
-        for (int w = 0; w < VEC_THREADS / 64; ++w) v += red[w][threadIdx.x];
-        partials[(long long)blockIdx.x * MAXD + threadIdx.x] = v;
-    }
+    block_sum_many<MAXD, VEC_THREADS>(acc, nd, bsum);
+    for (int d = threadIdx.x; d < nd; d += VEC_THREADS)
+        partials[(long long)blockIdx.x * MAXD + d] = bsum[d];
     if (gridDim.x > FUSE_MAX) return;   // uniform over the grid
     __threadfence();
     __syncthreads();
@@ -406,14 +395,7 @@ __device__ void block_finish(double (&acc)[MAXD], int nd, double* __restrict__ p
     __syncthreads();
     if (!amlast) return;
     __threadfence();
-    const int nb = gridDim.x;
-    for (int d = wave; d < nd; d += VEC_THREADS / 64) {
-        double v = 0.0;
-        for (int b = lane; b < nb; b += 64) v += partials[(long long)b * MAXD + d];
-        v = wave_sum(v);
-        if (lane == 0) sums[d] = v;
-    }
-    __syncthreads();
+    sum_block_partials<VEC_THREADS>(partials, (int)gridDim.x, MAXD, nd, sums);
     if (threadIdx.x == 0) *counter = 0u;
     if (ks)
         kstate_finalize_block(ks, mode, j, sums, nd);
@@ -422,20 +404,15 @@ __device__ void block_finish(double (&acc)[MAXD], int nd, double* __restrict__ p
 }
 
 // One block: sum the partials of a reduction grid (block order) and finalise.
+// A full-size workgroup, so that the partial sums keep many loads in flight.
+constexpr int RF_THREADS = 1024;
 template <int MAXD>
-__global__ __launch_bounds__(VEC_THREADS) void k_reduce_finalize(const double* __restrict__ partials,
-                                                                 int nb, int nd, KState* ks,
-                                                                 int mode, int j, double* out) {
+__global__ __launch_bounds__(RF_THREADS) void k_reduce_finalize(const double* __restrict__ partials,
+                                                                int nb, int nd, KState* ks,
+                                                                int mode, int j, double* out) {
     __shared__ double sums[MAXD];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (ks && ks->done && mode != FIN_INIT_SELF && mode != FIN_INIT_REF) return;
-    for (int d = wave; d < nd; d += VEC_THREADS / 64) {
-        double v = 0.0;
-        for (int b = lane; b < nb; b += 64) v += partials[(long long)b * MAXD + d];
-        v = wave_sum(v);
-        if (lane == 0) sums[d] = v;
-    }
-    __syncthreads();
+    sum_block_partials<RF_THREADS>(partials, nb, MAXD, nd, sums);
     if (ks)
         kstate_finalize_block(ks, mode, j, sums, nd);
     else if (threadIdx.x == 0)
@@ -446,7 +423,7 @@ template <int MAXD>
 static void finish(hipStream_t s, unsigned nb, int nd, double* partials, KState* ks, int mode,
                    int j, double* out) {
     if ((int)nb <= FUSE_MAX) return;
-    hipLaunchKernelGGL(k_reduce_finalize<MAXD>, dim3(1), dim3(VEC_THREADS), 0, s, partials,
+    hipLaunchKernelGGL(k_reduce_finalize<MAXD>, dim3(1), dim3(RF_THREADS), 0, s, partials,
                        (int)nb, nd, ks, mode, j, out);
 }
 

@@ -9,6 +9,7 @@
 // Reductions are deterministic: fixed trees inside a workgroup, partials summed
 // in workgroup order by the solve kernel.
 #include "st_internal.hpp"
+#include "reduce_core.hpp"
 
 namespace st {
 
@@ -87,20 +88,10 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram(long long n, const T* __res
 #pragma unroll
             for (int b = a; b < NV; ++b) acc[p++] += v[a] * v[b];
     }
-    __shared__ double red[GR_THREADS / 64][NP];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        const double s = gr_wave_sum(acc[p]);
-        if (lane == 0) red[w][p] = s;
-    }
-    __syncthreads();
-    for (int p = threadIdx.x; p < NP; p += blockDim.x) {
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < GR_THREADS / 64; ++q) s += red[q][p];
-        part[(long long)p * GR_MAX_BLOCKS + blockIdx.x] = s;
-    }
+    __shared__ double bsum[NP];
+    block_sum_many<NP, GR_THREADS>(acc, NP, bsum);
+    for (int p = threadIdx.x; p < NP; p += blockDim.x)
+        part[(long long)p * GR_MAX_BLOCKS + blockIdx.x] = bsum[p];
 }
 
 // One workgroup per pair p sums its partials (thread t adds workgroups t,
@@ -171,7 +162,9 @@ __global__ __launch_bounds__(GR_THREADS) void k_sstep_solve(const double* __rest
             if (!isfinite(gd)) bad = 1;
             sc[d] = gd > 0.0 ? 1.0 / sqrt(gd) : 0.0;
         }
-        double Lf[K > 0 ? K : 1][K > 0 ? K : 1], z[K > 0 ? K : 1];
+        // Lf holds the factor, ri the reciprocals of its diagonal (one division
+        // per column on the dependent chain instead of one per entry)
+        double Lf[K > 0 ? K : 1][K > 0 ? K : 1], z[K > 0 ? K : 1], ri[K > 0 ? K : 1];
         bool stop = bad != 0;
         double zz = 0.0;
 #pragma unroll
@@ -185,7 +178,7 @@ __global__ __launch_bounds__(GR_THREADS) void k_sstep_solve(const double* __rest
                         double v = G[gidx(c + 1, r + 1)] * sc[c + 1] * sc[r + 1];
 #pragma unroll
                         for (int e = 0; e < c; ++e) v -= Lf[r][e] * Lf[c][e];
-                        Lf[r][c] = v / Lf[c][c];
+                        Lf[r][c] = v * ri[c];
                     }
                     double piv = 1.0;   // Gs[r][r] = 1 by the scaling
 #pragma unroll
@@ -194,10 +187,11 @@ __global__ __launch_bounds__(GR_THREADS) void k_sstep_solve(const double* __rest
                         stop = true;
                     } else {
                         Lf[r][r] = sqrt(piv);
+                        ri[r] = 1.0 / Lf[r][r];
                         double v = G[gidx(0, r + 1)] * sc[0] * sc[r + 1];
 #pragma unroll
                         for (int e = 0; e < r; ++e) v -= Lf[r][e] * z[e];
-                        z[r] = v / Lf[r][r];
+                        z[r] = v * ri[r];
                         zz += z[r] * z[r];
                         m = r + 1;
                         res2 = fmax(1.0 - zz, 0.0);
@@ -214,7 +208,7 @@ __global__ __launch_bounds__(GR_THREADS) void k_sstep_solve(const double* __rest
 #pragma unroll
                 for (int c = i + 1; c < K; ++c)
                     if (c < m) v -= Lf[c][i] * y[c];
-                y[i] = v / Lf[i][i];
+                y[i] = v * ri[i];
             }
         }
 #pragma unroll
