@@ -521,6 +521,40 @@ void launch_scale_norm(hipStream_t s, long long n, int prec, const void* b, cons
     finish<1>(s, nb, 1, partials, ks, mode, 0, nullptr);
 }
 
+// w = invd .* b without the norm (the s-step smoother's first vector: its
+// norm comes out of the Gram pass).
+template <typename T>
+__global__ __launch_bounds__(VEC_THREADS) void k_scale(long long n, const T* __restrict__ b,
+                                                       const T* __restrict__ invd,
+                                                       T* __restrict__ w, int vec) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long t0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    long long tail = 0;
+    if (vec) {
+        const long long n4 = n >> 2;
+        for (long long q = t0; q < n4; q += stride) {
+            typename V4<T>::type bv = *reinterpret_cast<const typename V4<T>::type*>(b + 4 * q);
+            const typename V4<T>::type dv = *reinterpret_cast<const typename V4<T>::type*>(invd + 4 * q);
+            bv.x *= dv.x; bv.y *= dv.y; bv.z *= dv.z; bv.w *= dv.w;
+            *reinterpret_cast<typename V4<T>::type*>(w + 4 * q) = bv;
+        }
+        tail = 4 * n4;
+    }
+    for (long long i = tail + t0; i < n; i += stride) w[i] = b[i] * invd[i];
+}
+
+void launch_scale(hipStream_t s, long long n, int prec, const void* b, const void* invd, void* w) {
+    const size_t es = prec ? 4 : 8;
+    const int vec = al4(b, es) && al4(w, es) && al4(invd, es);
+    const unsigned nb = vec ? red_grid4(n) : red_grid(n);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_scale<double>, dim3(nb), dim3(VEC_THREADS), 0, s, n, (const double*)b,
+                           (const double*)invd, (double*)w, vec);
+    else
+        hipLaunchKernelGGL(k_scale<float>, dim3(nb), dim3(VEC_THREADS), 0, s, n, (const float*)b,
+                           (const float*)invd, (float*)w, vec);
+}
+
 // ---------------------------------------------------------------------------
 // Multi-dot: h_d = <V_d, w>, d < nd (mode FIN_PROJ1 / FIN_INIT_*).
 template <typename TW, typename TV, int MAXD>

@@ -74,22 +74,41 @@ void launch_stencil_apply(hipStream_t s, const Level& L, int prec, int trans, co
         stencil_dispatch<float, float, float>(s, L, L.st32, trans, x, y, b, invd, scale, skip);
 }
 
+// Row j of in-plane index r on rows of length rowp, without an integer
+// division: a reciprocal multiply (double, exact to one step for r < 2^31)
+// corrected by one step either way.
+__device__ __forceinline__ int row_of(int r, int rowp, double inv) {
+    int j = (int)((double)r * inv);
+    if (j * rowp > r)
+        --j;
+    else if ((j + 1) * rowp <= r)
+        ++j;
+    return j;
+}
+
+// Transfers run one thread per in-plane node and a grid row per time level
+// (looping when there are more levels than grid rows).
+static inline dim3 plane_grid(const Level& L) {
+    const long long P = (long long)(L.nx + 1) * (L.ny + 1);
+    const long long gy = L.nt + 1 < 65535 ? L.nt + 1 : 65535;
+    return dim3((unsigned)((P + 255) / 256), (unsigned)gy);
+}
+
 // ---------------------------------------------------------------------------
 // Restriction b_c = P_m^T r_f = P^T N_f r_f.  Space: coarse (I, J, n) gathers
 // fine (2I+a, 2J+c, n), a, c in {-1, 0, 1}, weight w(a) w(c) with w(0) = 1,
 // w(+-1) = 1/2.  Time: coarse (i, j, N) gathers fine (i, j, 2N+a).
 template <typename T>
 __global__ void k_restrict(int how, int nxf, int nyf, int ntf, int nxc, int nyc, int ntc,
-                           const uint8_t* __restrict__ maskf, const T* __restrict__ rf,
-                           T* __restrict__ bc) {
-    const long long rowc = nxc + 1, Pc = rowc * (nyc + 1);
-    const long long Nc = Pc * (ntc + 1);
+                           double inv_rowc, const uint8_t* __restrict__ maskf,
+                           const T* __restrict__ rf, T* __restrict__ bc) {
+    const int rowc = nxc + 1, Pc = rowc * (nyc + 1);
     const long long rowf = nxf + 1, Pf = rowf * (nyf + 1);
-    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < Nc;
-         idx += (long long)gridDim.x * blockDim.x) {
-        const int n = (int)(idx / Pc);
-        const long long r = idx - n * Pc;
-        const int J = (int)(r / rowc), I = (int)(r - (long long)J * rowc);
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= Pc) return;
+    const int J = row_of(r, rowc, inv_rowc), I = r - J * rowc;
+    for (int n = blockIdx.y; n <= ntc; n += gridDim.y) {
+        const long long idx = (long long)n * Pc + r;
         double acc = 0.0;
         if (how == 1) {
             for (int c = -1; c <= 1; ++c) {
@@ -137,30 +156,30 @@ __global__ void k_restrict(int how, int nxf, int nyf, int ntf, int nxc, int nyc,
 
 void launch_restrict(hipStream_t s, const Level& F, const Level& C, int prec, const void* rf,
                      void* bc) {
-    const unsigned nb = grid_for(C.nn);
+    const dim3 grid = plane_grid(C);
+    const double inv = 1.0 / (C.nx + 1);
     if (prec == 0)
-        hipLaunchKernelGGL(k_restrict<double>, dim3(nb), dim3(256), 0, s, C.how, F.nx, F.ny, F.nt,
-                           C.nx, C.ny, C.nt, F.mask, (const double*)rf, (double*)bc);
+        hipLaunchKernelGGL(k_restrict<double>, grid, dim3(256), 0, s, C.how, F.nx, F.ny, F.nt,
+                           C.nx, C.ny, C.nt, inv, F.mask, (const double*)rf, (double*)bc);
     else
-        hipLaunchKernelGGL(k_restrict<float>, dim3(nb), dim3(256), 0, s, C.how, F.nx, F.ny, F.nt,
-                           C.nx, C.ny, C.nt, F.mask, (const float*)rf, (float*)bc);
+        hipLaunchKernelGGL(k_restrict<float>, grid, dim3(256), 0, s, C.how, F.nx, F.ny, F.nt,
+                           C.nx, C.ny, C.nt, inv, F.mask, (const float*)rf, (float*)bc);
 }
 
 // Prolongation x_f (+)= P_m e_c: zero at fine Dirichlet nodes.
 template <typename T>
 __global__ void k_prolong(int how, int nxf, int nyf, int ntf, int nxc, int nyc, int ntc,
-                          const uint8_t* __restrict__ maskf, const T* __restrict__ ec,
-                          T* __restrict__ xf, int accumulate) {
-    const long long rowf = nxf + 1, Pf = rowf * (nyf + 1);
-    const long long Nf = Pf * (ntf + 1);
+                          double inv_rowf, const uint8_t* __restrict__ maskf,
+                          const T* __restrict__ ec, T* __restrict__ xf, int accumulate) {
+    const int rowf = nxf + 1, Pf = rowf * (nyf + 1);
     const long long rowc = nxc + 1, Pc = rowc * (nyc + 1);
-    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < Nf;
-         idx += (long long)gridDim.x * blockDim.x) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= Pf) return;
+    const int j = row_of(r, rowf, inv_rowf), i = r - j * rowf;
+    for (int n = blockIdx.y; n <= ntf; n += gridDim.y) {
+        const long long idx = (long long)n * Pf + r;
         double v = 0.0;
         if (!maskf[idx]) {
-            const int n = (int)(idx / Pf);
-            const long long r = idx - n * Pf;
-            const int j = (int)(r / rowf), i = (int)(r - (long long)j * rowf);
             if (how == 1) {
                 const int i0 = i >> 1, j0 = j >> 1;
                 const bool io = i & 1, jo = j & 1;
@@ -206,13 +225,16 @@ __global__ void k_prolong(int how, int nxf, int nyf, int ntf, int nxc, int nyc, 
 
 void launch_prolong(hipStream_t s, const Level& F, const Level& C, int prec, const void* ec,
                     void* xf, int accumulate) {
-    const unsigned nb = grid_for(F.nn);
+    const dim3 grid = plane_grid(F);
+    const double inv = 1.0 / (F.nx + 1);
     if (prec == 0)
-        hipLaunchKernelGGL(k_prolong<double>, dim3(nb), dim3(256), 0, s, C.how, F.nx, F.ny, F.nt,
-                           C.nx, C.ny, C.nt, F.mask, (const double*)ec, (double*)xf, accumulate);
+        hipLaunchKernelGGL(k_prolong<double>, grid, dim3(256), 0, s, C.how, F.nx, F.ny, F.nt,
+                           C.nx, C.ny, C.nt, inv, F.mask, (const double*)ec, (double*)xf,
+                           accumulate);
     else
-        hipLaunchKernelGGL(k_prolong<float>, dim3(nb), dim3(256), 0, s, C.how, F.nx, F.ny, F.nt,
-                           C.nx, C.ny, C.nt, F.mask, (const float*)ec, (float*)xf, accumulate);
+        hipLaunchKernelGGL(k_prolong<float>, grid, dim3(256), 0, s, C.how, F.nx, F.ny, F.nt,
+                           C.nx, C.ny, C.nt, inv, F.mask, (const float*)ec, (float*)xf,
+                           accumulate);
 }
 
 // Coarse Dirichlet mask: a coarse node is Dirichlet when every fine node in the

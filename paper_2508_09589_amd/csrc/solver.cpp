@@ -432,7 +432,7 @@ void smooth(st_handle* h, int l, int prec, int trans, const void* b, void* x, in
     if ((h->opts.flags & ST_FLAG_SSTEP_SMOOTHER) && its <= SSTEP_MAX_ITS) {
         if (zero_x0) {
             Timed t(h, kd, n * (int64_t)(3 * vb));
-            launch_scale_norm(s, n, prec, b, invd, Vj(0), h->partials, ks, FIN_INIT_SELF, its, rtol, 1);
+            launch_scale(s, n, prec, b, invd, Vj(0));
         } else {
             level_apply(h, l, prec, trans, x, Vj(0), b, invd, nullptr, nullptr);
         }

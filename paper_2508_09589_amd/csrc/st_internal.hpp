@@ -153,6 +153,7 @@ void launch_cast(hipStream_t s, long long n, int from, int to, const void* in, v
 void launch_fill(hipStream_t s, long long n, int prec, void* p, double v);
 
 // Krylov kernels.
+void launch_scale(hipStream_t s, long long n, int prec, const void* b, const void* invd, void* w);
 void launch_scale_norm(hipStream_t s, long long n, int prec, const void* b, const void* invd,
                        void* w, double* partials, KState* ks, int mode, int maxit, double rtol,
                        int scale_update);
