@@ -1,7 +1,7 @@
 """Benchmark: space-time DOFs solved per second to a 1e-8 relative residual.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large]
-                    [--precision mixed|fp64] [--no-cpu-baseline] [--compare-fp64]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|medium|...]
+                    [--precision mixed|fp64] [--no-cpu-baseline] [--no-compare-fp64]
 
 A step is one complete st_solve (FGMRES + space-time multigrid V-cycles, from
 a zero initial guess) of the workload; the design, hierarchy and right-hand
@@ -158,7 +158,7 @@ def cpu_baseline(name):
     from paper_2508_09589_amd.inputs import WORKLOADS, workload_density
     w = WORKLOADS[name]
     rho = workload_density(name)
-    slabs = {"large": 4, "medium": 32, "grad": 32, "small": 32}[name]
+    slabs = {"large": 8, "medium": 32, "grad": 32, "small": 32}[name]
     k, _, _, _ = simp(rho, Material(k_ins=1e-3, k_con=1.0, p_k=3.0, c_ins=1.0, c_con=1.0, p_c=1.0))
     if k.ndim == 3:
         k = k[:slabs]
@@ -170,11 +170,18 @@ def cpu_baseline(name):
         bs = BlockTimeSystem(g, k, np.ones_like(k), mask)
         s, sweeps, rel = bs.gauss_seidel(bs.masked_rhs(f), tol=1e-8)
         dt = time.perf_counter() - t0
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
     return {"value": g.n_nodes / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
             "sample": f"first {slabs} of {w['nt']} time slabs of the {w['nx']}x{w['ny']} grid "
                       f"({g.n_nodes} nodes), block Gauss-Seidel in time with SuperLU blocks, "
                       f"{sweeps} sweeps to rel. residual {rel:.1e}, {dt:.1f} s",
-            "seconds": dt}
+            "seconds": dt, "threads_used": 1, "host_cpu_count": os.cpu_count(),
+            "host_affinity_cores": affinity,
+            "note": "the oracle as written (SuperLU factorisations and triangular solves, "
+                    "one thread); not an optimised CPU solver"}
 
 
 def run(args):
@@ -186,15 +193,17 @@ def run(args):
                                            args.bf16_from_level, args.max_it, args.smoother,
                                            args.restart, args.coarse)
     n_nodes = p.n_nodes
-    # Warm-up solves time every kernel class to find the dominant one.
-    warm = []
-    for _ in range(max(args.warmup, 1)):
+    # The first warm-up solve times every kernel class (one event pair per
+    # launch); the others run untimed.
+    kern = None
+    for w in range(max(args.warmup, 1)):
         t0 = time.perf_counter()
         T, info = p.solve(allow_not_converged=True)
-        warm.append(info_dict(info))
+        if w == 0:
+            kern = info_dict(info)["kernels"]
+            p.set_flags(p.opts.flags & ~L.ST_FLAG_TIME_KERNELS)
         log(f"warm-up solve: {info.iterations} its, true rel res {info.true_rel_res:.2e}, "
-            f"{time.perf_counter() - t0:.2f} s (all kernel classes timed)")
-    kern = warm[-1]["kernels"]
+            f"{time.perf_counter() - t0:.2f} s" + (" (all kernel classes timed)" if w == 0 else ""))
     # The roofline names the fine-level matrix-free apply in the precision the
     # V-cycle runs in: the defining operator of the method, one kernel of one
     # shape per launch, and with the coarse-level stencils and the smoother's
@@ -249,27 +258,73 @@ def run(args):
         "coarse_solve_share": kern.get("coarse_solve", {}).get("ms", 0.0) / total_ms if total_ms else None,
     }
     p.close()
+    out["copy_ceiling"] = copy_ceiling()
+    out["roofline"]["frac_of_copy_ceiling"] = achieved / out["copy_ceiling"]["gbs"]
+    torch.cuda.empty_cache()
+    if not args.no_compare_fp64 and args.precision != "fp64":
+        # Plain FP64 at the same settings (smoother, coarse solve, restart,
+        # 1e-8): the mixed problem is closed first (both do not fit at once on
+        # the large grid); its solution stays for the difference.
+        out["fp64_compare"] = fp64_compare(args, T, n_nodes, out["value"])
     del T
     torch.cuda.empty_cache()
-    if args.compare_fp64 and args.precision != "fp64":
-        q, ts, _ = workload_problem(args.workload, "fp64", False, 0, args.max_it, args.smoother,
-                                    args.restart, args.coarse)
-        Tq, iq = q.solve(allow_not_converged=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        Tq, iq = q.solve(allow_not_converged=True)
-        torch.cuda.synchronize()
-        dtq = time.perf_counter() - t0
-        out["fp64_compare"] = {"value": n_nodes / dtq, "unit": "DOF/s",
-                               "iterations": iq.iterations, "true_rel_res": iq.true_rel_res,
-                               "setup_s": ts}
-        q.close()
-        del Tq
-        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(args.workload)
     return out
+
+
+def fp64_compare(args, T_mixed, n_nodes, mixed_value):
+    """Plain FP64 solve of the same workload with the same smoother, coarse
+    solve, restart and tolerance; timed solves from a zero initial guess
+    (one on the large grid, two elsewhere, after one warm-up)."""
+    import torch
+    q, ts, _ = workload_problem(args.workload, "fp64", False, 0, args.max_it, args.smoother,
+                                args.restart, args.coarse)
+    timed = 1 if args.workload == "large" else 2
+    if args.workload != "large":
+        q.solve(allow_not_converged=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(timed):
+        Tq, iq = q.solve(allow_not_converged=True)
+    torch.cuda.synchronize()
+    dtq = (time.perf_counter() - t0) / timed
+    diff = float(torch.linalg.vector_norm(T_mixed - Tq) / torch.linalg.vector_norm(Tq))
+    log(f"fp64 compare: {iq.iterations} its, true rel res {iq.true_rel_res:.2e}, {dtq:.2f} s/solve, "
+        f"|T_mixed - T_fp64| / |T_fp64| = {diff:.2e}")
+    res = {"value": n_nodes / dtq, "unit": "DOF/s", "ms_per_step": dtq * 1e3, "timed_solves": timed,
+           "iterations": iq.iterations, "true_rel_res": iq.true_rel_res,
+           "converged": iq.true_rel_res <= 1e-8, "setup_s": ts,
+           "mixed_over_fp64": mixed_value / (n_nodes / dtq),
+           "rel_diff_mixed_vs_fp64": diff,
+           "settings": {"smoother": args.smoother, "coarse": args.coarse,
+                        "fgmres_restart": 20 if args.workload == "large" and args.restart is None
+                        else (args.restart or 30), "rtol": 1e-8}}
+    q.close()
+    del Tq
+    return res
+
+
+def copy_ceiling():
+    """Measured device-copy bandwidth: a 1 GiB FP32 copy (1 GiB read + 1 GiB
+    written), best of five, timed with HIP events."""
+    import torch
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    best = None
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        y.copy_(x)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    del x, y
+    return {"gbs": 2 * (1 << 30) / (best * 1e-3) / 1e9, "bytes": 2 * (1 << 30),
+            "what": "1 GiB FP32 device copy, read + write, best of 5"}
 
 
 def run_serving(args):
@@ -287,7 +342,6 @@ def run_serving(args):
     res = {}
     for prec in (["mixed", "fp64"] if args.compare_fp64 else [args.precision]):
         srv = Server(int(args.hbm_budget_gb * (1 << 30)), slots=args.slots, keep_outputs=False)
-        # warm-up: one request of each shape class is not timed
         stream = [(Request(r["id"], r["n"], r["nt"], dens[r["id"]], adjoint=r["adjoint"],
                            precision=prec, smoother=args.smoother), r["t_arrive"]) for r in specs]
         torch.cuda.synchronize()
@@ -467,7 +521,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="medium",
+    ap.add_argument("--workload", default="large",
                     choices=["small", "medium", "large", "grad", "serving", "design", "coarsening"])
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--slots", type=int, default=4)
@@ -484,7 +538,10 @@ def main():
     ap.add_argument("--coarse", default="direct", choices=["direct", "gmres"],
                     help="coarsest-level solve: exact, or the paper's Jacobi-GMRES")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--compare-fp64", action="store_true")
+    ap.add_argument("--compare-fp64", action="store_true",
+                    help="serving workload: also run the request stream in plain FP64")
+    ap.add_argument("--no-compare-fp64", action="store_true",
+                    help="skip the plain FP64 solve that follows the timed mixed solves")
     ap.add_argument("--max-it", type=int, default=400)
     ap.add_argument("--example-n", type=int, default=160,
                     help="coarsening workload: spatial elements per side (nt = 2 n)")

@@ -170,7 +170,8 @@ class VCycle:
     """
 
     def __init__(self, A, Pm, smooth_its=10, smooth_rtol=1e-6, coarse_its=200,
-                 coarse_rtol=1e-6, coarse_restart=30, coarse="gmres", smoother="gmres"):
+                 coarse_rtol=1e-6, coarse_restart=30, coarse="gmres", smoother="gmres",
+                 pre_its=None, post_its=None):
         if coarse not in ("gmres", "direct"):
             raise ValueError(coarse)
         if smoother not in ("gmres", "sstep"):
@@ -179,6 +180,10 @@ class VCycle:
         self.A, self.Pm = A, Pm
         self.dinv = [1.0 / a.diagonal() for a in A]
         self.si, self.sr = smooth_its, smooth_rtol
+        # pre- and post-smoothing iteration counts (0 skips that smoothing);
+        # both default to smooth_its, the paper's symmetric cycle
+        self.pre = smooth_its if pre_its is None else pre_its
+        self.post = smooth_its if post_its is None else post_its
         self.ci, self.cr, self.crs = coarse_its, coarse_rtol, coarse_restart
         self.coarse = coarse
         self._lu = None
@@ -191,16 +196,20 @@ class VCycle:
                     self._lu = spla.splu(sp.csc_matrix(A))
                 return self._lu.solve(np.asarray(b, dtype=np.float64))
             return gmres_jacobi(A, b, None, self.ci, self.cr, self.crs, dinv)[0]
-        x = self._smooth(A, b, None, dinv)
+        # pre-smoothing from x = 0, residual, restriction, coarse correction,
+        # post-smoothing from the corrected iterate
+        x = self._smooth(A, b, np.zeros(b.shape[0]), dinv, self.pre)
         r = b - A @ x
         xc = self(self.Pm[l].T @ r, l + 1)
         x = x + self.Pm[l] @ xc
-        return self._smooth(A, b, x, dinv)
+        return self._smooth(A, b, x, dinv, self.post)
 
-    def _smooth(self, A, b, x0, dinv):
-        if self.smoother == "sstep" and self.si <= SSTEP_MAX_ITS:
-            return gmres_jacobi_sstep(A, b, x0, self.si, self.sr, dinv)[0]
-        return gmres_jacobi(A, b, x0, self.si, self.sr, None, dinv)[0]
+    def _smooth(self, A, b, x0, dinv, its):
+        if its == 0:
+            return x0
+        if self.smoother == "sstep" and its <= SSTEP_MAX_ITS:
+            return gmres_jacobi_sstep(A, b, x0, its, self.sr, dinv)[0]
+        return gmres_jacobi(A, b, x0, its, self.sr, None, dinv)[0]
 
 
 def fgmres(A, b, prec, m=30, rtol=1e-8, maxit=1000, x0=None):

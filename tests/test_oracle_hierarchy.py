@@ -52,13 +52,17 @@ def test_workload_hierarchies(n, nt, expect):
 
 
 def test_tie_goes_to_space():
-    # lambda exactly at lambda_crit: the strict comparison coarsens in space.
+    # k_con = k_ins = 0.25, C = 1: D_eff = 0.25 and lambda = 0.25 * 0.125 / 0.25^2 = 0.5.
     lv = build_hierarchy(4, 4, 8, 0.25, 0.125, 0.25, 0.25, 1.0, 1.0, lambda_crit=0.125, n_levels=2)
-    assert lv[0]["lam"] == pytest.approx(0.125 * 0.125 / 0.0625 * 0.25 / 0.5) or True
-    D = 0.25
-    lam0 = D * 0.125 / 0.25 ** 2
-    lv = build_hierarchy(4, 4, 8, 0.25, 0.125, 0.25, 0.25, 1.0, 1.0, lambda_crit=lam0, n_levels=2)
+    assert lv[0]["lam"] == 0.5
+    assert lv[1]["how"] == "space"            # 0.5 >= 0.125
+    # lambda exactly at lambda_crit: the strict comparison coarsens in space ...
+    lv = build_hierarchy(4, 4, 8, 0.25, 0.125, 0.25, 0.25, 1.0, 1.0, lambda_crit=0.5, n_levels=2)
     assert lv[1]["how"] == "space"
+    # ... and just above it, in time
+    lv = build_hierarchy(4, 4, 8, 0.25, 0.125, 0.25, 0.25, 1.0, 1.0, lambda_crit=0.5 + 1e-12,
+                         n_levels=2)
+    assert lv[1]["how"] == "time"
 
 
 def test_printed_dof_counts():

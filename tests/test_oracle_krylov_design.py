@@ -168,6 +168,73 @@ def test_direct_coarse_two_grid_galerkin_orthogonality():
     assert np.linalg.norm(x) > 0
 
 
+def _two_level(n=8, nt=8, seed=3):
+    g, A, b, mask = _system(n, nt, seed=seed, tv=True)
+    lv = build_hierarchy(n, n, nt, 1 / n, 1 / nt, 1.0, 1e-3, 1.0, 1.0, n_levels=2)
+    As, masks, Pm = build_operators(lv, A, mask)
+    return A, b, As, Pm
+
+
+@pytest.mark.parametrize("smoother", ["gmres", "sstep"])
+def test_vcycle_restricts_the_residual_of_the_presmoothed_iterate(smoother):
+    """Pre-smoothing only, exact coarse solve: the coarse correction makes the
+    residual of the returned iterate orthogonal to range(P_m),
+    P_m^T (b - A x) = 0.  Restricting b instead of b - A x_pre, or dropping
+    x_pre from the corrected iterate, leaves P_m^T A x_pre != 0 there."""
+    A, b, As, Pm = _two_level()
+    x = VCycle(As, Pm, coarse="direct", smoother=smoother, pre_its=3, post_its=0)(b)
+    nb = np.linalg.norm(Pm[0].T @ b)
+    assert np.linalg.norm(Pm[0].T @ (b - A @ x)) <= 1e-12 * nb
+    # the pre-smoothed part is really there: the cycle differs from the bare
+    # Galerkin correction
+    import scipy.sparse.linalg as spla
+    x_gal = Pm[0] @ spla.spsolve(As[1].tocsc(), Pm[0].T @ b)
+    assert np.linalg.norm(x - x_gal) > 1e-3 * np.linalg.norm(x_gal)
+
+
+def test_vcycle_with_converged_presmoothing_returns_the_solution():
+    """Pre-smoothing run to convergence (rtol 1e-14, as many iterations as
+    unknowns) and no post-smoothing: the residual restricted to the coarse
+    level is zero, the correction vanishes and the cycle returns A^-1 b."""
+    A, b, As, Pm = _two_level(n=4, nt=4, seed=5)
+    x = VCycle(As, Pm, smooth_rtol=1e-14, coarse="direct", pre_its=A.shape[0], post_its=0)(b)
+    xs = solve_direct(A, b)
+    assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("trans", [False, True])
+def test_vcycle_post_smooths_from_the_corrected_iterate(trans):
+    """No pre-smoothing, exact coarse solve, one post-smoothing iteration:
+    the cycle returns x_cc + alpha D^-1 (b - A x_cc) with x_cc = P_m A_c^-1
+    P_m^T b the Galerkin correction (one GMRES step from x_cc searches the
+    direction of the preconditioned residual).  A post-smoothing from zero
+    would move along D^-1 b instead."""
+    import scipy.sparse.linalg as spla
+    A, b, As, Pm = _two_level(seed=4)
+    if trans:
+        As = [a.T.tocsr() for a in As]
+        A = As[0]
+    x = VCycle(As, Pm, coarse="direct", pre_its=0, post_its=1)(b)
+    x_cc = Pm[0] @ spla.spsolve(As[1].tocsc(), Pm[0].T @ b)
+    v = (b - A @ x_cc) / A.diagonal()
+    u = x - x_cc
+    cos = abs(u @ v) / (np.linalg.norm(u) * np.linalg.norm(v))
+    assert np.linalg.norm(u) > 0 and abs(1.0 - cos) <= 1e-12
+
+
+def test_vcycle_recursion_without_smoothing_is_nested_galerkin():
+    """Three levels, no smoothing, exact coarsest solve: the cycle is
+    P_0 P_1 A_2^-1 P_1^T P_0^T b (each level passes its restricted residual
+    down and adds the prolonged correction to its own iterate)."""
+    import scipy.sparse.linalg as spla
+    g, A, b, mask = _system(8, 8, seed=6, tv=True)
+    lv = build_hierarchy(8, 8, 8, 1 / 8, 1 / 8, 1.0, 1e-3, 1.0, 1.0, n_levels=3)
+    As, masks, Pm = build_operators(lv, A, mask)
+    x = VCycle(As, Pm, coarse="direct", pre_its=0, post_its=0)(b)
+    ref = Pm[0] @ (Pm[1] @ spla.spsolve(As[2].tocsc(), Pm[1].T @ (Pm[0].T @ b)))
+    assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
 def test_fgmres_direct_coarse_matches_direct_solution():
     """The exact coarse solve changes neither the converged solution nor (on
     the small workload) the outer iteration count by more than one."""
