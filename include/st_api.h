@@ -118,6 +118,10 @@ typedef struct {
     double proj_beta;         /* Heaviside projection of the filtered design
                                  (§3.3.2): sharpness beta; 0 = no projection    */
     double proj_eta;          /* projection threshold eta, default 0.5          */
+    int32_t filter_max_it;    /* PDE filter: CG iteration cap, default 2000;
+                                 reaching it gives ST_NOT_CONVERGED             */
+    double filter_rtol;       /* PDE filter: CG stops at ||r|| <= filter_rtol
+                                 ||r_0||, default 1e-13                         */
 } st_opts;
 
 typedef struct {
@@ -166,7 +170,10 @@ st_status st_footprint_bytes(const st_grid* grid, const st_material* mat, const 
  *              or NULL for a uniform q0
  *   patches    n_patches (<= ST_MAX_PATCHES) T = 0 patches
  *   workspace  >= st_footprint_bytes, 256-byte aligned, device memory
- * rho, ic and source are copied; no caller pointer is kept. */
+ * rho, ic and source are copied; no caller pointer is kept.
+ * A density with a NaN or Inf entry gives ST_ERR_ARG.  When the density filter
+ * reaches opts->filter_max_it, the handle is still created from the field it
+ * reached and ST_NOT_CONVERGED is returned (the caller may st_destroy it). */
 st_status st_setup(const st_grid* grid, const st_material* mat,
                    const double* rho_dev, int32_t rho_time_varying,
                    const double* ic_dev, const double* source_dev, double q0,
@@ -175,7 +182,10 @@ st_status st_setup(const st_grid* grid, const st_material* mat,
                    void* hip_stream, st_handle** out);
 
 /* Replace the design (same layout as at setup) and rebuild every
- * density-dependent quantity; allocations are reused. */
+ * density-dependent quantity; allocations are reused.  Status as for
+ * st_setup: ST_ERR_ARG for a non-finite density (the handle keeps no valid
+ * operators until a finite one is loaded), ST_NOT_CONVERGED when the filter
+ * reaches its cap. */
 st_status st_update_density(st_handle* h, const double* rho_dev);
 
 /* Forward solve J s = f.  T_dev: in = initial guess (warm start, §3.2),
@@ -190,7 +200,8 @@ st_status st_adjoint_solve(st_handle* h, const double* g_dev, double* lambda_dev
  * element, summed over slabs for a time-constant design (§3.4.1), multiplied
  * by the projection's derivative at the filtered design when the problem
  * projects, then sent through the filter (F^T = F, §3.3.2) when it filters.
- * dJdrho_dev has the design's layout. */
+ * dJdrho_dev has the design's layout.  ST_NOT_CONVERGED (output written)
+ * when that filter solve reaches opts->filter_max_it. */
 st_status st_sensitivity(st_handle* h, const double* T_dev, const double* lambda_dev,
                          double* dJdrho_dev);
 
@@ -217,7 +228,9 @@ st_status st_pnorm(st_handle* h, const double* T_dev, double P, double* phi_host
 st_status st_volume(st_handle* h, double vf, double* chi_host, double* dchi_drho_dev);
 
 /* Apply the density filter F (§3.3.2) to an element field of the design's
- * layout.  ST_ERR_STATE when the problem has no filter. */
+ * layout.  ST_ERR_STATE when the problem has no filter; ST_NOT_CONVERGED
+ * (output written from the last CG iterate) when the filter's CG reaches
+ * opts->filter_max_it before opts->filter_rtol. */
 st_status st_filter(st_handle* h, const double* in_dev, double* out_dev);
 
 /* Move a built problem to another HIP stream (e.g. a serving slot's); the

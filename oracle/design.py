@@ -136,6 +136,26 @@ def objective_and_gradient(grid, mat, rho, patches, q0=1.0, r_elems=None, with_g
     return out
 
 
+def power_difference(a, b, p, d):
+    """a^p - b^p formed from the difference d = a - b itself:
+    (a - b) * sum_{q<p} a^q b^(p-1-q) for an integer exponent p (no
+    subtraction of nearly equal powers); other exponents subtract."""
+    pi = int(round(p))
+    if abs(p - pi) > 0 or pi < 1:
+        return a ** p - b ** p
+    acc = np.zeros_like(a)
+    for q in range(pi):
+        acc = acc + a ** q * b ** (pi - 1 - q)
+    return d * acc
+
+
+def simp_difference(a, b, d, mat):
+    """k(a) - k(b) and C(a) - C(b) of the SIMP laws (§2.2) for physical
+    densities a, b with d = a - b given."""
+    return ((mat.k_con - mat.k_ins) * power_difference(a, b, mat.p_k, d),
+            (mat.c_con - mat.c_ins) * power_difference(a, b, mat.p_c, d))
+
+
 def central_difference(grid, mat, rho, patches, e, h=1e-6, q0=1.0, r_elems=None):
     """(J(rho + h e_i) - J(rho - h e_i)) / (2h) without cancellation.
 
@@ -159,18 +179,7 @@ def central_difference(grid, mat, rho, patches, e, h=1e-6, q0=1.0, r_elems=None)
         fp, fm_, dphys = rp, rm, rp - rm
     kp, Cp, _, _ = simp(fp, mat)
     km, Cm, _, _ = simp(fm_, mat)
-    # k(a) - k(b) = (k_con - k_ins) (a^p - b^p), formed from the difference a - b
-    # itself: a^p - b^p = (a - b) * sum_{q<p} a^q b^(p-1-q) for integer p.
-    def powdiff(a, b, p, d):
-        pi = int(round(p))
-        if abs(p - pi) > 0 or pi < 1:
-            return a ** p - b ** p
-        acc = np.zeros_like(a)
-        for q in range(pi):
-            acc = acc + a ** q * b ** (pi - 1 - q)
-        return d * acc
-    dk = (mat.k_con - mat.k_ins) * powdiff(fp, fm_, mat.p_k, dphys)
-    dC = (mat.c_con - mat.c_ins) * powdiff(fp, fm_, mat.p_c, dphys)
+    dk, dC = simp_difference(fp, fm_, dphys, mat)
     mask = dirichlet_mask(grid, patches)
     f = load_vector(grid, q0)
     Jp, _ = apply_dirichlet(assemble_matrix(grid, kp, Cp), f, mask)

@@ -41,7 +41,8 @@ class st_opts(C.Structure):
                 ("coarse_rtol", C.c_double), ("coarse_restart", C.c_int32),
                 ("lambda_crit", C.c_double), ("max_levels", C.c_int32),
                 ("max_coarse_nodes", C.c_int64), ("filter_r", C.c_double), ("flags", C.c_int32),
-                ("proj_beta", C.c_double), ("proj_eta", C.c_double)]
+                ("proj_beta", C.c_double), ("proj_eta", C.c_double),
+                ("filter_max_it", C.c_int32), ("filter_rtol", C.c_double)]
 
 
 class st_info(C.Structure):

@@ -57,6 +57,38 @@ def build(jobs=4, verbose=False):
     return LIB
 
 
+def build_host_check(out_dir=None):
+    """Build tests/host_check.cpp against the library's host code compiled
+    with AddressSanitizer and UndefinedBehaviorSanitizer (host side only: the
+    kernels stay as built) and return the executable's path.  Needs the
+    kernel objects of build()."""
+    out_dir = out_dir or os.path.join(BUILD, "san")
+    os.makedirs(out_dir, exist_ok=True)
+    san_obj = os.path.join(out_dir, "solver_san.o")
+    cmd = [_hipcc(), "-x", "hip", "-c", os.path.join(CSRC, "solver.cpp"), "-o", san_obj] + FLAGS + [
+        "-O1", "-g", "-fno-omit-frame-pointer",
+        "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for the sanitized host code:\n{r.stderr}")
+    drv_obj = os.path.join(out_dir, "host_check.o")
+    gxx = ["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-I", os.path.join(ROOT, "include")]
+    r = subprocess.run(gxx + ["-c", os.path.join(ROOT, "tests", "host_check.cpp"), "-o", drv_obj],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"g++ failed for host_check.cpp:\n{r.stderr}")
+    kern = [os.path.join(BUILD, os.path.splitext(x)[0] + ".o") for x in SOURCES if x != "solver.cpp"]
+    exe = os.path.join(out_dir, "host_check")
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    r = subprocess.run(gxx + ["-o", exe, drv_obj, san_obj] + kern +
+                       ["-L", os.path.join(rocm, "lib"), "-Wl,-rpath," + os.path.join(rocm, "lib"),
+                        "-lamdhip64"], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link of host_check failed:\n{r.stderr}")
+    return exe
+
+
 if __name__ == "__main__":
     jobs = 4
     if "--jobs" in sys.argv:

@@ -279,6 +279,7 @@ st_status validate(const st_grid* g, const st_material* m, const st_opts* o) {
     if (o->coarse_max_it < 1 || o->max_it < 1) return ST_ERR_ARG;
     if (!(o->rtol >= 0) || !(o->smooth_rtol >= 0) || !(o->coarse_rtol >= 0)) return ST_ERR_ARG;
     if (!(o->filter_r >= 0)) return ST_ERR_ARG;
+    if (o->filter_max_it < 1 || !(o->filter_rtol >= 0)) return ST_ERR_ARG;
     if (!(o->proj_beta >= 0) || !(o->proj_eta > 0 && o->proj_eta < 1)) return ST_ERR_ARG;
     return ST_OK;
 }
@@ -598,8 +599,10 @@ st_status dedup_planes(st_handle* h, int l) {
 // ---------------------------------------------------------------------------
 // PDE filter (§3.3.2): F g = (1/8) E^T H^{-1} (V/8) E g with the nodal
 // Helmholtz operator H = K_d + M (natural boundaries), solved by
-// Jacobi-preconditioned CG to a relative residual of 1e-13.  F is symmetric, so
-// the same routine sends sensitivities back through the filter.
+// Jacobi-preconditioned CG to the relative residual filter_rtol (1e-13).  F is
+// symmetric, so the same routine sends sensitivities back through the filter.
+// Reaching filter_max_it iterations first writes the last iterate's filtered
+// field and returns ST_NOT_CONVERGED.
 st_status filter_apply(st_handle* h, const double* in, double* out) {
     hipStream_t s = h->stream;
     const st_grid& g = h->grid;
@@ -616,8 +619,11 @@ st_status filter_apply(st_handle* h, const double* in, double* out) {
     HIPCHK(hipMemcpyAsync(h->hbuf, scal + 3, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const double rr0 = h->hbuf[0];
-    const double tol2 = 1e-26 * rr0;
-    for (int it = 0; it < 2000 && rr0 > 0; ++it) {
+    if (!(rr0 == rr0) || rr0 > 1e300) return ST_ERR_BREAKDOWN;
+    const double tol2 = h->opts.filter_rtol * h->opts.filter_rtol * rr0;
+    const int maxit = h->opts.filter_max_it;
+    bool converged = !(rr0 > tol2);
+    for (int it = 0; it < maxit && !converged; ++it) {
         launch_tensor_op(s, nx, ny, nt, g.dx, g.dt, dxx, dtt, h->flt_p, h->flt_q, nullptr, nullptr,
                          nullptr);
         launch_cg_step(s, 0, n, h->flt_x, h->flt_r, h->flt_z, h->flt_p, h->flt_q, h->flt_invd,
@@ -628,26 +634,35 @@ st_status filter_apply(st_handle* h, const double* in, double* out) {
                        h->partials, scal, nullptr);
         launch_cg_step(s, 4, n, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, scal,
                        nullptr);
-        if (it % 4 == 3) {
+        if (it % 4 == 3 || it == maxit - 1) {
             HIPCHK(hipMemcpyAsync(h->hbuf, scal + 3, sizeof(double), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             if (!(h->hbuf[0] == h->hbuf[0])) return ST_ERR_BREAKDOWN;
-            if (h->hbuf[0] <= tol2) break;
+            converged = h->hbuf[0] <= tol2;
         }
     }
     launch_node_to_elem(s, nx, ny, nt, h->flt_x, out);
-    return ST_OK;
+    return converged ? ST_OK : ST_NOT_CONVERGED;
 }
 
 // SIMP coefficients, fine diagonal and mask, Galerkin hierarchy: every
 // density-dependent quantity.
+// A density that is not finite everywhere is rejected (ST_ERR_ARG) before
+// anything is built from it; a filter that reaches its iteration cap builds
+// the operators from the field it reached and returns ST_NOT_CONVERGED.
 st_status build_operators(st_handle* h) {
     hipStream_t s = h->stream;
     const st_grid& g = h->grid;
     st_status rc;
+    launch_dot(s, h->nde, h->rho, h->rho, h->partials, h->dscal + 5);
+    HIPCHK(hipMemcpyAsync(h->hbuf, h->dscal + 5, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (!std::isfinite(h->hbuf[0])) return ST_ERR_ARG;
+    st_status warn = ST_OK;
     if (h->opts.filter_r > 0) {
         rc = filter_apply(h, h->rho, h->rho_filt);
-        if (rc != ST_OK) return rc;
+        if (rc == ST_NOT_CONVERGED) warn = rc;
+        else if (rc != ST_OK) return rc;
     }
     if (h->opts.proj_beta > 0)
         launch_heaviside(s, h->nde, h->rho_filt, h->opts.proj_beta, h->opts.proj_eta, h->rho_phys,
@@ -694,7 +709,7 @@ st_status build_operators(st_handle* h) {
     }
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
-    return ST_OK;
+    return warn;
 }
 
 // Consistent load, Dirichlet lifting f_m = N (f - J g) + g and ||f_m||.
@@ -912,6 +927,8 @@ void st_opts_default(st_opts* o) {
     o->flags = 0;
     o->proj_beta = 0.0;
     o->proj_eta = 0.5;
+    o->filter_max_it = 2000;
+    o->filter_rtol = 1e-13;
 }
 
 const char* st_status_string(st_status s) {
@@ -1040,17 +1057,17 @@ st_status st_setup(const st_grid* grid, const st_material* mat, const double* rh
         launch_tensor_invdiag(s, grid->nx, grid->ny, h->fnt, grid->dx, grid->dt, rx * rx / 12.0,
                               rt * rt / 12.0, h->flt_invd);
     }
-    const double t0 = now_s();
     rc = build_operators(h);
+    const st_status warn = rc == ST_NOT_CONVERGED ? rc : ST_OK;
+    if (warn != ST_OK) rc = ST_OK;
     if (rc == ST_OK) rc = build_rhs(h, h->have_src, h->have_ic);
     if (rc != ST_OK) {
         st_destroy(h);
         return rc;
     }
-    (void)t0;
     h->setup_done = 1;
     *out = h;
-    return ST_OK;
+    return warn;
 }
 
 st_status st_update_density(st_handle* h, const double* rho_dev) {
@@ -1058,8 +1075,10 @@ st_status st_update_density(st_handle* h, const double* rho_dev) {
     if (!h->setup_done) return ST_ERR_STATE;
     HIPCHK(hipMemcpyAsync(h->rho, rho_dev, sizeof(double) * h->nde, hipMemcpyDeviceToDevice, h->stream));
     st_status rc = build_operators(h);
+    const st_status warn = rc == ST_NOT_CONVERGED ? rc : ST_OK;
+    if (warn != ST_OK) rc = ST_OK;
     if (rc == ST_OK) rc = build_rhs(h, h->have_src, h->have_ic);
-    return rc;
+    return rc == ST_OK ? warn : rc;
 }
 
 st_status st_solve(st_handle* h, double* T_dev, st_info* info) {
@@ -1123,13 +1142,14 @@ st_status st_sensitivity(st_handle* h, const double* T_dev, const double* lambda
     double* dst = chain ? h->gtmp : dJdrho_dev;
     launch_sensitivity(s, h->fg, h->grid.dx, h->grid.dt, T_dev, lambda_dev, h->dk, h->dc, dst,
                        h->rho_tv ? 0 : 1);
+    st_status rc = ST_OK;
     if (chain) {
-        st_status rc = chain_to_design(h, h->gtmp, dJdrho_dev);
-        if (rc != ST_OK) return rc;
+        rc = chain_to_design(h, h->gtmp, dJdrho_dev);
+        if (rc != ST_OK && rc != ST_NOT_CONVERGED) return rc;
     }
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
-    return ST_OK;
+    return rc;
 }
 
 st_status st_objective(st_handle* h, const double* T_dev, double* J_host) {
@@ -1198,9 +1218,9 @@ st_status st_filter(st_handle* h, const double* in_dev, double* out_dev) {
     if (!h || !in_dev || !out_dev) return ST_ERR_ARG;
     if (!(h->opts.filter_r > 0)) return ST_ERR_STATE;
     st_status rc = filter_apply(h, in_dev, out_dev);
-    if (rc != ST_OK) return rc;
+    if (rc != ST_OK && rc != ST_NOT_CONVERGED) return rc;
     HIPCHK(hipStreamSynchronize(h->stream));
-    return ST_OK;
+    return rc;
 }
 
 st_status st_set_stream(st_handle* h, void* hip_stream) {

@@ -43,8 +43,10 @@ class Request:
 
     @property
     def key(self):
+        """Requests with equal keys can share a resident problem: same grid,
+        design layout and solver options."""
         tv = np.asarray(self.rho).ndim == 3
-        return (self.n, self.nt, tv, self.precision)
+        return (self.n, self.nt, tv, self.precision, self.smoother)
 
     @property
     def dofs(self):
@@ -132,8 +134,23 @@ class Server:
             if self.closed and not self.queue:
                 return None
             for i, (req, fut) in enumerate(self.queue):
-                key = req.key
-                if self.pool.get(key):
+                if fut.cancelled():
+                    del self.queue[i]
+                    break
+                try:
+                    key = req.key
+                    pooled = bool(self.pool.get(key))
+                    need = 0 if pooled else self.footprint_fn(req.n, req.nt, key[2],
+                                                              req.precision)
+                except Exception as e:          # an invalid request fails alone
+                    del self.queue[i]
+                    if fut.set_running_or_notify_cancel():
+                        fut.set_exception(e)
+                    break
+                if pooled:
+                    if not fut.set_running_or_notify_cancel():
+                        del self.queue[i]
+                        break
                     p = self.pool[key].pop()
                     if not self.pool[key]:
                         del self.pool[key]
@@ -141,11 +158,12 @@ class Server:
                     self.busy_bytes += p.workspace_bytes + 256
                     del self.queue[i]
                     return req, fut, p, 0
-                need = self.footprint_fn(req.n, req.nt, key[2], req.precision)
                 if need > self.budget:
                     del self.queue[i]
-                    fut.set_exception(MemoryError(
-                        f"request {req.id} needs {need} bytes, over the {self.budget}-byte budget"))
+                    if fut.set_running_or_notify_cancel():
+                        fut.set_exception(MemoryError(
+                            f"request {req.id} needs {need} bytes, over the {self.budget}-byte "
+                            "budget"))
                     break
                 # evict idle problems (least recently used) until it fits
                 while self.busy_bytes + self.pool_bytes + need > self.budget and self.pool:
@@ -156,6 +174,9 @@ class Server:
                     self.pool_bytes -= victim.workspace_bytes + 256
                     victim.close()
                 if self.busy_bytes + self.pool_bytes + need <= self.budget:
+                    if not fut.set_running_or_notify_cancel():
+                        del self.queue[i]
+                        break
                     self.busy_bytes += need
                     self.peak_bytes = max(self.peak_bytes, self.busy_bytes + self.pool_bytes)
                     del self.queue[i]
@@ -174,36 +195,70 @@ class Server:
             return
         while True:
             with self.cv:
-                item = self._take()
+                try:
+                    item = self._take()
+                except Exception as e:      # scheduler bug: fail what waits, stop cleanly
+                    item = e
+            if isinstance(item, Exception):
+                self._fail_all(item)
+                return
             if item is None:
                 return
             req, fut, prob, need = item
-            holding = need if prob is None else prob.workspace_bytes + 256
+            # the future is already running (set in _take), so it cannot be
+            # cancelled any more and takes exactly one result or exception
             try:
                 req.t_admit = time.perf_counter()
-                out = self._run(req, prob, stream)
-                fut.set_result(out)
-            except Exception as e:   # the request fails, the server goes on
-                if prob is not None:
-                    prob.close()
-                with self.cv:
-                    self.busy_bytes -= holding
-                    self.cv.notify_all()
+                out = self._run(req, prob, need, stream)
+            except Exception as e:      # the request fails, the slot goes on
                 fut.set_exception(e)
+            else:
+                fut.set_result(out)
 
     def _fail_all(self, exc):
         with self.cv:
             while self.queue:
                 _, fut = self.queue.popleft()
-                fut.set_exception(exc)
+                if fut.set_running_or_notify_cancel():
+                    fut.set_exception(exc)
             self.closed = True
             self.cv.notify_all()
 
-    def _run(self, req, prob, stream):
+    def _run(self, req, prob, need, stream):
+        """Runs one admitted request.  It holds `need` bytes (a new problem)
+        or its pooled problem's bytes; on success the problem goes back to
+        the pool, on failure it is closed (its state is not trusted) and the
+        bytes are released before the exception propagates."""
+        holding = need if prob is None else prob.workspace_bytes + 256
+        made = []                       # the problem _solve builds, if any
+        try:
+            out = self._solve(req, prob, stream, made)
+        except BaseException:
+            prob = made[0] if prob is None and made else prob
+            if prob is not None:
+                prob.close()
+            with self.cv:
+                self.busy_bytes -= holding
+                self.cv.notify_all()
+            raise
+        prob = out.pop("_problem")
+        with self.cv:
+            key = req.key
+            self.busy_bytes -= holding
+            self.pool.setdefault(key, []).append(prob)
+            self.pool.move_to_end(key)
+            self.pool_bytes += prob.workspace_bytes + 256
+            self.peak_bytes = max(self.peak_bytes, self.busy_bytes + self.pool_bytes)
+            self.stats.append(out)
+            self.cv.notify_all()
+        return out
+
+    def _solve(self, req, prob, stream, made):
         ctx = torch.cuda.stream(stream) if stream is not None else _nullctx()
         with ctx:
             if prob is None:
                 prob = self.make_problem(req, self.device, stream)
+                made.append(prob)
             else:
                 if stream is not None:
                     prob.set_stream(stream)
@@ -221,15 +276,7 @@ class Server:
                 stream.synchronize()
         req.t_done = time.perf_counter()
         out.update(latency_s=req.t_done - req.t_arrive, queue_s=req.t_admit - req.t_arrive,
-                   dofs=req.dofs)
-        with self.cv:
-            key = req.key
-            self.busy_bytes -= prob.workspace_bytes + 256
-            self.pool.setdefault(key, []).append(prob)
-            self.pool.move_to_end(key)
-            self.pool_bytes += prob.workspace_bytes + 256
-            self.stats.append(out)
-            self.cv.notify_all()
+                   dofs=req.dofs, _problem=prob)
         return out
 
 

@@ -95,19 +95,32 @@ class Problem:
             self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8,
                                          device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.density_version = 0
         icd = _dev_f64(ic, self.device).reshape(-1) if ic is not None else None
         srcd = _dev_f64(source, self.device).reshape(-1) if source is not None else None
         h = C.c_void_p()
+        self._order()
         code = self.lib.st_setup(C.byref(self.grid), C.byref(self.mat), _ptr(rho), self.rho_tv,
                                  _ptr(icd), _ptr(srcd), float(q0), parr, len(pl),
                                  C.byref(self.opts), _ptr(self.workspace),
                                  self.workspace_bytes + 256, C.c_void_p(self.stream.cuda_stream),
                                  C.byref(h))
+        if code == L.ST_NOT_CONVERGED:          # the density filter reached its cap
+            self.lib.st_destroy(h)
         L.check("st_setup", code)
         self.h = h
         self.n_nodes = (self.nx + 1) * (self.ny + 1) * (self.nt + 1)
 
     # ------------------------------------------------------------------
+    def _order(self):
+        """Inputs are made (allocated, zeroed, copied) on torch's current
+        stream; the library reads them on the problem's stream.  Make the
+        latter wait for the former.  Every entry point synchronises its own
+        stream before returning, so outputs need no ordering back."""
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+
     def _new_nodal(self):
         return torch.zeros((self.nt + 1, self.ny + 1, self.nx + 1), dtype=torch.float64,
                            device=self.device)
@@ -117,6 +130,7 @@ class Problem:
         T = self._new_nodal() if x0 is None else _dev_f64(x0, self.device).clone().reshape(
             self.nt + 1, self.ny + 1, self.nx + 1)
         info = L.st_info()
+        self._order()
         code = self.lib.st_solve(self.h, _ptr(T), C.byref(info))
         L.check("st_solve", code, allow_not_converged)
         return T, info
@@ -126,6 +140,7 @@ class Problem:
         lam = self._new_nodal() if lam0 is None else _dev_f64(lam0, self.device).clone().reshape(
             self.nt + 1, self.ny + 1, self.nx + 1)
         info = L.st_info()
+        self._order()
         code = self.lib.st_adjoint_solve(self.h, _ptr(g), _ptr(lam), C.byref(info))
         L.check("st_adjoint_solve", code, allow_not_converged)
         return lam, info
@@ -134,12 +149,14 @@ class Problem:
         out = torch.empty(self.design_shape, dtype=torch.float64, device=self.device)
         T = _dev_f64(T, self.device)
         lam = _dev_f64(lam, self.device)
+        self._order()
         L.check("st_sensitivity", self.lib.st_sensitivity(self.h, _ptr(T), _ptr(lam), _ptr(out)))
         return out
 
     def objective(self, T):
         J = C.c_double(0.0)
         T = _dev_f64(T, self.device)
+        self._order()
         L.check("st_objective", self.lib.st_objective(self.h, _ptr(T), C.byref(J)))
         return J.value
 
@@ -148,6 +165,7 @@ class Problem:
         T = _dev_f64(T, self.device)
         phi = C.c_double(0.0)
         g = self._new_nodal() if grad else None
+        self._order()
         L.check("st_pnorm", self.lib.st_pnorm(self.h, _ptr(T), float(P), C.byref(phi),
                                               _ptr(g) if grad else None))
         return phi.value, g
@@ -157,24 +175,29 @@ class Problem:
         None), the gradient in the design's layout."""
         chi = C.c_double(0.0)
         g = torch.empty(self.design_shape, dtype=torch.float64, device=self.device) if grad else None
+        self._order()
         L.check("st_volume", self.lib.st_volume(self.h, float(vf), C.byref(chi),
                                                 _ptr(g) if grad else None))
         return chi.value, g
 
     def load_vector(self):
         f = self._new_nodal()
+        self._order()
         L.check("st_load_vector", self.lib.st_load_vector(self.h, _ptr(f)))
         return f
 
     def filter(self, x):
         x = _dev_f64(x, self.device).reshape(self.design_shape)
         out = torch.empty_like(x)
+        self._order()
         L.check("st_filter", self.lib.st_filter(self.h, _ptr(x), _ptr(out)))
         return out
 
     def update_density(self, rho):
         rho = _dev_f64(rho, self.device).reshape(self.design_shape)
+        self._order()
         L.check("st_update_density", self.lib.st_update_density(self.h, _ptr(rho)))
+        self.density_version += 1
 
     def set_stream(self, stream):
         L.check("st_set_stream", self.lib.st_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
@@ -198,6 +221,7 @@ class Problem:
     def debug_apply(self, level, x, transpose=False, mixed=False):
         x = _dev_f64(x, self.device)
         y = torch.empty_like(x)
+        self._order()
         L.check("st_debug_apply", self.lib.st_debug_apply(
             self.h, level, int(transpose), L.ST_MIXED if mixed else L.ST_FP64, _ptr(x), _ptr(y)))
         return y
@@ -205,6 +229,7 @@ class Problem:
     def debug_stencil(self, level):
         shp = self.level_shape(level)
         out = torch.empty((27,) + shp, dtype=torch.float64, device=self.device)
+        self._order()
         L.check("st_debug_stencil", self.lib.st_debug_stencil(self.h, level, _ptr(out)))
         return out
 
@@ -212,6 +237,7 @@ class Problem:
         shp = self.level_shape(level)
         d = torch.empty(shp, dtype=torch.float64, device=self.device)
         m = torch.empty(shp, dtype=torch.uint8, device=self.device)
+        self._order()
         L.check("st_debug_diag", self.lib.st_debug_diag(self.h, level, _ptr(d), _ptr(m)))
         return d, m
 
@@ -219,6 +245,7 @@ class Problem:
         x = _dev_f64(x, self.device)
         shp = self.level_shape(level if prolong else level + 1)
         out = torch.empty(shp, dtype=torch.float64, device=self.device)
+        self._order()
         L.check("st_debug_transfer", self.lib.st_debug_transfer(
             self.h, level, int(prolong), _ptr(x), _ptr(out)))
         return out
@@ -226,6 +253,7 @@ class Problem:
     def debug_smooth(self, level, b, x0=None, its=10, rtol=1e-6, transpose=False):
         b = _dev_f64(b, self.device)
         x = torch.zeros_like(b) if x0 is None else _dev_f64(x0, self.device).clone()
+        self._order()
         L.check("st_debug_smooth", self.lib.st_debug_smooth(
             self.h, level, int(transpose), _ptr(b), _ptr(x), int(x0 is None), its, rtol))
         return x
@@ -233,6 +261,7 @@ class Problem:
     def debug_vcycle(self, b, transpose=False):
         b = _dev_f64(b, self.device)
         x = torch.empty_like(b)
+        self._order()
         L.check("st_debug_vcycle", self.lib.st_debug_vcycle(self.h, int(transpose), _ptr(b),
                                                             _ptr(x)))
         return x
@@ -261,6 +290,16 @@ def info_dict(info):
     return d
 
 
+def _reload_if_changed(problem, version, rho):
+    """The adjoint operator and the sensitivities belong to the design a
+    forward call loaded.  If the problem has been given another design since
+    (a second forward call on the same problem, or update_density), load that
+    forward call's design again before the backward solve; the problem then
+    holds it."""
+    if problem.density_version != version:
+        problem.update_density(rho.detach())
+
+
 class STSolve(torch.autograd.Function):
     """T = STSolve.apply(rho, problem): the design is loaded into the problem
     (filter + SIMP + Galerkin rebuild), the state solved; the backward pass is
@@ -271,13 +310,15 @@ class STSolve(torch.autograd.Function):
         problem.update_density(rho.detach())
         T, _ = problem.solve()
         ctx.problem = problem
-        ctx.save_for_backward(T)
+        ctx.version = problem.density_version
+        ctx.save_for_backward(T, rho)
         return T
 
     @staticmethod
     def backward(ctx, gT):
         problem = ctx.problem
-        (T,) = ctx.saved_tensors
+        T, rho = ctx.saved_tensors
+        _reload_if_changed(problem, ctx.version, rho)
         lam, _ = problem.adjoint(gT.contiguous())
         grad = problem.sensitivity(T, lam)
         return grad.reshape(problem.design_shape), None
@@ -295,13 +336,15 @@ class STPNorm(torch.autograd.Function):
         T, _ = problem.solve()
         phi, dphi = problem.pnorm(T, P)
         ctx.problem = problem
-        ctx.save_for_backward(T, dphi)
+        ctx.version = problem.density_version
+        ctx.save_for_backward(T, dphi, rho)
         return torch.tensor(phi, dtype=torch.float64, device=rho.device)
 
     @staticmethod
     def backward(ctx, gphi):
         problem = ctx.problem
-        T, dphi = ctx.saved_tensors
+        T, dphi, rho = ctx.saved_tensors
+        _reload_if_changed(problem, ctx.version, rho)
         lam, _ = problem.adjoint(dphi)
         grad = problem.sensitivity(T, lam)
         return gphi * grad.reshape(problem.design_shape), None, None

@@ -8,6 +8,9 @@ seeded inputs of paper_2508_09589_amd/inputs.py; nothing comes from the GPU.
                  PDE filter r = 1.5 elements): J, the gradient at the 16
                  elements default_rng(3).choice(N_e, 16), its norm, and the
                  state at 2000 sampled nodes.
+  grad_128_fd.npz  the central differences (h = 1e-6) of J at the same 16
+                 elements in the difference-system form (J+ ds = -(J+ - J-) s-,
+                 block Gauss-Seidel solves; no cancellation).
 The medium and large workloads are checked without fixtures: the oracle
 recomputes the residual of the GPU solution (tests/test_gpu_fullsize.py); a
 block solve of the time-varying medium grid would hold 256 sparse LU factors
@@ -24,7 +27,8 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 from oracle.assemble import Material                               # noqa: E402
-from oracle.blockgrad import objective_and_gradient_blocks       # noqa: E402
+from oracle.blockgrad import (objective_and_gradient_blocks,       # noqa: E402
+                              central_difference_blocks)
 from oracle.grid import Grid                                       # noqa: E402
 from paper_2508_09589_amd.inputs import workload_density, PATCH_LEFT_CENTRED  # noqa: E402
 
@@ -47,5 +51,50 @@ def grad():
     print("grad fixture", out["J"], out["sweeps"], out["rel"], f"{time.time() - t:.1f} s")
 
 
+_S0 = None
+
+
+def _fd_init(s0):
+    global _S0
+    _S0 = s0
+
+
+def _fd_one(e):
+    n = 128
+    g = Grid(n, n, n, 1.0 / n, 1.0 / n)
+    rho = workload_density("grad")
+    t = time.time()
+    fd, sweeps = central_difference_blocks(g, MAT, rho, [PATCH_LEFT_CENTRED], int(e), 1e-6, 1.0,
+                                           1.5, tol=1e-13, max_sweeps=200, s0=_S0)
+    print(f"element {e}: fd {fd:.12e}, sweeps {sweeps}, {time.time() - t:.1f} s", flush=True)
+    return fd
+
+
+def grad_fd(workers=4):
+    """The state at rho (solved once, to 1e-13) starts every s- solve."""
+    from concurrent.futures import ProcessPoolExecutor
+    from oracle.assemble import load_vector, simp
+    from oracle.design import filter_apply
+    from oracle.grid import dirichlet_mask
+    from oracle.solve import BlockTimeSystem
+    n = 128
+    g = Grid(n, n, n, 1.0 / n, 1.0 / n)
+    rho = workload_density("grad")
+    k, C, _, _ = simp(filter_apply(rho, g.dx, g.dt, 1.5 * g.dx, 1.5 * g.dt), MAT)
+    bs = BlockTimeSystem(g, k, C, dirichlet_mask(g, [PATCH_LEFT_CENTRED]))
+    s0, sw, rel = bs.gauss_seidel(bs.masked_rhs(load_vector(g, 1.0)), tol=1e-13, max_sweeps=200)
+    print(f"base state: {sw} sweeps, rel. residual {rel:.2e}", flush=True)
+    del bs
+    idx = np.random.default_rng(3).choice(n * n * n, 16, replace=False)
+    with ProcessPoolExecutor(workers, initializer=_fd_init, initargs=(s0,)) as ex:
+        fd = np.array(list(ex.map(_fd_one, idx)))
+    np.savez(os.path.join(HERE, "grad_128_fd.npz"), elems=idx, h=np.array(1e-6), fd=fd)
+    print("grad fd fixture written")
+
+
 if __name__ == "__main__":
-    grad()
+    which = sys.argv[1:] or ["grad", "grad_fd"]
+    if "grad" in which:
+        grad()
+    if "grad_fd" in which:
+        grad_fd()

@@ -47,6 +47,8 @@ def test_defaults_are_the_papers_parameters():
     assert o.precision == L.ST_FP64
     # §3.3.2 projection is off by default; its threshold defaults to eta = 0.5
     assert o.proj_beta == 0.0 and o.proj_eta == 0.5
+    # the filter's CG: cap and tolerance
+    assert o.filter_max_it == 2000 and o.filter_rtol == 1e-13
 
 
 def _fp(nx, ny, nt, tv, **kw):
@@ -72,7 +74,9 @@ def test_footprints_fit_one_gpu():
 
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(nt=0), dict(restart=2), dict(restart=40),
                                  dict(smooth_its=0), dict(smooth_its=20), dict(precision=7),
-                                 dict(proj_beta=-1.0), dict(proj_eta=0.0), dict(proj_eta=1.0)])
+                                 dict(proj_beta=-1.0), dict(proj_eta=0.0), dict(proj_eta=1.0),
+                                 dict(filter_max_it=0), dict(filter_rtol=-1.0),
+                                 dict(filter_r=float("nan"))])
 def test_invalid_arguments_rejected_on_host(bad):
     nx, ny, nt = bad.pop("nx", 8), 8, bad.pop("nt", 8)
     rc, _ = _fp(nx, ny, nt, 0, **bad)

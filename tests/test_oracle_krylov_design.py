@@ -332,3 +332,25 @@ def test_sstep_smoother_cuts_an_ill_conditioned_basis():
     rs = np.linalg.norm(dinv * (b - A @ xs))
     rg = np.linalg.norm(dinv * (b - A @ xg))
     assert rs == pytest.approx(rg, rel=1e-3)   # the last kept pivot is ~1e-11
+
+
+@pytest.mark.parametrize("tv,filt", [(True, 1.5), (False, None)])
+def test_block_central_difference_matches_adjoint_gradient(tv, filt):
+    """The block-in-time difference-system central difference (the route of
+    the 128^3 fixture) equals the adjoint gradient of the global-LU chain to
+    1e-7 relative at h = 1e-6 on an 8^2 x 6 grid, and the global-LU
+    difference system to 1e-9."""
+    from oracle.blockgrad import central_difference_blocks
+    from oracle.design import central_difference
+    nx, nt = 8, 6
+    g = Grid(nx, nx, nt, 1 / nx, 1 / nt)
+    rng = np.random.default_rng(13)
+    rho = rng.uniform(0.1, 0.9, (nt, nx, nx) if tv else (nx, nx))
+    out = objective_and_gradient(g, MAT, rho, PATCH, 1.0, filt)
+    for e in rng.choice(rho.size, 4, replace=False):
+        ad = out["grad"].ravel()[e]
+        fdb, sweeps = central_difference_blocks(g, MAT, rho, PATCH, e, 1e-6, 1.0, filt)
+        fdg = central_difference(g, MAT, rho, PATCH, e, 1e-6, 1.0, filt)
+        assert abs(fdb - ad) <= 1e-7 * abs(ad), (e, fdb, ad)
+        assert abs(fdb - fdg) <= 1e-9 * abs(fdg), (e, fdb, fdg)
+        assert max(sweeps) < 80

@@ -31,6 +31,8 @@ class MockProblem:
 
     def solve(self, allow_not_converged=False):
         time.sleep(0.01)
+        if getattr(self, "fail_next", False):
+            raise RuntimeError("scripted solve failure")
         info = type("I", (), dict(iterations=3, true_rel_res=1e-9))()
         return np.zeros(1), info
 
@@ -88,6 +90,96 @@ def test_eviction_makes_room_for_new_shapes():
     c = srv.submit(Request(2, 32, 32, np.zeros((32, 32, 32)))).result(timeout=10)
     srv.close()
     assert srv.peak_bytes <= fp32 + 100 and a and b and c
+
+
+def _failing_server(budget, fail_ids, slots=2, bad_ids=()):
+    """Mock server whose problems fail the solve of the requests in fail_ids
+    and whose footprint function rejects the requests in bad_ids."""
+    def fp(n, nt, tv, prec):
+        if n == 7:
+            raise ValueError("grid rejected by the footprint function")
+        return n * n * nt * 100 + 256
+
+    def mk(req, dev, s):
+        p = MockProblem(req, fp(req.n, req.nt, True, req.precision))
+        return p
+
+    srv = Server(budget, slots=slots, device="cpu", make_problem=mk, footprint_fn=fp)
+    orig = srv._solve
+
+    def solve(req, prob, stream, made):
+        if prob is not None:
+            prob.fail_next = req.id in fail_ids
+        else:
+            def mk2(r, dev, s, _mk=mk):
+                p = _mk(r, dev, s)
+                p.fail_next = r.id in fail_ids
+                return p
+            srv.make_problem = mk2
+        return orig(req, prob, stream, made)
+    srv._solve = solve
+    return srv
+
+
+def test_failing_solves_release_memory_and_close_problems():
+    """A solve that raises fails only its request: a new problem is closed,
+    a pooled one too (its state is not trusted), the bytes go back, and the
+    slot serves the next requests."""
+    MockProblem.live = 0
+    budget = 32 * 32 * 32 * 100 * 3 + 1000
+    srv = _failing_server(budget, fail_ids={0, 3, 4})
+    reqs = [Request(i, 32, 32, np.zeros((32, 32, 32))) for i in range(8)]
+    futs = [srv.submit(r) for r in reqs]
+    ok, failed = [], []
+    for f in futs:
+        try:
+            ok.append(f.result(timeout=30)["id"])
+        except RuntimeError:
+            failed.append(f)
+    assert len(failed) == 3 and sorted(ok) == [1, 2, 5, 6, 7]
+    with srv.cv:
+        assert srv.busy_bytes == 0
+    srv.close()
+    assert MockProblem.live == 0
+
+
+def test_invalid_request_fails_alone():
+    """A request the footprint function rejects fails its own future; the
+    slot threads survive and serve the requests behind it."""
+    MockProblem.live = 0
+    srv = _failing_server(10 ** 9, fail_ids=set(), slots=1)
+    bad = srv.submit(Request(0, 7, 8, np.zeros((8, 7, 7))))
+    good = [srv.submit(Request(i, 16, 16, np.zeros((16, 16, 16)))) for i in (1, 2)]
+    with pytest.raises(ValueError):
+        bad.result(timeout=10)
+    assert [g.result(timeout=10)["id"] for g in good] == [1, 2]
+    srv.close()
+    assert MockProblem.live == 0 and srv.busy_bytes == 0
+
+
+def test_cancelled_request_is_skipped():
+    """A future cancelled while queued is never run and holds no memory."""
+    MockProblem.live = 0
+    fp32 = 32 * 32 * 32 * 100 + 256
+    srv = _mock_server(fp32 + 100, slots=1)
+    first = srv.submit(Request(0, 32, 32, np.zeros((32, 32, 32))))
+    second = srv.submit(Request(1, 32, 32, np.zeros((32, 32, 32))))
+    third = srv.submit(Request(2, 16, 16, np.zeros((16, 16, 16))))
+    second.cancel()
+    assert first.result(timeout=10)["id"] == 0
+    assert third.result(timeout=10)["id"] == 2
+    assert second.cancelled()
+    srv.close()
+    assert MockProblem.live == 0 and srv.busy_bytes == 0
+
+
+def test_pool_key_separates_solver_options():
+    """A resident problem built for one smoother is not reused for a request
+    asking for the other."""
+    a = Request(0, 32, 32, np.zeros((32, 32, 32)), smoother="sstep")
+    b = Request(1, 32, 32, np.zeros((32, 32, 32)), smoother="gmres")
+    c = Request(2, 32, 32, np.zeros((32, 32, 32)), smoother="sstep", precision="fp64")
+    assert len({a.key, b.key, c.key}) == 3
 
 
 def test_request_density_range_and_determinism():
