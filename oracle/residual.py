@@ -81,3 +81,43 @@ def apply_masked_at(grid, k_e, C_e, mask, x, nodes):
                             acc += row[b] * X[xn, xj, xi]
         out[q] = acc
     return out
+
+
+def residual_by_planes(grid, k_e, C_e, mask, x, f_m, transpose=False):
+    """(||f_m - J_m x||_2, max_a |(f_m - J_m x)_a|) for the full grid, formed
+    one time level at a time: slab s adds its element contributions to levels
+    s and s + 1, after which level s is complete and its residual is folded
+    into the sums.  Temporaries are two node planes, so grids of hundreds of
+    millions of nodes fit; the arithmetic is that of apply_masked."""
+    A, B = element_matrices(grid.dx, grid.dt)
+    Ae, Be = (A, B) if transpose else (A.T, B.T)
+    nx, ny, nt = grid.nx, grid.ny, grid.nt
+    X = np.asarray(x, dtype=np.float64).reshape(grid.shape_nodes)
+    M = np.asarray(mask, dtype=bool).reshape(grid.shape_nodes)
+    F = np.asarray(f_m, dtype=np.float64).reshape(grid.shape_nodes)
+    acc = np.zeros((2, ny + 1, nx + 1))
+    ss, mx = 0.0, 0.0
+
+    def fold(n, y):
+        nonlocal ss, mx
+        r = np.where(M[n], F[n] - X[n], F[n] - y)
+        ss += float(np.sum(r * r))
+        mx = max(mx, float(np.max(np.abs(r))))
+
+    for s in range(nt):
+        k = _slab_coeff(k_e, s)
+        C = _slab_coeff(C_e, s)
+        planes = (np.where(M[s], 0.0, X[s]), np.where(M[s + 1], 0.0, X[s + 1]))
+        xe = np.empty((ny, nx, 8))
+        for a in range(8):
+            a1, a2, a3 = a & 1, (a >> 1) & 1, (a >> 2) & 1
+            xe[:, :, a] = planes[a3][a2:a2 + ny, a1:a1 + nx]
+        ye = k[:, :, None] * (xe @ Ae) + C[:, :, None] * (xe @ Be)
+        for a in range(8):
+            a1, a2, a3 = a & 1, (a >> 1) & 1, (a >> 2) & 1
+            acc[a3, a2:a2 + ny, a1:a1 + nx] += ye[:, :, a]
+        fold(s, acc[0])
+        acc[0] = acc[1]
+        acc[1] = 0.0
+    fold(nt, acc[0])
+    return float(np.sqrt(ss)), mx

@@ -11,10 +11,12 @@ seeded inputs of paper_2508_09589_amd/inputs.py; nothing comes from the GPU.
   grad_128_fd.npz  the central differences (h = 1e-6) of J at the same 16
                  elements in the difference-system form (J+ ds = -(J+ - J-) s-,
                  block Gauss-Seidel solves; no cancellation).
-The medium and large workloads are checked without fixtures: the oracle
-recomputes the residual of the GPU solution (tests/test_gpu_fullsize.py); a
-block solve of the time-varying medium grid would hold 256 sparse LU factors
-at once, more memory than a test host has.
+  medium_256.npz  the state of the medium workload (256^2 x 256, smooth
+                 time-varying density seed 1) by block Gauss-Seidel in time to
+                 a relative residual of 1e-13: ||s||, the full time levels
+                 n = 128 and 256 and 20000 random nodes.
+The large workload is checked without a fixture: the oracle recomputes the
+residual of the GPU solution at every node (tests/test_gpu_fullsize.py).
 """
 import os
 import sys
@@ -65,13 +67,15 @@ def _fd_one(e):
     rho = workload_density("grad")
     t = time.time()
     fd, sweeps = central_difference_blocks(g, MAT, rho, [PATCH_LEFT_CENTRED], int(e), 1e-6, 1.0,
-                                           1.5, tol=1e-13, max_sweeps=200, s0=_S0)
+                                           1.5, tol=3e-12, max_sweeps=200, s0=_S0)
     print(f"element {e}: fd {fd:.12e}, sweeps {sweeps}, {time.time() - t:.1f} s", flush=True)
     return fd
 
 
 def grad_fd(workers=4):
-    """The state at rho (solved once, to 1e-13) starts every s- solve."""
+    """The state at rho (solved once) starts every s- solve.  Block
+    Gauss-Seidel stagnates near a relative residual of 1.2e-12 on this grid
+    (rounding of the residual itself), so the solves stop at 3e-12."""
     from concurrent.futures import ProcessPoolExecutor
     from oracle.assemble import load_vector, simp
     from oracle.design import filter_apply
@@ -82,7 +86,7 @@ def grad_fd(workers=4):
     rho = workload_density("grad")
     k, C, _, _ = simp(filter_apply(rho, g.dx, g.dt, 1.5 * g.dx, 1.5 * g.dt), MAT)
     bs = BlockTimeSystem(g, k, C, dirichlet_mask(g, [PATCH_LEFT_CENTRED]))
-    s0, sw, rel = bs.gauss_seidel(bs.masked_rhs(load_vector(g, 1.0)), tol=1e-13, max_sweeps=200)
+    s0, sw, rel = bs.gauss_seidel(bs.masked_rhs(load_vector(g, 1.0)), tol=3e-12, max_sweeps=200)
     print(f"base state: {sw} sweeps, rel. residual {rel:.2e}", flush=True)
     del bs
     idx = np.random.default_rng(3).choice(n * n * n, 16, replace=False)
@@ -92,9 +96,32 @@ def grad_fd(workers=4):
     print("grad fd fixture written")
 
 
+def medium():
+    from oracle.assemble import load_vector, simp
+    from oracle.grid import dirichlet_mask
+    from oracle.solve import BlockTimeSystem
+    n = 256
+    g = Grid(n, n, n, 1.0 / n, 1.0 / n)
+    rho = workload_density("medium")
+    k, C, _, _ = simp(rho, MAT)
+    t = time.time()
+    bs = BlockTimeSystem(g, k, C, dirichlet_mask(g, [PATCH_LEFT_CENTRED]))
+    s, sweeps, rel = bs.gauss_seidel(bs.masked_rhs(load_vector(g, 1.0)), tol=1e-13,
+                                     max_sweeps=300)
+    S = s.reshape(g.shape_nodes)
+    nodes = np.random.default_rng(6).choice(g.n_nodes, 20000, replace=False)
+    levels = np.array([128, 256])
+    np.savez(os.path.join(HERE, "medium_256.npz"), s_norm=np.linalg.norm(s), levels=levels,
+             s_levels=S[levels], nodes=nodes, s_at=s[nodes], rel_res=np.array(rel),
+             sweeps=np.array(sweeps))
+    print(f"medium fixture: {sweeps} sweeps, rel. residual {rel:.2e}, {time.time() - t:.0f} s")
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["grad", "grad_fd"]
+    which = sys.argv[1:] or ["grad", "grad_fd", "medium"]
     if "grad" in which:
         grad()
     if "grad_fd" in which:
         grad_fd()
+    if "medium" in which:
+        medium()

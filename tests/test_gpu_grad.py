@@ -113,3 +113,89 @@ def test_naive_central_difference_informational(torch_cuda):
         fd = (vals[0] - vals[1]) / (2 * h)
         assert abs(fd - grad[e]) <= 2e-2 * abs(grad[e]) + 1e-12, (e, fd, grad[e])
     p.close()
+
+
+def _grad_fixture():
+    path = os.path.join(GOLD, "grad_128.npz")
+    fdp = os.path.join(GOLD, "grad_128_fd.npz")
+    if not (os.path.exists(path) and os.path.exists(fdp)):
+        pytest.skip("fixture not generated")
+    fx, fd = np.load(path), np.load(fdp)
+    assert np.array_equal(fx["elems"], fd["elems"])
+    return fx, fd
+
+
+@pytest.mark.parametrize("precision,rtol,gate", [("fp64", 1e-12, 1e-10), ("mixed", 1e-12, 1e-10),
+                                                 ("mixed", 1e-8, 1e-6)])
+def test_grad_workload_autograd_against_fd_and_oracle(torch_cuda, precision, rtol, gate):
+    """128^2 x 128 differentiation workload through the autograd functions
+    (STSolve, STObjective, .backward()): dJ/drho at the 16 elements of
+    default_rng(3) against the oracle's central differences (h = 1e-6,
+    difference-system form, 1e-6) and against the oracle's adjoint gradient
+    (1e-10 with both solves in parity mode; 1e-6 for the mixed path at the
+    benchmark's 1e-8)."""
+    import torch
+    from paper_2508_09589_amd import Problem, STSolve, STObjective
+    from paper_2508_09589_amd.inputs import workload_density
+    fx, fd = _grad_fixture()
+    rho = workload_density("grad")
+    kw = dict(bf16_from_level=1, smoother="sstep") if precision == "mixed" else {}
+    p = Problem(128, 128, 128, torch.tensor(rho), filter_r=1.5, rtol=rtol, precision=precision,
+                **kw)
+    r = torch.tensor(rho, device="cuda", requires_grad=True)
+    J = STObjective.apply(STSolve.apply(r, p), p)
+    J.backward()
+    g = r.grad.detach().cpu().numpy().ravel()[fx["elems"]]
+    e_fd = np.abs(g - fd["fd"]) / np.abs(fd["fd"])
+    e_or = rel(g, fx["grad_at"])
+    print(f"grad {precision} rtol {rtol:g}: max rel vs FD {e_fd.max():.2e}, "
+          f"vs oracle gradient {e_or:.2e}", flush=True)
+    assert abs(J.item() - float(fx["J"])) <= max(gate, 1e-10) * abs(float(fx["J"]))
+    assert np.all(e_fd <= 1e-6), e_fd
+    assert e_or <= gate, e_or
+    p.close()
+
+
+def test_backward_after_second_forward_uses_its_own_design(torch_cuda):
+    """Two forward calls on one problem, then backward through the first:
+    the gradient is the first design's (checked against the oracle)."""
+    import torch
+    from paper_2508_09589_amd import Problem, STSolve, STObjective
+    nx, nt = 10, 8
+    g = Grid(nx, nx, nt, 1 / nx, 1 / nt)
+    rng = np.random.default_rng(17)
+    rho1 = rng.uniform(0.1, 0.9, (nt, nx, nx))
+    rho2 = rng.uniform(0.1, 0.9, (nt, nx, nx))
+    ref1 = objective_and_gradient(g, MAT, rho1, PATCH, 1.0, 1.5)
+    ref2 = objective_and_gradient(g, MAT, rho2, PATCH, 1.0, 1.5)
+    p = Problem(nx, nx, nt, torch.tensor(rho1), filter_r=1.5, rtol=1e-12)
+    r1 = torch.tensor(rho1, device="cuda", requires_grad=True)
+    r2 = torch.tensor(rho2, device="cuda", requires_grad=True)
+    J1 = STObjective.apply(STSolve.apply(r1, p), p)
+    J2 = STObjective.apply(STSolve.apply(r2, p), p)
+    J1.backward()
+    J2.backward()
+    assert rel(r1.grad.cpu().numpy(), ref1["grad"]) < 1e-10
+    assert rel(r2.grad.cpu().numpy(), ref2["grad"]) < 1e-10
+    p.close()
+
+
+def test_problem_on_a_side_stream(torch_cuda):
+    """A problem bound to a stream that is not torch's current one: inputs
+    made on the current stream are ordered before the library reads them."""
+    import torch
+    from paper_2508_09589_amd import Problem
+    nx, nt = 12, 10
+    g = Grid(nx, nx, nt, 1 / nx, 1 / nt)
+    rng = np.random.default_rng(19)
+    rho = rng.uniform(0.1, 0.9, (nt, nx, nx))
+    ref = objective_and_gradient(g, MAT, rho, PATCH, 1.0, None)
+    side = torch.cuda.Stream()
+    p = Problem(nx, nx, nt, torch.tensor(rho), rtol=1e-12, stream=side)
+    for _ in range(3):
+        T, _ = p.solve()
+        lam, _ = p.adjoint(p.load_vector())
+        grad = p.sensitivity(T, lam)
+    assert rel(T.cpu().numpy().ravel(), ref["s"]) < 1e-10
+    assert rel(grad.cpu().numpy(), ref["grad"]) < 1e-10
+    p.close()

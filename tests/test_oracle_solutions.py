@@ -223,3 +223,26 @@ def test_sampled_residual_rows_match_assembled_matrix():
     y = Jm @ x
     assert np.max(np.abs(apply_masked_at(g, k, C, mask, x, nodes) - y[nodes])) < 1e-14
     assert np.max(np.abs(apply_masked(g, k, C, mask, x) - y)) < 1e-14
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_residual_by_planes_equals_assembled_residual(transpose):
+    """The plane-by-plane residual of the full-size checks equals the
+    residual formed with the assembled sparse matrix (norm and maximum)."""
+    from oracle.assemble import assemble_matrix, apply_dirichlet, load_vector
+    from oracle.grid import Grid, dirichlet_mask
+    from oracle.residual import residual_by_planes
+    g = Grid(7, 5, 6, 1 / 7, 1 / 6)
+    rng = np.random.default_rng(21)
+    k = rng.uniform(0.01, 1.0, (6, 5, 7))
+    C = rng.uniform(0.5, 2.0, (6, 5, 7))
+    mask = dirichlet_mask(g, [(0, 0.5, 0.2)])
+    Jm, fm = apply_dirichlet(assemble_matrix(g, k, C), load_vector(g, 1.0), mask)
+    x = rng.standard_normal(g.n_nodes)
+    r = fm - (Jm.T if transpose else Jm) @ x
+    if transpose:
+        # the transposed masked system keeps identity rows on the Dirichlet set
+        r = np.where(mask.ravel(), fm - x, r)
+    nr, mx = residual_by_planes(g, k, C, mask, x, fm, transpose)
+    assert abs(nr - np.linalg.norm(r)) <= 1e-13 * np.linalg.norm(r)
+    assert abs(mx - np.max(np.abs(r))) <= 1e-13 * np.max(np.abs(r))
