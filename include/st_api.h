@@ -192,6 +192,25 @@ st_status st_update_density(st_handle* h, const double* rho_dev);
  * out = solution.  info may be NULL. */
 st_status st_solve(st_handle* h, double* T_dev, st_info* info);
 
+/* Size in MiB of the static device scratch of st_solve_noalloc. */
+#define ST_NOALLOC_SCRATCH_MIB 256
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): st_setup,
+ * st_solve and st_destroy in one call, with the workspace in a static device
+ * array of ST_NOALLOC_SCRATCH_MIB MiB that the library holds on every GPU it
+ * runs on (resolved once per device).  No device or pinned host memory is
+ * allocated.  Arguments as for st_setup (without the workspace) and st_solve;
+ * T_dev: in = initial guess, out = solution.  ST_ERR_OOM (with a message on
+ * stderr) when st_footprint_bytes exceeds the scratch; per-kernel timing is
+ * not recorded.  Every call on one GPU uses the same array: calls that
+ * overlap on one GPU (from several threads or streams) race. */
+st_status st_solve_noalloc(const st_grid* grid, const st_material* mat, const double* rho_dev,
+                           int32_t rho_time_varying, const double* ic_dev,
+                           const double* source_dev, double q0, const st_patch* patches,
+                           int32_t n_patches, const st_opts* opts, void* hip_stream,
+                           double* T_dev, st_info* info);
+
 /* Adjoint solve J^T lambda = N g (§3.3.3); lambda is zero on Dirichlet nodes.
  * g_dev: nodal dphi/ds.  lambda_dev: in = initial guess, out = solution. */
 st_status st_adjoint_solve(st_handle* h, const double* g_dev, double* lambda_dev, st_info* info);

@@ -87,6 +87,9 @@ _SIGS = {
                                   C.c_double]),
     "st_debug_vcycle": (C.c_int, [_P, C.c_int32, _P, _P]),
     "st_abi_sizes": (C.c_int, [C.POINTER(C.c_size_t), C.c_int32]),
+    "st_solve_noalloc": (C.c_int, [C.POINTER(st_grid), C.POINTER(st_material), _P, C.c_int32, _P,
+                                   _P, C.c_double, C.POINTER(st_patch), C.c_int32,
+                                   C.POINTER(st_opts), _P, _P, C.POINTER(st_info)]),
 }
 
 _lib = None

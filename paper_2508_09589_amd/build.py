@@ -17,7 +17,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libst.so")
 
 SOURCES = ["kernels_fine.hip", "kernels_level.hip", "kernels_krylov.hip", "kernels_coarse.hip",
-           "kernels_smooth.hip", "kernels_sstep.hip", "kernels_design.hip", "solver.cpp"]
+           "kernels_smooth.hip", "kernels_sstep.hip", "kernels_design.hip", "noalloc.hip",
+           "solver.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Wno-unused-variable", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]

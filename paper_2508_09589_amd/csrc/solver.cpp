@@ -82,7 +82,9 @@ struct st_handle {
     double *flt_invd = nullptr, *flt_x = nullptr, *flt_r = nullptr, *flt_z = nullptr,
            *flt_p = nullptr, *flt_q = nullptr, *flt_b = nullptr;
     // host
-    double* hbuf = nullptr;    // pinned staging
+    double* hbuf = nullptr;    // staging: pinned, or hbuf_local (st_solve_noalloc)
+    bool hbuf_pinned = false;
+    double hbuf_local[64] = {};
     bool timing = false;
     std::vector<TimedRec> trecs;
     std::vector<hipEvent_t> evpool;
@@ -965,11 +967,15 @@ st_status st_footprint_bytes(const st_grid* grid, const st_material* mat, const 
     return ST_OK;
 }
 
-st_status st_setup(const st_grid* grid, const st_material* mat, const double* rho_dev,
-                   int32_t rho_time_varying, const double* ic_dev, const double* source_dev,
-                   double q0, const st_patch* patches, int32_t n_patches, const st_opts* opts,
-                   void* workspace_dev, size_t workspace_bytes, void* hip_stream,
-                   st_handle** out) {
+}  // extern "C"
+
+// st_setup with a choice of host staging: pinned memory (hipHostMalloc), or a
+// plain array inside the handle for the entry point that allocates nothing.
+st_status setup_impl(const st_grid* grid, const st_material* mat, const double* rho_dev,
+                     int32_t rho_time_varying, const double* ic_dev, const double* source_dev,
+                     double q0, const st_patch* patches, int32_t n_patches, const st_opts* opts,
+                     void* workspace_dev, size_t workspace_bytes, void* hip_stream,
+                     bool pinned_host, st_handle** out) {
     if (!out || !rho_dev || !workspace_dev) return ST_ERR_ARG;
     *out = nullptr;
     st_status rc = validate(grid, mat, opts);
@@ -1028,9 +1034,15 @@ st_status st_setup(const st_grid* grid, const st_material* mat, const double* rh
     h->ws = (char*)workspace_dev;
     h->ws_bytes = workspace_bytes;
     h->timing = (opts->flags & ST_FLAG_TIME_KERNELS) != 0;
-    if (hipHostMalloc((void**)&h->hbuf, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-        delete h;
-        return ST_ERR_HIP;
+    if (pinned_host) {
+        if (hipHostMalloc((void**)&h->hbuf, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            h->hbuf = nullptr;
+            delete h;
+            return ST_ERR_HIP;
+        }
+        h->hbuf_pinned = true;
+    } else {
+        h->hbuf = h->hbuf_local;
     }
     hipStream_t s = h->stream;
     launch_fill(s, (long long)PARTIALS_DOUBLES, 0, h->partials, 0.0);
@@ -1068,6 +1080,17 @@ st_status st_setup(const st_grid* grid, const st_material* mat, const double* rh
     h->setup_done = 1;
     *out = h;
     return warn;
+}
+
+extern "C" {
+
+st_status st_setup(const st_grid* grid, const st_material* mat, const double* rho_dev,
+                   int32_t rho_time_varying, const double* ic_dev, const double* source_dev,
+                   double q0, const st_patch* patches, int32_t n_patches, const st_opts* opts,
+                   void* workspace_dev, size_t workspace_bytes, void* hip_stream,
+                   st_handle** out) {
+    return setup_impl(grid, mat, rho_dev, rho_time_varying, ic_dev, source_dev, q0, patches,
+                      n_patches, opts, workspace_dev, workspace_bytes, hip_stream, true, out);
 }
 
 st_status st_update_density(st_handle* h, const double* rho_dev) {
@@ -1249,7 +1272,7 @@ void st_destroy(st_handle* h) {
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     for (auto e : h->evpool) (void)hipEventDestroy(e);
-    if (h->hbuf) (void)hipHostFree(h->hbuf);
+    if (h->hbuf && h->hbuf_pinned) (void)hipHostFree(h->hbuf);
     delete h;
 }
 

@@ -243,3 +243,12 @@ void launch_cg_step(hipStream_t s, int step, long long n, double* x, double* r, 
                     double* p, const double* q, const double* invd, double* partials,
                     double* scal, const int* skip);
 }  // namespace st
+
+// st_setup with a choice of host staging (solver.cpp): pinned_host = true is
+// st_setup itself; false keeps the staging in the handle (no hipHostMalloc),
+// for the entry point that allocates nothing.
+st_status setup_impl(const st_grid* grid, const st_material* mat, const double* rho_dev,
+                     int32_t rho_time_varying, const double* ic_dev, const double* source_dev,
+                     double q0, const st_patch* patches, int32_t n_patches, const st_opts* opts,
+                     void* workspace_dev, size_t workspace_bytes, void* hip_stream,
+                     bool pinned_host, st_handle** out);
