@@ -146,6 +146,39 @@ bytes_per_launch: {total:.0f}
     print(text)
 
 
+def summarize_stats(stats_dir, title, command, out, top=20):
+    """Markdown table of a rocprofv3 --kernel-trace --stats run (the
+    *kernel_stats.csv it writes): calls, total and average time per kernel,
+    largest first."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(stats_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no kernel_stats.csv under {stats_dir}")
+    rows = {}
+    for fn in files:
+        with open(fn) as f:
+            for r in csv.DictReader(f):
+                name = r["Name"]
+                c, t = int(r["Calls"]), float(r["TotalDurationNs"])
+                pc, pt = rows.get(name, (0, 0.0))
+                rows[name] = (pc + c, pt + t)
+    total = sum(t for _, t in rows.values())
+    lines = [f"# rocprofv3 kernel statistics: {title}", "",
+             "Command (from the repository root, `cd /tmp && export TMPDIR=/tmp` first):", "",
+             f"    {command}", "",
+             f"Total kernel time {total / 1e6:.1f} ms. Top kernels by total time:", "",
+             "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+    for name, (c, t) in sorted(rows.items(), key=lambda kv: -kv[1][1])[:top]:
+        short = name.split("(")[0]
+        lines.append(f"| `{short}` | {c} | {t / 1e6:.2f} | {t / c / 1e3:.1f} | "
+                     f"{100 * t / total:.1f} |")
+    text = "\n".join(lines) + "\n"
+    with open(out, "w") as f:
+        f.write(text)
+    print(text)
+
+
 def cpu_baseline(name):
     """The FP64 oracle (block Gauss-Seidel in time with exact 2-D sparse LU
     blocks) on the first few time slabs of the same grid, same dt, to the same
@@ -550,11 +583,17 @@ def main():
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the roofline kernel's HBM traffic summary from two rocprofv3 "
                          "--pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
-    ap.add_argument("--out", default=None, help="output path of --summarize-counters")
+    ap.add_argument("--out", default=None, help="output path of --summarize-counters / -stats")
+    ap.add_argument("--summarize-stats", nargs=3, metavar=("STATS_DIR", "TITLE", "COMMAND"),
+                    help="write a markdown summary of a rocprofv3 --kernel-trace --stats run "
+                         "to --out and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy 1 GiB device buffers three times (a plain copy "
                          "kernel of known size, for scaling hardware byte counters)")
     args = ap.parse_args()
+    if args.summarize_stats:
+        summarize_stats(*args.summarize_stats, out=args.out or "kernel_stats.md")
+        return
     if args.summarize_counters:
         summarize_counters(args.summarize_counters[0], args.summarize_counters[1], args.workload,
                            args.precision, args.out or traffic_path(args.workload, args.precision))

@@ -157,7 +157,8 @@ const char* st_status_string(st_status s);
 
 /* Bytes of device workspace st_setup needs for this grid, material, options
  * and design layout (rho_time_varying: 0 = [1][ny][nx], 1 = [nt][ny][nx]).
- * Pure host computation; ST_ERR_ARG on invalid sizes. */
+ * Pure host computation; ST_ERR_ARG on invalid sizes (a grid must have fewer
+ * than 2^29 nodes, so that a node vector of FP64 values is below 4 GiB). */
 st_status st_footprint_bytes(const st_grid* grid, const st_material* mat, const st_opts* opts,
                              int32_t rho_time_varying, size_t* bytes);
 

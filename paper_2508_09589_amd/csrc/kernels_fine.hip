@@ -81,26 +81,46 @@ void launch_simp(hipStream_t s, long long ne, const double* rho, const st_materi
 // tiles: the halo rows a tile shares with its neighbours are then read from
 // the same L2.
 // Raw buffer access: base and size in a resource held in scalar registers,
-// 32-bit byte offsets per lane (no 64-bit address arithmetic per load).
+// 32-bit byte offsets per lane (no 64-bit address arithmetic per load).  One
+// resource per array serves the whole launch: it spans the whole array, and
+// the time level (or slab) is selected by the scalar offset operand, which the
+// range check includes.  The offsets need arrays below 4 GiB (checked on the
+// host).  An access at or past the resource's size reads zero without a
+// memory access.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, long long bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
-template <typename T> __device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off);
-template <> __device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff);
+template <>
+__device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
 }
-template <> __device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+template <>
+__device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
 }
 template <typename T>
-__device__ __forceinline__ void buf_st(T v, __amdgpu_buffer_rsrc_t r, unsigned off);
-template <> __device__ __forceinline__ void buf_st<float>(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+__device__ __forceinline__ void buf_st(T v, __amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff);
+template <>
+__device__ __forceinline__ void buf_st<float>(float v, __amdgpu_buffer_rsrc_t r, unsigned off,
+                                              unsigned soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, soff, 0);
 }
-template <> __device__ __forceinline__ void buf_st<double>(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+template <>
+__device__ __forceinline__ void buf_st<double>(double v, __amdgpu_buffer_rsrc_t r, unsigned off,
+                                               unsigned soff) {
     typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, soff, 0);
 }
+// Reciprocal of a Jacobi diagonal: the hardware estimate (1 ulp) in FP32, a
+// correctly rounded division in FP64.
+__device__ __forceinline__ float recip(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double recip(double d) { return 1.0 / d; }
+// Scalar offsets must be wave-uniform values in scalar registers.
+__device__ __forceinline__ unsigned uniform(unsigned v) { return __builtin_amdgcn_readfirstlane(v); }
+// Keeps a value computed before a loop from being recomputed inside it.
+template <typename T> __device__ __forceinline__ void pin_value(T& v) { asm volatile("" : "+v"(v)); }
 
 constexpr int FA_TX = 64, FA_RY = 2, FA_TY = 4 * FA_RY;
 
@@ -127,9 +147,9 @@ __global__ __launch_bounds__(256) void k_fine_apply(
     const int rem = lin - bz * tiles;
     const int by = rem / gx, bx = rem - by * gx;
     const int nx = g.nx, ny = g.ny, nt = g.nt;
-    const int n0 = bz * nchunk;
+    const int n0 = (int)uniform((unsigned)(bz * nchunk));
     if (n0 > nt) return;                      // uniform over the workgroup
-    const int n1 = min(n0 + nchunk, nt + 1);
+    const int n1 = (int)uniform((unsigned)min(n0 + nchunk, nt + 1));
     const int tx = threadIdx.x, ry0 = threadIdx.y * RY;
     const int tid = threadIdx.y * 64 + tx;
     const int i0 = bx * TX, jb = by * TY;
@@ -162,14 +182,24 @@ __global__ __launch_bounds__(256) void k_fine_apply(
         eo[r] = live ? (unsigned)(ej * nx + ei) * (unsigned)sizeof(TC) : 0u;
     }
     TC pk[LE], pc[CUNI ? 1 : LE];
+    // One resource per array for the launch (see buf_rsrc).
+    const unsigned pin = (unsigned)(P * (long long)sizeof(TIN));
+    const unsigned pout = (unsigned)(P * (long long)sizeof(TOUT));
+    const unsigned pcoef = TCONST ? 0u : (unsigned)(slab * (long long)sizeof(TC));
+    const long long levels = nt + 1, cslabs = TCONST ? 1 : nt;
+    const auto rsx = buf_rsrc(x, levels * P * (long long)sizeof(TIN));
+    const auto rsy = buf_rsrc(y, levels * P * (long long)sizeof(TOUT));
+    const auto rsb = buf_rsrc(b, b ? levels * P * (long long)sizeof(TOUT) : 0);
+    const auto rsk = buf_rsrc(kc, cslabs * slab * (long long)sizeof(TC));
+    const auto rsc = buf_rsrc(cc, CUNI ? 0 : cslabs * slab * (long long)sizeof(TC));
     // The loaded values are only touched when they are written to LDS one
     // iteration later (dead entries are zeroed there), so no wait for the
     // loads is placed before the arithmetic in between.
     TIN lx[LW];
     auto fetch_x = [&](int n) {
-        const auto rs = buf_rsrc(x + (long long)n * P, P * (long long)sizeof(TIN));
+        const unsigned so = uniform((unsigned)n * pin);
 #pragma unroll
-        for (int r = 0; r < LW; ++r) lx[r] = buf_ld<TIN>(rs, xo[r]);
+        for (int r = 0; r < LW; ++r) lx[r] = buf_ld<TIN>(rsx, xo[r], so);
     };
     auto put_x = [&](int n) {
         TC* d = xs[n % 3];
@@ -179,13 +209,11 @@ __global__ __launch_bounds__(256) void k_fine_apply(
             if (tid + 256 * r < NW) d[tid + 256 * r] = ((live >> r) & 1u) ? (TC)lx[r] : (TC)0;
     };
     auto fetch_c = [&](int s) {
-        const long long sb = TCONST ? 0 : (long long)s * slab;
-        const auto rk = buf_rsrc(kc + sb, slab * (long long)sizeof(TC));
-        const auto rc = buf_rsrc(cc + sb, CUNI ? 0 : slab * (long long)sizeof(TC));
+        const unsigned so = TCONST ? 0u : uniform((unsigned)s * pcoef);
 #pragma unroll
         for (int r = 0; r < LE; ++r) {
-            pk[r] = buf_ld<TC>(rk, eo[r]);
-            if (!CUNI) pc[r] = buf_ld<TC>(rc, eo[r]);
+            pk[r] = buf_ld<TC>(rsk, eo[r], so);
+            if (!CUNI) pc[r] = buf_ld<TC>(rsc, eo[r], so);
         }
     };
     auto put_c = [&](int s) {
@@ -279,14 +307,17 @@ __global__ __launch_bounds__(256) void k_fine_apply(
     TIN xd[RY];
     constexpr unsigned OOB = 0x7FFFFFF0u;
     auto fetch_bd = [&](int n) {
-        const auto rb = buf_rsrc(b + (long long)n * P, b ? P * (long long)sizeof(TOUT) : 0);
-        const auto rx = buf_rsrc(x + (long long)n * P, P * (long long)sizeof(TIN));
+        const unsigned sob = uniform((unsigned)n * pout);
+        // x of the Dirichlet rows: a resource over level n alone, so that
+        // the rows that are not Dirichlet rows read past its end (zero, no
+        // memory access) whatever the level
+        const auto rxn = buf_rsrc(x + (long long)n * P, P * (long long)sizeof(TIN));
         const bool ic = dir_rows && g.ic_dir && n == 0;
 #pragma unroll
         for (int m = 0; m < RY; ++m) {
-            bv[m] = buf_ld<TOUT>(rb, oo[m] * (unsigned)sizeof(TOUT));
+            bv[m] = buf_ld<TOUT>(rsb, oo[m] * (unsigned)sizeof(TOUT), sob);
             const bool dr = ic || (dir_rows && ((opatch >> m) & 1u));
-            xd[m] = buf_ld<TIN>(rx, dr ? oo[m] * (unsigned)sizeof(TIN) : OOB);
+            xd[m] = buf_ld<TIN>(rxn, dr ? oo[m] * (unsigned)sizeof(TIN) : OOB, 0u);
         }
     };
     // jacobi: the output is scaled by the inverse diagonal of the operator,
@@ -296,14 +327,14 @@ __global__ __launch_bounds__(256) void k_fine_apply(
     //   diag(s) = 8 kt (Sk(s - 1) + Sk(s)) + 4 mw Sc(s - 1),
     // Sk, Sc = sums over the four elements around the node in a slab; a
     // Dirichlet row has the unit diagonal.
-    auto emit = [&](int n, int m, TC v, TC diag) {
+    // rdiag: the reciprocal of that diagonal.
+    auto emit = [&](int n, int m, TC v, TC rdiag) {
         if (!((own >> m) & 1u)) return;
         const bool dir = dir_rows && ((g.ic_dir && n == 0) || ((opatch >> m) & 1u));
         TC val = dir ? (TC)xd[m] : v;
         if (b) val = (TC)bv[m] - val;
-        if (jacobi && !dir) val /= diag;
-        buf_st<TOUT>((TOUT)(val * sc), buf_rsrc(y + (long long)n * P, P * (long long)sizeof(TOUT)),
-                     oo[m] * (unsigned)sizeof(TOUT));
+        if (jacobi && !dir) val *= rdiag;
+        buf_st<TOUT>((TOUT)(val * sc), rsy, oo[m] * (unsigned)sizeof(TOUT), uniform((unsigned)n * pout));
     };
 
     const int sa = max(n0 - 1, 0);
@@ -326,12 +357,22 @@ __global__ __launch_bounds__(256) void k_fine_apply(
         Plo[m] = 0;
         Rlo[m] = 0;
     }
+    // Time-constant coefficients: the diagonal of a row is the same on every
+    // level but the first (no slab below) and the last (none above).
+    TC rmid[RY], rfirst[RY], rlast[RY];
     if (TCONST) {
         read_x(sa, ulo);
 #pragma unroll
         for (int m = 0; m < RY; ++m) {
             Plo[m] = kt * stiff(ulo, m);
             Rlo[m] = mw * mass(ulo, m);
+            const TC dl = (TC)8 * kt * (ke[m][0] + ke[m][1] + ke[m + 1][0] + ke[m + 1][1]);
+            const TC du = (TC)4 * mw * (ce[m][0] + ce[m][1] + ce[m + 1][0] + ce[m + 1][1]);
+            rmid[m] = (TC)1 / (dl + dl + du);
+            rfirst[m] = (TC)1 / dl;
+            rlast[m] = (TC)1 / (dl + du);
+            pin_value(rmid[m]);
+            pin_value(rfirst[m]);
         }
     }
     for (int s = sa; s <= sb; ++s) {
@@ -358,16 +399,18 @@ __global__ __launch_bounds__(256) void k_fine_apply(
                 const TC Rv = TCONST ? Rlo[m] : mw * mass(ulo, m);
                 top += Sv - Rv;
             }
-            const TC sk = ke[m][0] + ke[m][1] + ke[m + 1][0] + ke[m + 1][1];
-            const TC sc4 = ce[m][0] + ce[m][1] + ce[m + 1][0] + ce[m + 1][1];
-            const TC dlo = (TC)8 * kt * sk;
-            if (s >= n0) emit(s, m, acc[m] + bottom, dacc[m] + dlo);
-            acc[m] = top;
-            dacc[m] = dlo + (TC)4 * mw * sc4;
             if (TCONST) {
+                if (s >= n0) emit(s, m, acc[m] + bottom, s == 0 ? rfirst[m] : rmid[m]);
                 Plo[m] = Qv;
                 Rlo[m] = Sv;
+            } else {
+                const TC sk = ke[m][0] + ke[m][1] + ke[m + 1][0] + ke[m + 1][1];
+                const TC sc4 = ce[m][0] + ce[m][1] + ce[m + 1][0] + ce[m + 1][1];
+                const TC dlo = (TC)8 * kt * sk;
+                if (s >= n0) emit(s, m, acc[m] + bottom, jacobi ? recip(dacc[m] + dlo) : (TC)1);
+                dacc[m] = dlo + (TC)4 * mw * sc4;
             }
+            acc[m] = top;
         }
         if (!TCONST && s + 1 <= sb) read_c(s + 1);
         // b of the next level: issued after this level's outputs, so
@@ -376,7 +419,8 @@ __global__ __launch_bounds__(256) void k_fine_apply(
     }
     if (sb + 1 == nt && nt >= n0 && nt < n1) {
 #pragma unroll
-        for (int m = 0; m < RY; ++m) emit(nt, m, acc[m], dacc[m]);
+        for (int m = 0; m < RY; ++m)
+            emit(nt, m, acc[m], TCONST ? rlast[m] : (jacobi ? recip(dacc[m]) : (TC)1));
     }
 }
 

@@ -272,6 +272,9 @@ size_t carve(st_handle* h, char* base) {
 st_status validate(const st_grid* g, const st_material* m, const st_opts* o) {
     if (!g || !m || !o) return ST_ERR_ARG;
     if (g->nx < 1 || g->ny < 1 || g->nt < 1) return ST_ERR_ARG;
+    // the fine-level kernels address a node vector of FP64 values with 32-bit
+    // byte offsets: fewer than 2^29 nodes
+    if ((long long)(g->nx + 1) * (g->ny + 1) * (g->nt + 1) >= (1LL << 29)) return ST_ERR_ARG;
     if (!(g->dx > 0) || !(g->dt > 0)) return ST_ERR_ARG;
     if (!(m->k_ins > 0) || !(m->k_con > 0) || !(m->c_ins > 0) || !(m->c_con > 0)) return ST_ERR_ARG;
     if (o->precision != ST_FP64 && o->precision != ST_MIXED) return ST_ERR_ARG;

@@ -78,6 +78,8 @@ int main() {
         expect(footprint(8, 8, 8, q, 0, &b) == ST_ERR_ARG, "rtol");
         expect(footprint(0, 8, 8, o, 0, &b) == ST_ERR_ARG, "nx");
         expect(footprint(8, 8, -3, o, 0, &b) == ST_ERR_ARG, "nt");
+        expect(footprint(1024, 1024, 512, o, 0, &b) == ST_ERR_ARG, "2^29 nodes");
+        expect(footprint(1022, 1022, 510, o, 0, &b) == ST_OK, "under 2^29 nodes");
         st_grid g{8, 8, 8, 0.125, 0.125};
         st_material m{1e-3, 1.0, 3.0, 1.0, 1.0, 1.0};
         expect(st_footprint_bytes(nullptr, &m, &o, 0, &b) == ST_ERR_ARG, "null grid");
