@@ -110,7 +110,11 @@ typedef struct {
     double coarse_rtol;       /* default 1e-6                                   */
     int32_t coarse_restart;   /* default 30 (<= 32)                             */
     double lambda_crit;       /* Algorithm 1 threshold, default 0.5             */
-    int32_t max_levels;       /* default 32; a positive n fixes at most n levels */
+    int32_t max_levels;       /* N_l, default 8 (the paper's space-time runs):
+                                 at most this many levels unless the coarsest
+                                 one is too large to factorise exactly (planes
+                                 over 2048 nodes or factors over 16 GiB); 1 =
+                                 one level (the coarsest solve alone)          */
     int64_t max_coarse_nodes; /* stop coarsening at <= this many nodes, 4096    */
     double filter_r;          /* PDE filter radius in elements (r_x = r dx,
                                  r_t = r dt); 0 = no filter                      */

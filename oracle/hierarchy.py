@@ -13,8 +13,12 @@ Readings where the paper is silent:
   * the comparison is strict ("<"), so lambda == lambda_crit coarsens in space;
   * when the chosen direction cannot be halved (odd or unit element count) the
     other direction is tried, and when neither can the hierarchy stops;
-  * without an explicit level count the hierarchy stops once a level has at
-    most max_coarse_nodes nodes.
+  * the number of levels N_l is a user choice in the paper (8 for its
+    space-time runs in §4, 7 in §5); max_levels defaults to 8, and the
+    hierarchy also stops once a level has at most max_coarse_nodes nodes;
+  * past max_levels coarsening continues only while the coarsest level is too
+    large to be factorised exactly by the solver (planes of more than
+    max_plane nodes, or a block factorisation of more than max_factor_bytes).
 """
 import math
 
@@ -33,9 +37,14 @@ def _can_halve_time(nt):
     return nt % 2 == 0 and nt >= 2
 
 
+def _factorable(L, max_plane, max_factor_bytes):
+    P = (L["nx"] + 1) * (L["ny"] + 1)
+    return P <= max_plane and P * P * 16.0 * (L["nt"] + 1) <= max_factor_bytes
+
+
 def build_hierarchy(nx, ny, nt, dx, dt, k_con, k_ins, c_con, c_ins,
-                    lambda_crit=0.5, n_levels=None, max_coarse_nodes=4096, max_levels=32,
-                    full=False):
+                    lambda_crit=0.5, n_levels=None, max_coarse_nodes=4096, max_levels=8,
+                    full=False, max_plane=2048, max_factor_bytes=16.0 * 2 ** 30):
     """Return a list of dicts, one per level (finest first), with keys
     nx, ny, nt, dx, dt, lam (anisotropy of that level) and how (how the level
     was made from the one above it: None, 'space', 'time' or 'full').
@@ -44,10 +53,13 @@ def build_hierarchy(nx, ny, nt, dx, dt, k_con, k_ins, c_con, c_ins,
     D = d_eff(k_con, k_ins, c_con, c_ins)
     levels = [dict(nx=nx, ny=ny, nt=nt, dx=dx, dt=dt, how=None)]
     limit = n_levels if n_levels is not None else max_levels
-    while len(levels) < limit:
+    while len(levels) < (limit if n_levels is not None else 32):
         L = levels[-1]
         L["lam"] = D * L["dt"] / L["dx"] ** 2
         if n_levels is None and (L["nx"] + 1) * (L["ny"] + 1) * (L["nt"] + 1) <= max_coarse_nodes:
+            break
+        if n_levels is None and len(levels) >= limit and (
+                max_levels < 2 or _factorable(L, max_plane, max_factor_bytes)):
             break
         if full:
             if not (_can_halve_space(L["nx"], L["ny"]) and _can_halve_time(L["nt"])):

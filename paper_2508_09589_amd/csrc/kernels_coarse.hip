@@ -26,11 +26,14 @@
 //     J^T x = b:  w_s = b_s - G_{s-1}^T w_{s-1},
 //                 x_s = D'_s^{-T} w_s - M_s x_{s+1}.
 // (one barrier per time level instead of a chain of dependent global loads).
+#include <algorithm>
+
 #include "st_internal.hpp"
 
 namespace st {
 
 constexpr int CDT = 1024;   // threads of the coarse factor / solve workgroup
+constexpr int CW_NB = CW_PANEL_NB;   // panel width of the wide Gauss-Jordan
 constexpr int CD_SEG = 8;   // lanes that share one row of a dense product
 
 // Stencil entry of row (plane n, in-plane index r) towards the neighbour at
@@ -243,112 +246,6 @@ __global__ __launch_bounds__(CDT) void k_coarse_factor(int nx, int ny, int nt, i
     }
 }
 
-// out[r] = sum_c M[r][c] v[c] (trans = 0) or sum_c M[c][r] v[c] (trans = 1),
-// r < P; CD_SEG lanes share one output.  v in LDS, M in global.
-__device__ void cd_gemv(const double* __restrict__ M, const double* v, int P, int trans,
-                        double* out, double sub_sign, const double* base) {
-    const int q = threadIdx.x & (CD_SEG - 1);
-    for (int r0 = 0; r0 < P; r0 += CDT / CD_SEG) {
-        const int r = r0 + threadIdx.x / CD_SEG;
-        double acc = 0.0;
-        if (r < P) {
-            if (!trans)
-                for (int c = q; c < P; c += CD_SEG) acc += M[(long long)r * P + c] * v[c];
-            else
-                for (int c = q; c < P; c += CD_SEG) acc += M[(long long)c * P + r] * v[c];
-        }
-#pragma unroll
-        for (int o = CD_SEG / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-        if (r < P && q == 0) out[r] = base ? base[r] + sub_sign * acc : acc;
-    }
-}
-
-// Solve J x = b (trans = 0) or J^T x = b (trans = 1) with the factors; one
-// workgroup.  t, u: 2 P doubles of LDS; work: (nt + 1) P doubles (global).
-template <typename TIO>
-__global__ __launch_bounds__(CDT) void k_coarse_direct(int nx, int ny, int nt, int nplanes,
-                                                       const double* __restrict__ st,
-                                                       const int* __restrict__ pmap,
-                                                       const double* __restrict__ Dinv,
-                                                       const double* __restrict__ G,
-                                                       const TIO* __restrict__ b,
-                                                       TIO* __restrict__ x,
-                                                       double* __restrict__ work, int trans) {
-    extern __shared__ double dyn[];
-    const int row = nx + 1, P = row * (ny + 1);
-    const long long PP = (long long)P * P;
-    const long long DS = (long long)P * nplanes;
-    double* t = dyn;
-    double* u = dyn + P;
-    const int tid = threadIdx.x;
-    // Coupling of row a of level s to the level sn = s + dn vector y (global):
-    // forward uses row a's own entries, the transpose the entries of the rows
-    // of level sn that point at a.
-    auto couple = [&](int s, int a, int dn, const double* y, int transposed) -> double {
-        const int ja = a / row, ia = a - ja * row;
-        const int sn = s + dn;
-        double acc = 0.0;
-        for (int qj = -1; qj <= 1; ++qj) {
-            const int jb = ja + qj;
-            if (jb < 0 || jb > ny) continue;
-            for (int qi = -1; qi <= 1; ++qi) {
-                const int ib = ia + qi;
-                if (ib < 0 || ib > nx) continue;
-                const int bb = jb * row + ib;
-                const double c = transposed ? cd_entry(st, pmap, DS, P, sn, bb, -dn, -qj, -qi)
-                                            : cd_entry(st, pmap, DS, P, s, a, dn, qj, qi);
-                acc += c * y[(long long)sn * P + bb];
-            }
-        }
-        return acc;
-    };
-    if (!trans) {
-        for (int s = 0; s <= nt; ++s) {   // z_s = D'^{-1}_s (b_s - L_s z_{s-1})
-            for (int a = tid; a < P; a += CDT) {
-                double v = (double)b[(long long)s * P + a];
-                if (s > 0) v -= couple(s, a, -1, work, 0);
-                t[a] = v;
-            }
-            __syncthreads();
-            cd_gemv(Dinv + (long long)s * PP, t, P, 0, work + (long long)s * P, 0.0, nullptr);
-            __syncthreads();
-        }
-        for (int s = nt - 1; s >= 0; --s) {   // x_s = z_s - G_s x_{s+1}
-            for (int a = tid; a < P; a += CDT) u[a] = work[(long long)(s + 1) * P + a];
-            __syncthreads();
-            cd_gemv(G + (long long)s * PP, u, P, 0, work + (long long)s * P, -1.0,
-                    work + (long long)s * P);
-            __syncthreads();
-        }
-    } else {
-        for (int s = 0; s <= nt; ++s) {   // w_s = b_s - G_{s-1}^T w_{s-1}
-            if (s == 0) {
-                for (int a = tid; a < P; a += CDT) work[a] = (double)b[a];
-            } else {
-                for (int a = tid; a < P; a += CDT) {
-                    u[a] = work[(long long)(s - 1) * P + a];
-                    t[a] = (double)b[(long long)s * P + a];
-                }
-                __syncthreads();
-                cd_gemv(G + (long long)(s - 1) * PP, u, P, 1, work + (long long)s * P, -1.0, t);
-            }
-            __syncthreads();
-        }
-        for (int s = nt; s >= 0; --s) {   // x_s = D'^{-T}_s (w_s - L_{s+1}^T x_{s+1})
-            for (int a = tid; a < P; a += CDT) {
-                double v = work[(long long)s * P + a];
-                if (s < nt) v -= couple(s, a, 1, work, 1);
-                t[a] = v;
-            }
-            __syncthreads();
-            cd_gemv(Dinv + (long long)s * PP, t, P, 1, work + (long long)s * P, 0.0, nullptr);
-            __syncthreads();
-        }
-    }
-    const long long n = (long long)P * (nt + 1);
-    for (long long i = tid; i < n; i += CDT) x[i] = (TIO)work[i];
-}
-
 // Fast solve (P <= CD_FAST_P, 2 (nt + 1) P doubles of LDS).  Thread t owns row
 // r = t / 8 of each product and its columns c = t % 8 + 8 k; the row slices of
 // the next step's matrices are loaded while the current step reduces and
@@ -439,6 +336,439 @@ __global__ __launch_bounds__(CDT) void k_coarse_direct_fast(int P, int nt,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Wide factorisation and solve (planes larger than CD_FAST_P): the same block
+// LU, with every step spread over the whole GPU.
+//
+// D'_s^{-1} by blocked Gauss-Jordan with partial pivoting, in place on A:
+// the steps of CW_NB consecutive columns (a panel) are carried out on the
+// P x CW_NB panel alone by one workgroup (the row interchanges go to whole
+// rows at once); their product is the identity except in the panel's
+// columns, E = I + W B^T with W = (panel after the steps) - (identity
+// columns), so every other column then takes the rank-CW_NB update
+// A[:, c] += W A[B, c] (A[B, c]: the panel's pivot rows before the update).
+// Columns done by earlier panels hold columns of the inverse under
+// construction and are updated like the others.  At the end the row
+// interchanges are undone as column interchanges (last first).
+
+__global__ void k_cw_init_status(int* status) { *status = 0; }
+
+// A = D_s - L_s G_{s-1} (no coupling term for s = 0).
+__global__ void k_cw_schur(int nx, int ny, int nplanes, const double* __restrict__ st,
+                           const int* __restrict__ pmap, int s, const double* __restrict__ Gp,
+                           double* __restrict__ A) {
+    const int row = nx + 1, P = row * (ny + 1);
+    const long long PP = (long long)P * P;
+    const long long DS = (long long)P * nplanes;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < PP;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int a = (int)(e / P), c = (int)(e - (long long)a * P);
+        const int ja = a / row, ia = a - ja * row;
+        const int jc = c / row, ic = c - jc * row;
+        double v = 0.0;
+        const int dj = jc - ja, di = ic - ia;
+        if (dj >= -1 && dj <= 1 && di >= -1 && di <= 1) v = cd_entry(st, pmap, DS, P, s, a, 0, dj, di);
+        if (Gp) {
+            for (int qj = -1; qj <= 1; ++qj) {
+                const int jb = ja + qj;
+                if (jb < 0 || jb > ny) continue;
+                for (int qi = -1; qi <= 1; ++qi) {
+                    const int ib = ia + qi;
+                    if (ib < 0 || ib > nx) continue;
+                    const double l = cd_entry(st, pmap, DS, P, s, a, -1, qj, qi);
+                    if (l != 0.0) v -= l * Gp[(long long)(jb * row + ib) * P + c];
+                }
+            }
+        }
+        A[e] = v;
+    }
+}
+
+// The Gauss-Jordan steps of panel columns k0 .. k0 + nb - 1 (one workgroup).
+// pan: the P x CW_NB panel (LDS when it fits, else global scratch), colk: P
+// doubles.  Writes the panel back into A, W = panel - identity columns, and
+// R = the pivot rows' entries outside the panel (zero inside it).
+template <bool LDSPAN>
+__global__ __launch_bounds__(CDT) void k_cw_panel(int P, int k0, double* __restrict__ A,
+                                                  double* __restrict__ panel_g,
+                                                  double* __restrict__ colk_g,
+                                                  double* __restrict__ W, double* __restrict__ R,
+                                                  int* __restrict__ perm, int* __restrict__ status) {
+    extern __shared__ double dyn[];
+    double* pan = LDSPAN ? dyn : panel_g;
+    double* colk = LDSPAN ? dyn + (long long)P * CW_NB : colk_g;
+    __shared__ double rv[CDT / 64 + 1];
+    __shared__ int ri[CDT / 64 + 1];
+    const int tid = threadIdx.x;
+    const int nb = min(CW_NB, P - k0);
+    for (long long e = tid; e < (long long)P * CW_NB; e += CDT) {
+        const int i = (int)(e / CW_NB), j = (int)(e - (long long)i * CW_NB);
+        pan[e] = j < nb ? A[(long long)i * P + k0 + j] : 0.0;
+    }
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        const int k = k0 + j;
+        // pivot: largest |pan[i][j]| over rows i >= k (smallest index on ties)
+        double best = -1.0;
+        int bi = k;
+        for (int i = k + tid; i < P; i += CDT) {
+            const double v = fabs(pan[(long long)i * CW_NB + j]);
+            if (v > best) {
+                best = v;
+                bi = i;
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ov = __shfl_down(best, o, 64);
+            const int oi = __shfl_down(bi, o, 64);
+            if (ov > best || (ov == best && oi < bi)) {
+                best = ov;
+                bi = oi;
+            }
+        }
+        if ((tid & 63) == 0) {
+            rv[tid >> 6] = best;
+            ri[tid >> 6] = bi;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double b = rv[0];
+            int i0 = ri[0];
+            for (int w = 1; w < CDT / 64; ++w)
+                if (rv[w] > b || (rv[w] == b && ri[w] < i0)) {
+                    b = rv[w];
+                    i0 = ri[w];
+                }
+            ri[CDT / 64] = i0;
+            perm[k] = i0;
+            if (b == 0.0) *status = 1;
+        }
+        __syncthreads();
+        const int p = ri[CDT / 64];
+        if (p != k) {
+            for (int c = tid; c < CW_NB; c += CDT) {
+                const double t = pan[(long long)k * CW_NB + c];
+                pan[(long long)k * CW_NB + c] = pan[(long long)p * CW_NB + c];
+                pan[(long long)p * CW_NB + c] = t;
+            }
+            for (int c = tid; c < P; c += CDT) {
+                if (c >= k0 && c < k0 + nb) continue;
+                const double t = A[(long long)k * P + c];
+                A[(long long)k * P + c] = A[(long long)p * P + c];
+                A[(long long)p * P + c] = t;
+            }
+        }
+        __syncthreads();
+        const double ipiv = 1.0 / pan[(long long)k * CW_NB + j];
+        for (int i = tid; i < P; i += CDT) colk[i] = pan[(long long)i * CW_NB + j];
+        __syncthreads();
+        for (int c = tid; c < nb; c += CDT)
+            pan[(long long)k * CW_NB + c] = (c == j ? 1.0 : pan[(long long)k * CW_NB + c]) * ipiv;
+        __syncthreads();
+        for (long long e = tid; e < (long long)P * CW_NB; e += CDT) {
+            const int i = (int)(e / CW_NB), c = (int)(e - (long long)i * CW_NB);
+            if (i == k || c >= nb) continue;
+            pan[e] = (c == j ? 0.0 : pan[e]) - colk[i] * pan[(long long)k * CW_NB + c];
+        }
+        __syncthreads();
+    }
+    for (long long e = tid; e < (long long)P * CW_NB; e += CDT) {
+        const int i = (int)(e / CW_NB), j = (int)(e - (long long)i * CW_NB);
+        const double v = pan[e];
+        if (j < nb) A[(long long)i * P + k0 + j] = v;
+        W[e] = j < nb ? v - (i == k0 + j ? 1.0 : 0.0) : 0.0;
+    }
+    for (long long e = tid; e < (long long)CW_NB * P; e += CDT) {
+        const int j = (int)(e / P), c = (int)(e - (long long)j * P);
+        R[e] = (j < nb && (c < k0 || c >= k0 + nb)) ? A[(long long)(k0 + j) * P + c] : 0.0;
+    }
+}
+
+// A[i][c] += sum_j W[i][j] R[j][c] for the columns outside the panel
+// (R is zero in the panel's columns); grid (columns / 256, P rows).
+__global__ __launch_bounds__(256) void k_cw_update(int P, int k0, double* __restrict__ A,
+                                                   const double* __restrict__ W,
+                                                   const double* __restrict__ R) {
+    const int i = blockIdx.y;
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= P || (c >= k0 && c < k0 + CW_NB)) return;
+    double w[CW_NB];
+#pragma unroll
+    for (int j = 0; j < CW_NB; ++j) w[j] = W[(long long)i * CW_NB + j];
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < CW_NB; ++j) acc += w[j] * R[(long long)j * P + c];
+    A[(long long)i * P + c] += acc;
+}
+
+// Undo the row interchanges as column interchanges (last first):
+// Dinv[i][c] = A[i][idx[c]].  One thread forms idx.
+__global__ void k_cw_colperm(int P, const int* __restrict__ perm, int* __restrict__ idx) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    for (int c = 0; c < P; ++c) idx[c] = c;
+    for (int k = P - 1; k >= 0; --k) {
+        const int p = perm[k];
+        const int t = idx[k];
+        idx[k] = idx[p];
+        idx[p] = t;
+    }
+}
+__global__ void k_cw_gather(int P, const double* __restrict__ A, const int* __restrict__ idx,
+                            double* __restrict__ Dinv) {
+    const long long PP = (long long)P * P;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < PP;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(e / P), c = (int)(e - (long long)i * P);
+        Dinv[e] = A[(long long)i * P + idx[c]];
+    }
+}
+
+// G_s = D'_s^{-1} U_s (U_s: the dn = +1 entries; only in-plane neighbours
+// b of c are non-zero).
+__global__ void k_cw_gmat(int nx, int ny, int nplanes, const double* __restrict__ st,
+                          const int* __restrict__ pmap, int s, const double* __restrict__ Di,
+                          double* __restrict__ Gs) {
+    const int row = nx + 1, P = row * (ny + 1);
+    const long long PP = (long long)P * P;
+    const long long DS = (long long)P * nplanes;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < PP;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int a = (int)(e / P), c = (int)(e - (long long)a * P);
+        const int jc = c / row, ic = c - jc * row;
+        double v = 0.0;
+        for (int qj = -1; qj <= 1; ++qj) {
+            const int jb = jc + qj;
+            if (jb < 0 || jb > ny) continue;
+            for (int qi = -1; qi <= 1; ++qi) {
+                const int ib = ic + qi;
+                if (ib < 0 || ib > nx) continue;
+                const int b = jb * row + ib;
+                const double u = cd_entry(st, pmap, DS, P, s, b, 1, -qj, -qi);
+                if (u != 0.0) v += Di[(long long)a * P + b] * u;
+            }
+        }
+        Gs[e] = v;
+    }
+}
+
+size_t cw_panel_lds(int P) { return (size_t)P * (CW_NB + 1) * sizeof(double); }
+
+void launch_coarse_factor_wide(hipStream_t s, const Level& L, int lds_max, double* A,
+                               double* Dinv, double* G, double* panel, double* colk, double* W,
+                               double* R, int* perm, int* idx, int* status) {
+    const int P = (L.nx + 1) * (L.ny + 1);
+    const long long PP = (long long)P * P;
+    const unsigned eb = (unsigned)std::min<long long>((PP + 255) / 256, 65535);
+    const size_t lds = cw_panel_lds(P);
+    const bool lds_panel = lds <= (size_t)lds_max;
+    if (lds_panel && lds > 65536)
+        (void)hipFuncSetAttribute((const void*)&k_cw_panel<true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_cw_init_status, dim3(1), dim3(1), 0, s, status);
+    for (int t = 0; t <= L.nt; ++t) {
+        hipLaunchKernelGGL(k_cw_schur, dim3(eb), dim3(256), 0, s, L.nx, L.ny, L.nplanes, L.st64,
+                           L.plane_map, t, t > 0 ? G + (long long)(t - 1) * PP : nullptr, A);
+        for (int k0 = 0; k0 < P; k0 += CW_NB) {
+            if (lds_panel)
+                hipLaunchKernelGGL(k_cw_panel<true>, dim3(1), dim3(CDT), lds, s, P, k0, A, panel,
+                                   colk, W, R, perm, status);
+            else
+                hipLaunchKernelGGL(k_cw_panel<false>, dim3(1), dim3(CDT), 0, s, P, k0, A, panel,
+                                   colk, W, R, perm, status);
+            hipLaunchKernelGGL(k_cw_update, dim3((P + 255) / 256, P), dim3(256), 0, s, P, k0, A, W,
+                               R);
+        }
+        hipLaunchKernelGGL(k_cw_colperm, dim3(1), dim3(1), 0, s, P, perm, idx);
+        double* Di = Dinv + (long long)t * PP;
+        hipLaunchKernelGGL(k_cw_gather, dim3(eb), dim3(256), 0, s, P, A, idx, Di);
+        if (t < L.nt)
+            hipLaunchKernelGGL(k_cw_gmat, dim3(eb), dim3(256), 0, s, L.nx, L.ny, L.nplanes, L.st64,
+                               L.plane_map, t, Di, G + (long long)t * PP);
+    }
+}
+
+// Wide solve.  z: forward-sweep vectors, xo: solution, both [nt + 1][P]
+// FP64.  Dense products: row form out[r] = sum_c M[r][c] v[c] (one wave per
+// row, lanes across columns) or column form out[r] = sum_c M[c][r] v[c]
+// (lanes across outputs, the workgroup's waves across segments of c).
+constexpr int CW_ROWS = 1;      // rows per wave in the row form
+constexpr int CW_CSEG = 16;     // waves (column segments) per workgroup in the column form
+
+// Coupling of row a of level t to level t + dn of y (forward: row a's own
+// entries; transposed: the entries of the rows of level t + dn that point at a).
+__device__ __forceinline__ double cw_couple(int nx, int ny, const double* st, const int* pmap,
+                                            long long DS, int P, int t, int a, int dn,
+                                            const double* y, int transposed) {
+    const int row = nx + 1;
+    const int ja = a / row, ia = a - ja * row;
+    const int tn = t + dn;
+    double acc = 0.0;
+    for (int qj = -1; qj <= 1; ++qj) {
+        const int jb = ja + qj;
+        if (jb < 0 || jb > ny) continue;
+        for (int qi = -1; qi <= 1; ++qi) {
+            const int ib = ia + qi;
+            if (ib < 0 || ib > nx) continue;
+            const int bb = jb * row + ib;
+            const double c = transposed ? cd_entry(st, pmap, DS, P, tn, bb, -dn, -qj, -qi)
+                                        : cd_entry(st, pmap, DS, P, t, a, dn, qj, qi);
+            acc += c * y[bb];
+        }
+    }
+    return acc;
+}
+
+// Row form: out[r] = base[r] + sgn * sum_c M[r][c] v[c], with v = vb - (coupling of
+// level t to level t + dn of y) formed in LDS by every workgroup (y null: v = vb).
+template <typename TB>
+__global__ __launch_bounds__(256) void k_cw_rows(int nx, int ny, int nplanes,
+                                                 const double* __restrict__ st,
+                                                 const int* __restrict__ pmap, int t, int dn,
+                                                 int couple_trans, const TB* __restrict__ vb,
+                                                 const double* __restrict__ y,
+                                                 const double* __restrict__ M,
+                                                 const double* __restrict__ base, double sgn,
+                                                 double* __restrict__ out, double* __restrict__ out2) {
+    extern __shared__ double v[];
+    const int P = (nx + 1) * (ny + 1);
+    const long long DS = (long long)P * nplanes;
+    for (int a = threadIdx.x; a < P; a += 256) {
+        double w = (double)vb[a];
+        if (y) w -= cw_couple(nx, ny, st, pmap, DS, P, t, a, dn, y, couple_trans);
+        v[a] = w;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r0 = (blockIdx.x * 4 + wave) * CW_ROWS;
+#pragma unroll
+    for (int q = 0; q < CW_ROWS; ++q) {
+        const int r = r0 + q;
+        if (r >= P) break;
+        // four independent partial sums keep several loads of the row in flight
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        const double* Mr = M + (long long)r * P;
+        int c = lane;
+        for (; c + 192 < P; c += 256) {
+            a0 += Mr[c] * v[c];
+            a1 += Mr[c + 64] * v[c + 64];
+            a2 += Mr[c + 128] * v[c + 128];
+            a3 += Mr[c + 192] * v[c + 192];
+        }
+        for (; c < P; c += 64) a0 += Mr[c] * v[c];
+        double acc = (a0 + a1) + (a2 + a3);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (lane == 0) {
+            const double val = base ? base[r] + sgn * acc : sgn * acc;
+            out[r] = val;
+            if (out2) out2[r] = val;
+        }
+    }
+}
+
+// Column form: out[r] = base[r] + sgn * sum_c M[c][r] v[c], v as in the row form.
+template <typename TB>
+__global__ __launch_bounds__(64 * CW_CSEG) void k_cw_cols(int nx, int ny, int nplanes,
+                                                          const double* __restrict__ st,
+                                                          const int* __restrict__ pmap, int t,
+                                                          int dn, int couple_trans,
+                                                          const double* __restrict__ vb,
+                                                          const double* __restrict__ y,
+                                                          const double* __restrict__ M,
+                                                          const TB* __restrict__ base, double sgn,
+                                                          double* __restrict__ out) {
+    extern __shared__ double v[];
+    __shared__ double part[CW_CSEG][64];
+    const int P = (nx + 1) * (ny + 1);
+    const long long DS = (long long)P * nplanes;
+    for (int a = threadIdx.x; a < P; a += 64 * CW_CSEG) {
+        double w = vb[a];
+        if (y) w -= cw_couple(nx, ny, st, pmap, DS, P, t, a, dn, y, couple_trans);
+        v[a] = w;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
+    const int r = blockIdx.x * 64 + lane;
+    const int cs = (P + CW_CSEG - 1) / CW_CSEG;
+    const int c0 = seg * cs, c1 = min(P, c0 + cs);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (r < P) {
+        int c = c0;
+        for (; c + 3 < c1; c += 4) {
+            a0 += M[(long long)c * P + r] * v[c];
+            a1 += M[(long long)(c + 1) * P + r] * v[c + 1];
+            a2 += M[(long long)(c + 2) * P + r] * v[c + 2];
+            a3 += M[(long long)(c + 3) * P + r] * v[c + 3];
+        }
+        for (; c < c1; ++c) a0 += M[(long long)c * P + r] * v[c];
+    }
+    part[seg][lane] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (seg == 0 && r < P) {
+        double sum = 0.0;
+        for (int q = 0; q < CW_CSEG; ++q) sum += part[q][lane];
+        out[r] = base ? (double)base[r] + sgn * sum : sgn * sum;
+    }
+}
+
+template <typename TIO>
+__global__ void k_cw_in(long long n, const TIO* __restrict__ b, double* __restrict__ z) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        z[i] = (double)b[i];
+}
+
+template <typename TIO>
+__global__ void k_cw_out(long long n, const double* __restrict__ xo, TIO* __restrict__ x) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        x[i] = (TIO)xo[i];
+}
+
+template <typename TIO>
+static void cw_solve(hipStream_t s, const Level& L, int trans, const TIO* b, TIO* x,
+                     const double* Dinv, const double* G, double* work) {
+    const int P = (L.nx + 1) * (L.ny + 1), nt = L.nt;
+    const long long PP = (long long)P * P, n = (long long)P * (nt + 1);
+    double* z = work;
+    double* xo = work + n;
+    const size_t lds = (size_t)P * sizeof(double);
+    const dim3 grow((P + 4 * CW_ROWS - 1) / (4 * CW_ROWS)), gcol((P + 63) / 64);
+    const double* nul = nullptr;
+    if (!trans) {
+        // z_t = D'^{-1}_t (b_t - L_t z_{t-1}); x_nt = z_nt
+        for (int t = 0; t <= nt; ++t)
+            hipLaunchKernelGGL(k_cw_rows<TIO>, grow, dim3(256), lds, s, L.nx, L.ny, L.nplanes,
+                               L.st64, L.plane_map, t, -1, 0, b + (long long)t * P,
+                               t > 0 ? z + (long long)(t - 1) * P : nul, Dinv + (long long)t * PP,
+                               nul, 1.0, z + (long long)t * P,
+                               t == nt ? xo + (long long)t * P : nullptr);
+        // x_t = z_t - G_t x_{t+1}
+        for (int t = nt - 1; t >= 0; --t)
+            hipLaunchKernelGGL(k_cw_rows<double>, grow, dim3(256), lds, s, L.nx, L.ny, L.nplanes,
+                               L.st64, L.plane_map, t, 0, 0, xo + (long long)(t + 1) * P, nul,
+                               G + (long long)t * PP, z + (long long)t * P, -1.0,
+                               xo + (long long)t * P, nullptr);
+    } else {
+        // w_0 = b_0, w_t = b_t - G_{t-1}^T w_{t-1}
+        hipLaunchKernelGGL(k_cw_in<TIO>, dim3((P + 255) / 256), dim3(256), 0, s, (long long)P, b, z);
+        for (int t = 1; t <= nt; ++t)
+            hipLaunchKernelGGL(k_cw_cols<TIO>, gcol, dim3(64 * CW_CSEG), lds, s, L.nx, L.ny,
+                               L.nplanes, L.st64, L.plane_map, t, 0, 0, z + (long long)(t - 1) * P,
+                               nul, G + (long long)(t - 1) * PP, b + (long long)t * P, -1.0,
+                               z + (long long)t * P);
+        // x_t = D'^{-T}_t (w_t - L_{t+1}^T x_{t+1})
+        for (int t = nt; t >= 0; --t)
+            hipLaunchKernelGGL(k_cw_cols<double>, gcol, dim3(64 * CW_CSEG), lds, s, L.nx, L.ny,
+                               L.nplanes, L.st64, L.plane_map, t, 1, 1, z + (long long)t * P,
+                               t < nt ? xo + (long long)(t + 1) * P : nul, Dinv + (long long)t * PP,
+                               (const double*)nullptr, 1.0, xo + (long long)t * P);
+    }
+    hipLaunchKernelGGL(k_cw_out<TIO>, dim3((unsigned)std::min<long long>((n + 255) / 256, 4096)),
+                       dim3(256), 0, s, n, xo, x);
+}
+
 size_t coarse_direct_lds(int P) { return (size_t)P * P * sizeof(double); }
 bool coarse_direct_fast(int P, int nt) {
     return P <= CD_FAST_P && (long long)(nt + 1) * P <= CD_FAST_NODES;
@@ -461,6 +791,13 @@ void launch_coarse_direct(hipStream_t s, const Level& L, int prec_io, int trans,
                           void* x, const double* Dinv, const double* G, const double* H,
                           const double* M, double* work) {
     const int P = (L.nx + 1) * (L.ny + 1);
+    if (!(H && M)) {
+        if (prec_io == 0)
+            cw_solve<double>(s, L, trans, (const double*)b, (double*)x, Dinv, G, work);
+        else
+            cw_solve<float>(s, L, trans, (const float*)b, (float*)x, Dinv, G, work);
+        return;
+    }
     if (H && M) {
         const size_t lds = (size_t)2 * P * (L.nt + 1) * sizeof(double);
         if (prec_io == 0)
@@ -471,15 +808,6 @@ void launch_coarse_direct(hipStream_t s, const Level& L, int prec_io, int trans,
                                Dinv, G, H, M, (const float*)b, (float*)x, trans);
         return;
     }
-    const size_t lds = (size_t)2 * P * sizeof(double);
-    if (prec_io == 0)
-        hipLaunchKernelGGL(k_coarse_direct<double>, dim3(1), dim3(CDT), lds, s, L.nx, L.ny, L.nt,
-                           L.nplanes, L.st64, L.plane_map, Dinv, G, (const double*)b, (double*)x,
-                           work, trans);
-    else
-        hipLaunchKernelGGL(k_coarse_direct<float>, dim3(1), dim3(CDT), lds, s, L.nx, L.ny, L.nt,
-                           L.nplanes, L.st64, L.plane_map, Dinv, G, (const float*)b, (float*)x,
-                           work, trans);
 }
 
 }  // namespace st

@@ -123,6 +123,7 @@ __device__ __forceinline__ unsigned uniform(unsigned v) { return __builtin_amdgc
 template <typename T> __device__ __forceinline__ void pin_value(T& v) { asm volatile("" : "+v"(v)); }
 
 constexpr int FA_TX = 64, FA_RY = 2, FA_TY = 4 * FA_RY;
+constexpr int FA_DEPTH_TCONST = 3;   // load distance (loop iterations), see k_fine_apply
 
 template <typename TIN, typename TOUT, typename TC, bool TRANS, bool TCONST, bool CUNI>
 __global__ __launch_bounds__(256) void k_fine_apply(
@@ -181,7 +182,15 @@ __global__ __launch_bounds__(256) void k_fine_apply(
         if (live) elive |= 1u << r;
         eo[r] = live ? (unsigned)(ej * nx + ei) * (unsigned)sizeof(TC) : 0u;
     }
-    TC pk[LE], pc[CUNI ? 1 : LE];
+    // Loads run DEPTH loop iterations ahead, in DEPTH register sets used by
+    // iterations in turn (the loop is unrolled so that every set is named
+    // statically).  Three iterations of cover for the FP32 time-constant
+    // kernels (measured on the large grid: 731 us with one, 617 with two,
+    // 605 with three, 601 with four); the time-varying and FP64 kernels
+    // hold more registers per set and keep one (more sets cost them more
+    // occupancy than they hide latency).
+    constexpr int DEPTH = (TCONST && sizeof(TC) == 4) ? FA_DEPTH_TCONST : 1;
+    TC pk[DEPTH][LE], pc[DEPTH][CUNI ? 1 : LE];
     // One resource per array for the launch (see buf_rsrc).
     const unsigned pin = (unsigned)(P * (long long)sizeof(TIN));
     const unsigned pout = (unsigned)(P * (long long)sizeof(TOUT));
@@ -195,34 +204,34 @@ __global__ __launch_bounds__(256) void k_fine_apply(
     // The loaded values are only touched when they are written to LDS one
     // iteration later (dead entries are zeroed there), so no wait for the
     // loads is placed before the arithmetic in between.
-    TIN lx[LW];
-    auto fetch_x = [&](int n) {
+    TIN lx[DEPTH][LW];
+    auto fetch_x = [&](int n, int q) {
         const unsigned so = uniform((unsigned)n * pin);
 #pragma unroll
-        for (int r = 0; r < LW; ++r) lx[r] = buf_ld<TIN>(rsx, xo[r], so);
+        for (int r = 0; r < LW; ++r) lx[q][r] = buf_ld<TIN>(rsx, xo[r], so);
     };
-    auto put_x = [&](int n) {
+    auto put_x = [&](int n, int q) {
         TC* d = xs[n % 3];
         const unsigned live = (mask_in && g.ic_dir && n == 0) ? 0u : xlive;
 #pragma unroll
         for (int r = 0; r < LW; ++r)
-            if (tid + 256 * r < NW) d[tid + 256 * r] = ((live >> r) & 1u) ? (TC)lx[r] : (TC)0;
+            if (tid + 256 * r < NW) d[tid + 256 * r] = ((live >> r) & 1u) ? (TC)lx[q][r] : (TC)0;
     };
-    auto fetch_c = [&](int s) {
+    auto fetch_c = [&](int s, int q) {
         const unsigned so = TCONST ? 0u : uniform((unsigned)s * pcoef);
 #pragma unroll
         for (int r = 0; r < LE; ++r) {
-            pk[r] = buf_ld<TC>(rsk, eo[r], so);
-            if (!CUNI) pc[r] = buf_ld<TC>(rsc, eo[r], so);
+            pk[q][r] = buf_ld<TC>(rsk, eo[r], so);
+            if (!CUNI) pc[q][r] = buf_ld<TC>(rsc, eo[r], so);
         }
     };
-    auto put_c = [&](int s) {
+    auto put_c = [&](int s, int q) {
 #pragma unroll
         for (int r = 0; r < LE; ++r)
             if (tid + 256 * r < NE) {
                 const bool v = (elive >> r) & 1u;
-                ks[s & 1][tid + 256 * r] = v ? pk[r] : (TC)0;
-                if (!CUNI) cs[s & 1][tid + 256 * r] = v ? pc[r] : (TC)0;
+                ks[s & 1][tid + 256 * r] = v ? pk[q][r] : (TC)0;
+                if (!CUNI) cs[s & 1][tid + 256 * r] = v ? pc[q][r] : (TC)0;
             }
     };
     // Capacity of the elements around this thread's nodes when it is uniform.
@@ -303,10 +312,10 @@ __global__ __launch_bounds__(256) void k_fine_apply(
     // zero-size buffer, and a row that is not a Dirichlet row reads x at an
     // offset past the end of the buffer -- both read as zero without a memory
     // access.
-    TOUT bv[RY];
-    TIN xd[RY];
+    TOUT bv[DEPTH][RY];
+    TIN xd[DEPTH][RY];
     constexpr unsigned OOB = 0x7FFFFFF0u;
-    auto fetch_bd = [&](int n) {
+    auto fetch_bd = [&](int n, int q) {
         const unsigned sob = uniform((unsigned)n * pout);
         // x of the Dirichlet rows: a resource over level n alone, so that
         // the rows that are not Dirichlet rows read past its end (zero, no
@@ -315,9 +324,9 @@ __global__ __launch_bounds__(256) void k_fine_apply(
         const bool ic = dir_rows && g.ic_dir && n == 0;
 #pragma unroll
         for (int m = 0; m < RY; ++m) {
-            bv[m] = buf_ld<TOUT>(rsb, oo[m] * (unsigned)sizeof(TOUT), sob);
+            bv[q][m] = buf_ld<TOUT>(rsb, oo[m] * (unsigned)sizeof(TOUT), sob);
             const bool dr = ic || (dir_rows && ((opatch >> m) & 1u));
-            xd[m] = buf_ld<TIN>(rxn, dr ? oo[m] * (unsigned)sizeof(TIN) : OOB, 0u);
+            xd[q][m] = buf_ld<TIN>(rxn, dr ? oo[m] * (unsigned)sizeof(TIN) : OOB, 0u);
         }
     };
     // jacobi: the output is scaled by the inverse diagonal of the operator,
@@ -328,11 +337,11 @@ __global__ __launch_bounds__(256) void k_fine_apply(
     // Sk, Sc = sums over the four elements around the node in a slab; a
     // Dirichlet row has the unit diagonal.
     // rdiag: the reciprocal of that diagonal.
-    auto emit = [&](int n, int m, TC v, TC rdiag) {
+    auto emit = [&](int n, int m, TC v, TC rdiag, int q) {
         if (!((own >> m) & 1u)) return;
         const bool dir = dir_rows && ((g.ic_dir && n == 0) || ((opatch >> m) & 1u));
-        TC val = dir ? (TC)xd[m] : v;
-        if (b) val = (TC)bv[m] - val;
+        TC val = dir ? (TC)xd[q][m] : v;
+        if (b) val = (TC)bv[q][m] - val;
         if (jacobi && !dir) val *= rdiag;
         buf_st<TOUT>((TOUT)(val * sc), rsy, oo[m] * (unsigned)sizeof(TOUT), uniform((unsigned)n * pout));
     };
@@ -341,13 +350,23 @@ __global__ __launch_bounds__(256) void k_fine_apply(
     const int sb = min(n1 - 1, nt - 1);
     TC ulo[RY + 2][3], uhi[RY + 2][3];
     TC Plo[RY], Rlo[RY], acc[RY], dacc[RY];
-    fetch_x(sa);
-    put_x(sa);
-    fetch_c(sa);
-    put_c(sa);
-    fetch_x(sa + 1);
-    if (!TCONST && sa + 1 <= sb) fetch_c(sa + 1);
-    fetch_bd(sa);
+    // Iteration s of the loop puts level s + 1 (and slab s + 1) into LDS from
+    // register set (s - sa) % DEPTH, then reloads that set with level (slab)
+    // s + 1 + DEPTH; it emits level s with b and Dirichlet x from the same
+    // set, loaded DEPTH iterations before, and then loads level s + DEPTH
+    // into it.  Indices past the chunk's end load the last level / slab again
+    // (cache hits that keep the loop free of branches around loads).
+    const int xl = sb + 1, cl = sb;
+    fetch_x(sa, 0);
+    fetch_c(sa, 0);
+    put_x(sa, 0);
+    put_c(sa, 0);
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) {
+        fetch_x(min(sa + 1 + d, xl), d);
+        if (!TCONST) fetch_c(min(sa + 1 + d, cl), d);
+        fetch_bd(min(sa + d, xl), d);
+    }
     __syncthreads();
     read_c(sa);
 #pragma unroll
@@ -375,14 +394,12 @@ __global__ __launch_bounds__(256) void k_fine_apply(
             pin_value(rfirst[m]);
         }
     }
-    for (int s = sa; s <= sb; ++s) {
-        put_x(s + 1);
-        if (!TCONST && s + 1 <= sb) put_c(s + 1);
+    auto step = [&](int s, int q) {
+        put_x(s + 1, q);
+        if (!TCONST && s + 1 <= sb) put_c(s + 1, q);
         __syncthreads();
-        // (past the end of the chunk the last level / slab is loaded again:
-        // a cache hit that keeps the loop free of branches around loads)
-        fetch_x(min(s + 2, sb + 1));
-        if (!TCONST) fetch_c(min(s + 2, sb));
+        fetch_x(min(s + 1 + DEPTH, xl), q);
+        if (!TCONST) fetch_c(min(s + 1 + DEPTH, cl), q);
         if (!TCONST) read_x(s, ulo);
         read_x(s + 1, uhi);
 #pragma unroll
@@ -400,27 +417,39 @@ __global__ __launch_bounds__(256) void k_fine_apply(
                 top += Sv - Rv;
             }
             if (TCONST) {
-                if (s >= n0) emit(s, m, acc[m] + bottom, s == 0 ? rfirst[m] : rmid[m]);
+                if (s >= n0) emit(s, m, acc[m] + bottom, s == 0 ? rfirst[m] : rmid[m], q);
                 Plo[m] = Qv;
                 Rlo[m] = Sv;
             } else {
                 const TC sk = ke[m][0] + ke[m][1] + ke[m + 1][0] + ke[m + 1][1];
                 const TC sc4 = ce[m][0] + ce[m][1] + ce[m + 1][0] + ce[m + 1][1];
                 const TC dlo = (TC)8 * kt * sk;
-                if (s >= n0) emit(s, m, acc[m] + bottom, jacobi ? recip(dacc[m] + dlo) : (TC)1);
+                if (s >= n0)
+                    emit(s, m, acc[m] + bottom, jacobi ? recip(dacc[m] + dlo) : (TC)1, q);
                 dacc[m] = dlo + (TC)4 * mw * sc4;
             }
             acc[m] = top;
         }
         if (!TCONST && s + 1 <= sb) read_c(s + 1);
-        // b of the next level: issued after this level's outputs, so
+        // b of level s + DEPTH: issued after this level's outputs, so
         // waiting for them never waits for the x / coefficient loads above
-        fetch_bd(s + 1);
+        fetch_bd(min(s + DEPTH, xl), q);
+    };
+    int s = sa;
+    for (; s + DEPTH - 1 <= sb; s += DEPTH) {
+#pragma unroll
+        for (int d = 0; d < DEPTH; ++d) step(s + d, d);
     }
+#pragma unroll
+    for (int d = 0; d < DEPTH - 1; ++d)
+        if (s + d <= sb) step(s + d, d);
     if (sb + 1 == nt && nt >= n0 && nt < n1) {
+        // level nt was emitted by no step; its b and x come from the set of
+        // the step after the last one
+        const int q = (sb + 1 - sa) % DEPTH;
 #pragma unroll
         for (int m = 0; m < RY; ++m)
-            emit(nt, m, acc[m], TCONST ? rlast[m] : (jacobi ? recip(dacc[m]) : (TC)1));
+            emit(nt, m, acc[m], TCONST ? rlast[m] : (jacobi ? recip(dacc[m]) : (TC)1), q);
     }
 }
 

@@ -70,6 +70,10 @@ struct st_handle {
     bool cd_factored = false;  // factors match the current coarse operator
     double *cd_Dinv = nullptr, *cd_G = nullptr, *cd_A = nullptr, *cd_colk = nullptr;
     double *cd_H = nullptr, *cd_M = nullptr;   // fast-solve products (small planes)
+    double *cd_W = nullptr, *cd_R = nullptr, *cd_panel = nullptr;   // wide factorisation
+    int* cd_idx = nullptr;
+    bool cd_wide = false;      // wide factorisation and solve (not the one-workgroup fast path)
+    int lds_max = 65536;       // bytes of LDS one workgroup may use on this device
     int* cd_perm = nullptr;
     int* cd_status = nullptr;
     double* partials = nullptr;
@@ -122,8 +126,12 @@ struct Carver {
 
 // Algorithm 1 (§3.2.1): lambda = D_eff dt / dx^2; below lambda_crit coarsen in
 // time, otherwise in space; when the chosen direction cannot be halved try the
-// other; stop at max_levels or once a level has <= max_coarse_nodes nodes.
-// With ST_FLAG_FULL_COARSENING every level halves all three counts instead.
+// other; stop at max_levels (N_l, 8 by default as in the paper's space-time
+// runs, §4) or once a level has <= max_coarse_nodes nodes.  Past max_levels
+// coarsening goes on only while the coarsest level is too large for its exact
+// factorisation (planes over CD_MAX_PLANE nodes, or factors over
+// CD_MAX_FACTOR_BYTES).  With ST_FLAG_FULL_COARSENING every level halves all
+// three counts instead.
 struct LevelDims {
     int nx, ny, nt, how;
     double dx, dt;
@@ -135,10 +143,16 @@ std::vector<LevelDims> build_hierarchy(const st_grid& g, const st_material& m, c
     const double D = std::sqrt(m.k_con * m.k_ins / (m.c_con * m.c_ins));
     const int maxl = std::max(1, std::min(o.max_levels, (int)ST_MAX_LEVELS));
     const bool full = (o.flags & ST_FLAG_FULL_COARSENING) != 0;
-    while ((int)L.size() < maxl) {
+    auto factorable = [](const LevelDims& c) {
+        const long long P = (long long)(c.nx + 1) * (c.ny + 1);
+        return P <= CD_MAX_PLANE &&
+               (double)P * P * 16.0 * (c.nt + 1) <= (double)CD_MAX_FACTOR_BYTES;
+    };
+    while ((int)L.size() < ST_MAX_LEVELS) {
         const LevelDims c = L.back();
         const long long nodes = (long long)(c.nx + 1) * (c.ny + 1) * (c.nt + 1);
         if (nodes <= o.max_coarse_nodes) break;
+        if ((int)L.size() >= maxl && (factorable(c) || o.max_levels < 2)) break;
         const bool can_s = c.nx % 2 == 0 && c.ny % 2 == 0 && c.nx >= 2 && c.ny >= 2;
         const bool can_t = c.nt % 2 == 0 && c.nt >= 2;
         if (full) {
@@ -245,11 +259,19 @@ size_t carve(st_handle* h, char* base) {
         if (h->cd_fit) {
             h->cd_Dinv = c.take<double>((size_t)P * P * (Lc.nt + 1));
             h->cd_G = c.take<double>((size_t)P * P * Lc.nt);
-            if (coarse_direct_fast((int)P, Lc.nt)) {
+            h->cd_wide = !coarse_direct_fast((int)P, Lc.nt);
+            if (!h->cd_wide) {
                 h->cd_H = c.take<double>((size_t)P * P * (Lc.nt + 1));
                 h->cd_M = c.take<double>((size_t)P * P * (Lc.nt + 1));
+                h->cd_A = coarse_direct_lds((int)P) > CD_LDS_MAX ? c.take<double>((size_t)P * P)
+                                                                 : nullptr;
+            } else {
+                h->cd_A = c.take<double>((size_t)P * P);
+                h->cd_W = c.take<double>((size_t)P * CW_PANEL_NB);
+                h->cd_R = c.take<double>((size_t)P * CW_PANEL_NB);
+                h->cd_panel = c.take<double>((size_t)P * CW_PANEL_NB);
+                h->cd_idx = c.take<int>((size_t)P);
             }
-            h->cd_A = coarse_direct_lds((int)P) > CD_LDS_MAX ? c.take<double>((size_t)P * P) : nullptr;
             h->cd_colk = c.take<double>((size_t)P);
             h->cd_perm = c.take<int>((size_t)P);
             h->cd_status = c.take<int>(1);
@@ -500,8 +522,22 @@ void smooth(st_handle* h, int l, int prec, int trans, const void* b, void* x, in
 st_status coarse_factor(st_handle* h) {
     const Level& L = h->lev[h->nlev - 1];
     hipStream_t s = h->stream;
-    launch_coarse_factor(s, L, h->cd_A, h->cd_Dinv, h->cd_G, h->cd_H, h->cd_M, h->cd_colk, h->cd_perm,
-                         h->cd_status);
+    if (h->cd_wide) {
+        launch_coarse_factor_wide(s, L, h->lds_max, h->cd_A, h->cd_Dinv, h->cd_G, h->cd_panel,
+                                  h->cd_colk, h->cd_W, h->cd_R, h->cd_perm, h->cd_idx, h->cd_status);
+        const hipError_t le = hipGetLastError();
+        if (le != hipSuccess) {
+            // a panel over 64 KB of LDS may be refused at launch: panels in global memory
+            if (h->lds_max <= 65536) return ST_ERR_HIP;
+            HIPCHK(hipStreamSynchronize(s));
+            h->lds_max = 65536;
+            launch_coarse_factor_wide(s, L, h->lds_max, h->cd_A, h->cd_Dinv, h->cd_G, h->cd_panel,
+                                      h->cd_colk, h->cd_W, h->cd_R, h->cd_perm, h->cd_idx,
+                                      h->cd_status);
+        }
+    } else
+        launch_coarse_factor(s, L, h->cd_A, h->cd_Dinv, h->cd_G, h->cd_H, h->cd_M, h->cd_colk,
+                             h->cd_perm, h->cd_status);
     int st = 0;
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(h->hbuf, h->cd_status, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -926,7 +962,7 @@ void st_opts_default(st_opts* o) {
     o->coarse_rtol = 1e-6;
     o->coarse_restart = 30;
     o->lambda_crit = 0.5;
-    o->max_levels = ST_MAX_LEVELS;
+    o->max_levels = 8;
     o->max_coarse_nodes = 4096;
     o->filter_r = 0.0;
     o->flags = 0;
@@ -1037,6 +1073,13 @@ st_status setup_impl(const st_grid* grid, const st_material* mat, const double* 
     h->ws = (char*)workspace_dev;
     h->ws_bytes = workspace_bytes;
     h->timing = (opts->flags & ST_FLAG_TIME_KERNELS) != 0;
+    {
+        int dev = 0, lds = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            lds > 0)
+            h->lds_max = lds;
+    }
     if (pinned_host) {
         if (hipHostMalloc((void**)&h->hbuf, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
             h->hbuf = nullptr;

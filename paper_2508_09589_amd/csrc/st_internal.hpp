@@ -200,12 +200,21 @@ void launch_sstep_coefficients(hipStream_t s, long long n, int prec, const void*
 
 // Exact coarsest-level solve by block-tridiagonal factorisation in time.
 constexpr int CD_MAX_PLANE = 2048;        // largest (nx + 1)(ny + 1) it is used for
+constexpr double CD_MAX_FACTOR_BYTES = 16.0 * (1ull << 30);   // largest factor storage
 constexpr size_t CD_LDS_MAX = 56 * 1024;  // Gauss-Jordan matrix in LDS up to this size
 constexpr int CD_FAST_P = 128;            // fast solve: plane size bound (8 | CD_FAST_P)
 constexpr int CD_FAST_NODES = 3072;       // fast solve: whole level in 2 x 24 KB of LDS
 bool coarse_direct_fits(int P);
 bool coarse_direct_fast(int P, int nt);
 size_t coarse_direct_lds(int P);
+// Wide factorisation (planes over CD_FAST_P or levels over CD_FAST_NODES):
+// A: P^2 working matrix, panel: P x CW_PANEL_NB (used when the panel does not
+// fit lds_max bytes of LDS), colk: P, W: P x CW_PANEL_NB, R: CW_PANEL_NB x P,
+// perm, idx: P ints.
+constexpr int CW_PANEL_NB = 16;
+void launch_coarse_factor_wide(hipStream_t s, const Level& L, int lds_max, double* A,
+                               double* Dinv, double* G, double* panel, double* colk, double* W,
+                               double* R, int* perm, int* idx, int* status);
 void launch_coarse_factor(hipStream_t s, const Level& L, double* Ag, double* Dinv, double* G,
                           double* H, double* M, double* colk, int* perm, int* status);
 void launch_coarse_direct(hipStream_t s, const Level& L, int prec_io, int trans, const void* b,

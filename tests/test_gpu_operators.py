@@ -298,13 +298,18 @@ def test_vcycle_matches_oracle(torch_cuda, tv, coarse, full):
 
 
 @pytest.mark.parametrize("nx,ny,nt,tv", [(8, 8, 16, True), (5, 7, 3, False), (12, 12, 4, True),
-                                         (1, 1, 1, False), (3, 2, 9, True)])
+                                         (1, 1, 1, False), (3, 2, 9, True), (16, 16, 8, False),
+                                         (17, 16, 5, True), (24, 20, 6, True), (32, 32, 3, False),
+                                         (8, 8, 40, True)])
 def test_direct_coarse_solve_is_exact(torch_cuda, nx, ny, nt, tv):
     """A one-level hierarchy makes the V-cycle the coarsest-level solve: the
     block-tridiagonal factorisation must reproduce the oracle's direct solve,
-    forward and transposed (12 x 12 runs the Gauss-Jordan step out of LDS and
-    its plane of 169 nodes is past the LDS-resident fast solve, which the
-    others take)."""
+    forward and transposed.  Planes of at most 128 nodes with at most 3072
+    nodes in all take the one-workgroup factorisation and the LDS-resident
+    solve; the others (169, 289, 306, 525 and 1089-node planes, and 81-node
+    planes over 41 levels) the wide factorisation (blocked Gauss-Jordan, the
+    panel in LDS up to 481 nodes, in global memory above; panels of 16
+    columns with a short last one) and the multi-workgroup sweeps."""
     from oracle.solve import solve_direct, solve_adjoint_direct
     c = Case(nx, ny, nt, tv=tv, seed=nx + 3 * ny + 7 * nt,
              patches=((0, 0.5 * ny / max(nx, ny), 0.2), (3, 0.4, 0.3)))

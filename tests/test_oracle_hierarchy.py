@@ -38,17 +38,34 @@ def test_printed_hierarchies(case):
 @pytest.mark.parametrize("n,nt,expect", [
     (32, 32, [(32, 32), (16, 32), (16, 16), (8, 16)]),
     (256, 256, [(256, 256), (128, 256), (64, 256), (32, 256), (32, 128), (32, 64), (16, 64),
-                (16, 32), (16, 16), (8, 16)]),
+                (16, 32)]),
     (512, 1024, [(512, 1024), (256, 1024), (128, 1024), (64, 1024), (64, 512), (64, 256),
-                 (32, 256), (32, 128), (32, 64), (16, 64), (16, 32), (16, 16), (8, 16)]),
+                 (32, 256), (32, 128)]),
     (128, 128, [(128, 128), (64, 128), (32, 128), (32, 64), (16, 64), (16, 32), (16, 16), (8, 16)]),
 ])
 def test_workload_hierarchies(n, nt, expect):
-    """Unit square, tau = 1, k in [1e-3, 1], C = 1: coarsen until at most 4096
-    nodes."""
+    """Unit square, tau = 1, k in [1e-3, 1], C = 1: Algorithm 1 with N_l = 8
+    levels (the paper's space-time runs), or fewer once a level has at most
+    4096 nodes."""
     lv = build_hierarchy(n, n, nt, 1.0 / n, 1.0 / nt, 1.0, 1e-3, 1.0, 1.0)
     assert [(L["nx"], L["nt"]) for L in lv] == expect
-    assert (lv[-1]["nx"] + 1) ** 2 * (lv[-1]["nt"] + 1) <= 4096
+    assert len(lv) == 8 or (lv[-1]["nx"] + 1) ** 2 * (lv[-1]["nt"] + 1) <= 4096
+    # without the level cap: down to at most 4096 nodes
+    deep = build_hierarchy(n, n, nt, 1.0 / n, 1.0 / nt, 1.0, 1e-3, 1.0, 1.0, max_levels=32)
+    assert [(L["nx"], L["nt"]) for L in deep[:len(lv)]] == expect
+    assert (deep[-1]["nx"] + 1) ** 2 * (deep[-1]["nt"] + 1) <= 4096
+
+
+def test_level_cap_yields_to_the_coarsest_factorisation():
+    """Past N_l coarsening goes on while the coarsest planes are over the
+    exact factorisation's limit (2048 nodes): 512^2 x 4096 has 64^2-element
+    planes (4225 nodes) on its eighth level and takes a ninth (32^2)."""
+    lv = build_hierarchy(512, 512, 4096, 1 / 512, 1 / 4096, 1.0, 1e-3, 1.0, 1.0)
+    assert (lv[7]["nx"] + 1) * (lv[7]["ny"] + 1) > 2048
+    assert len(lv) == 9 and (lv[-1]["nx"], lv[-1]["nt"]) == (32, 256)
+    # the level count alone when the planes fit
+    lv = build_hierarchy(512, 512, 1024, 1 / 512, 1 / 1024, 1.0, 1e-3, 1.0, 1.0)
+    assert len(lv) == 8 and (lv[-1]["nx"] + 1) ** 2 <= 2048
 
 
 def test_tie_goes_to_space():
