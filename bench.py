@@ -35,7 +35,7 @@ def log(msg):
 
 
 def workload_problem(name, precision, time_kernels, bf16_from_level=0, max_it=1000,
-                     smoother="gmres", restart=None, coarse="direct"):
+                     smoother="gmres", restart=None, coarse="direct", max_levels=None):
     import torch
     from paper_2508_09589_amd import Problem
     from paper_2508_09589_amd.inputs import WORKLOADS, workload_density
@@ -44,10 +44,11 @@ def workload_problem(name, precision, time_kernels, bf16_from_level=0, max_it=10
     if restart is None:
         restart = 20 if name == "large" else 30
     t0 = time.perf_counter()
+    extra = {} if max_levels is None else dict(max_levels=max_levels)
     p = Problem(w["nx"], w["ny"], w["nt"], torch.tensor(rho), precision=precision, restart=restart,
                 rtol=1e-8, time_kernels=time_kernels, bf16_from_level=bf16_from_level,
                 smoother=smoother, coarse=coarse,
-                max_it=max_it)
+                max_it=max_it, **extra)
     torch.cuda.synchronize()
     log(f"{name} {precision}: setup {time.perf_counter() - t0:.2f} s, {p.n_nodes} nodes, "
         f"levels {p.hierarchy()[0]}")
@@ -116,10 +117,11 @@ def summarize_counters(fetch_dir, write_dir, workload, precision, out):
     fw = COPY_KIB / (sum(float(r["Counter_Value"]) for r in cw) / len(cw))
     fa, wa = sum(fk) / len(fk), sum(wk) / len(wk)
     total = (fa * ff + wa * fw) * 1024.0
-    cmd = ("cd /tmp && export TMPDIR=/tmp && timeout -s KILL 200 rocprofv3 --pmc {c} "
+    cmd = ("cd /tmp && export TMPDIR=/tmp && timeout -s KILL 240 rocprofv3 --pmc {c} "
            "--kernel-include-regex 'k_fine_apply|copy' --output-format csv -d <dir> -o run -- "
            f"python -u /root/repo/bench.py --workload {workload} --precision {precision} "
-           "--steps 1 --warmup 1 --no-cpu-baseline --copy-calibration")
+           "--steps 1 --warmup 1 --no-cpu-baseline --no-compare-fp64 --max-levels 32 "
+           "--copy-calibration")
     text = f"""# HBM traffic of the fine-level apply, {workload} workload, {precision} precision
 
 Two rocprofv3 counter runs of the same command, one counter each:
@@ -130,6 +132,10 @@ Two rocprofv3 counter runs of the same command, one counter each:
 then `python bench.py --summarize-counters <fetch dir> <write dir> --workload {workload} --precision {precision}`.
 The counters are averaged over the kernel's dispatches and scaled by what they read for
 the 1 GiB device copies at the end of the run (1 GiB read and 1 GiB written each).
+The counter runs coarsen down to at most 4096 nodes (`--max-levels 32`): rocprofv3's
+counter collection ends the process in the launch of the coarsest-level factorisation's
+panel kernel (148 KB of LDS) that the default 8-level hierarchy uses; the fine-level
+apply, whose traffic this is, is the same kernel with the same launch shape either way.
 
 kernel: {kern} ... ({len(fk)} / {len(wk)} dispatches)
 source_sha256: {_kernel_sha()}
@@ -224,7 +230,7 @@ def run(args):
 
     p, t_setup, restart = workload_problem(args.workload, args.precision, True,
                                            args.bf16_from_level, args.max_it, args.smoother,
-                                           args.restart, args.coarse)
+                                           args.restart, args.coarse, args.max_levels)
     n_nodes = p.n_nodes
     # The first warm-up solve times every kernel class (one event pair per
     # launch); the others run untimed.
@@ -276,7 +282,7 @@ def run(args):
                    "true_rel_res": last["true_rel_res"], "setup_s": t_setup,
                    "converged": last["true_rel_res"] <= 1e-8,
                    "bf16_from_level": args.bf16_from_level, "smoother": args.smoother,
-                   "coarse": args.coarse},
+                   "coarse": args.coarse, "hierarchy": [list(d) for d in p.hierarchy()[0]]},
         "roofline": {"bound": "hbm", "kernel_class": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": recorded_traffic(args.workload, args.precision),
@@ -313,7 +319,7 @@ def fp64_compare(args, T_mixed, n_nodes, mixed_value):
     (one on the large grid, two elsewhere, after one warm-up)."""
     import torch
     q, ts, _ = workload_problem(args.workload, "fp64", False, 0, args.max_it, args.smoother,
-                                args.restart, args.coarse)
+                                args.restart, args.coarse, args.max_levels)
     timed = 1 if args.workload == "large" else 2
     if args.workload != "large":
         q.solve(allow_not_converged=True)
@@ -570,6 +576,8 @@ def main():
                     help="FGMRES restart length (default 30; 20 for the large workload)")
     ap.add_argument("--coarse", default="direct", choices=["direct", "gmres"],
                     help="coarsest-level solve: exact, or the paper's Jacobi-GMRES")
+    ap.add_argument("--max-levels", type=int, default=None,
+                    help="multigrid levels N_l (default: the library's, 8)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare-fp64", action="store_true",
                     help="serving workload: also run the request stream in plain FP64")
