@@ -270,7 +270,9 @@ class Server:
                 lam, ainfo = prob.adjoint(f, allow_not_converged=True)
                 out["grad"] = prob.sensitivity(T, lam)
                 out["adjoint_iterations"] = ainfo.iterations
+                out["adjoint_true_rel_res"] = ainfo.true_rel_res
                 out["J"] = prob.objective(T)
+                out["lam"] = lam if self.keep_outputs else None
             out["T"] = T if self.keep_outputs else None
             if stream is not None:
                 stream.synchronize()

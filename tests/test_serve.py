@@ -41,7 +41,7 @@ class MockProblem:
 
     def adjoint(self, f, allow_not_converged=False):
         time.sleep(0.01)
-        return np.zeros(1), type("I", (), dict(iterations=4))()
+        return np.zeros(1), type("I", (), dict(iterations=4, true_rel_res=1e-9))()
 
     def sensitivity(self, T, lam):
         return np.zeros(1)
@@ -210,3 +210,49 @@ def test_alone_equals_in_the_mix(require_gpu):
         if "grad" in alone[i]:
             assert torch.equal(alone[i]["grad"], mix[i]["grad"]), i
         assert alone[i]["true_rel_res"] <= 1e-8
+
+
+@pytest.mark.gpu
+def test_served_requests_against_the_oracle(require_gpu):
+    """16 requests drawn at random (default_rng(5)) from the serving workload's
+    256 (square grids of 32..256 elements, 32..256 slabs, time-varying
+    densities, half with a gradient), served concurrently in 4 slots at the
+    benchmark's settings: the oracle recomputes, with its own element
+    matrices, the residual of every served state and adjoint over the whole
+    field (<= 1e-8 (1 + 1e-6) of the right-hand side) and the sensitivities
+    from the served state and adjoint (1e-12)."""
+    from oracle.assemble import Material, load_vector_uniform, simp
+    from oracle.design import element_sensitivity, reduce_to_design
+    from oracle.grid import Grid, dirichlet_mask
+    from oracle.residual import residual_by_planes
+    from paper_2508_09589_amd.inputs import serving_requests
+    specs = serving_requests(256)
+    pick = sorted(np.random.default_rng(5).choice(256, 16, replace=False))
+    reqs = [Request(specs[i]["id"], specs[i]["n"], specs[i]["nt"],
+                    request_density(specs[i]["n"], specs[i]["nt"], specs[i]["seed"]),
+                    adjoint=specs[i]["adjoint"], precision="mixed") for i in pick]
+    srv = Server(64 << 30, slots=4)
+    futs = [srv.submit(r) for r in reqs]
+    outs = {f.result(timeout=300)["id"]: f.result() for f in futs}
+    srv.close()
+    mat = Material(k_ins=1e-3, k_con=1.0, p_k=3.0, c_ins=1.0, c_con=1.0, p_c=1.0)
+    assert sum(r.adjoint for r in reqs) >= 4
+    for r in reqs:
+        o = outs[r.id]
+        g = Grid(r.n, r.n, r.nt, 1.0 / r.n, 1.0 / r.nt)
+        k, C, dk, dC = simp(r.rho, mat)
+        mask = dirichlet_mask(g, [(0, 0.5, 0.05)])
+        fm = load_vector_uniform(g, 1.0)
+        fm[mask.ravel()] = 0.0
+        nf = np.linalg.norm(fm)
+        T = o["T"].cpu().numpy().ravel()
+        rn, _ = residual_by_planes(g, k, C, mask, T, fm)
+        print(f"request {r.id} {r.n}^2 x {r.nt}: state res {rn / nf:.3e}", flush=True)
+        assert rn <= 1e-8 * (1 + 1e-6) * nf, (r.id, rn / nf)
+        if r.adjoint:
+            lam = o["lam"].cpu().numpy().ravel()
+            ra, _ = residual_by_planes(g, k, C, mask, lam, fm, transpose=True)
+            assert ra <= 1e-8 * (1 + 1e-6) * nf, (r.id, ra / nf)
+            ge = reduce_to_design(element_sensitivity(g, T, lam, dk, dC), r.rho.shape)
+            gg = o["grad"].cpu().numpy()
+            assert np.linalg.norm(gg - ge) <= 1e-12 * np.linalg.norm(ge), r.id
