@@ -552,11 +552,67 @@ __global__ void k_cw_gmat(int nx, int ny, int nplanes, const double* __restrict_
     }
 }
 
+// H_t = D'_t^{-1} L_t (t >= 1; L_t: the dn = -1 entries of level t, towards
+// level t - 1) and MT_t = L_{t+1} D'_t^{-1} (t < nt), so that every step of a
+// sweep is a dense product alone:
+//     z_t = D'^{-1}_t b_t - H_t z_{t-1},    x_t = D'^{-T}_t w_t - MT_t^T x_{t+1}.
+__global__ void k_cw_hmat(int nx, int ny, int nplanes, const double* __restrict__ st,
+                          const int* __restrict__ pmap, int t, const double* __restrict__ Di,
+                          double* __restrict__ Hs) {
+    const int row = nx + 1, P = row * (ny + 1);
+    const long long PP = (long long)P * P;
+    const long long DS = (long long)P * nplanes;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < PP;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int a = (int)(e / P), c = (int)(e - (long long)a * P);
+        const int jc = c / row, ic = c - jc * row;
+        double v = 0.0;
+        for (int qj = -1; qj <= 1; ++qj) {
+            const int jb = jc + qj;
+            if (jb < 0 || jb > ny) continue;
+            for (int qi = -1; qi <= 1; ++qi) {
+                const int ib = ic + qi;
+                if (ib < 0 || ib > nx) continue;
+                const int b = jb * row + ib;
+                const double l = cd_entry(st, pmap, DS, P, t, b, -1, -qj, -qi);
+                if (l != 0.0) v += Di[(long long)a * P + b] * l;
+            }
+        }
+        Hs[e] = v;
+    }
+}
+__global__ void k_cw_mtmat(int nx, int ny, int nplanes, const double* __restrict__ st,
+                           const int* __restrict__ pmap, int t, const double* __restrict__ Di,
+                           double* __restrict__ MTs) {
+    const int row = nx + 1, P = row * (ny + 1);
+    const long long PP = (long long)P * P;
+    const long long DS = (long long)P * nplanes;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < PP;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int a = (int)(e / P), c = (int)(e - (long long)a * P);
+        const int ja = a / row, ia = a - ja * row;
+        double v = 0.0;
+        for (int qj = -1; qj <= 1; ++qj) {
+            const int jb = ja + qj;
+            if (jb < 0 || jb > ny) continue;
+            for (int qi = -1; qi <= 1; ++qi) {
+                const int ib = ia + qi;
+                if (ib < 0 || ib > nx) continue;
+                const int b = jb * row + ib;
+                const double l = cd_entry(st, pmap, DS, P, t + 1, a, -1, qj, qi);
+                if (l != 0.0) v += l * Di[(long long)b * P + c];
+            }
+        }
+        MTs[e] = v;
+    }
+}
+
 size_t cw_panel_lds(int P) { return (size_t)P * (CW_NB + 1) * sizeof(double); }
 
 void launch_coarse_factor_wide(hipStream_t s, const Level& L, int lds_max, double* A,
-                               double* Dinv, double* G, double* panel, double* colk, double* W,
-                               double* R, int* perm, int* idx, int* status) {
+                               double* Dinv, double* G, double* H, double* MT, double* panel,
+                               double* colk, double* W, double* R, int* perm, int* idx,
+                               int* status) {
     const int P = (L.nx + 1) * (L.ny + 1);
     const long long PP = (long long)P * P;
     const unsigned eb = (unsigned)std::min<long long>((PP + 255) / 256, 65535);
@@ -582,118 +638,74 @@ void launch_coarse_factor_wide(hipStream_t s, const Level& L, int lds_max, doubl
         hipLaunchKernelGGL(k_cw_colperm, dim3(1), dim3(1), 0, s, P, perm, idx);
         double* Di = Dinv + (long long)t * PP;
         hipLaunchKernelGGL(k_cw_gather, dim3(eb), dim3(256), 0, s, P, A, idx, Di);
-        if (t < L.nt)
+        if (t < L.nt) {
             hipLaunchKernelGGL(k_cw_gmat, dim3(eb), dim3(256), 0, s, L.nx, L.ny, L.nplanes, L.st64,
                                L.plane_map, t, Di, G + (long long)t * PP);
+            hipLaunchKernelGGL(k_cw_mtmat, dim3(eb), dim3(256), 0, s, L.nx, L.ny, L.nplanes,
+                               L.st64, L.plane_map, t, Di, MT + (long long)t * PP);
+        }
+        if (t > 0)
+            hipLaunchKernelGGL(k_cw_hmat, dim3(eb), dim3(256), 0, s, L.nx, L.ny, L.nplanes, L.st64,
+                               L.plane_map, t, Di, H + (long long)t * PP);
     }
 }
 
 // Wide solve.  z: forward-sweep vectors, xo: solution, both [nt + 1][P]
-// FP64.  Dense products: row form out[r] = sum_c M[r][c] v[c] (one wave per
-// row, lanes across columns) or column form out[r] = sum_c M[c][r] v[c]
-// (lanes across outputs, the workgroup's waves across segments of c).
-constexpr int CW_ROWS = 1;      // rows per wave in the row form
+// FP64.  Every step is one launch of up to two dense products, in row form
+// out[r] = base[r] + s1 (M1 v1)[r] + s2 (M2 v2)[r] (one wave per row, lanes
+// across columns, four partial sums in flight) or column form with M1^T, M2^T
+// (lanes across outputs, the workgroup's waves across segments of c).  The
+// vectors are read from global memory (L2).
 constexpr int CW_CSEG = 16;     // waves (column segments) per workgroup in the column form
 
-// Coupling of row a of level t to level t + dn of y (forward: row a's own
-// entries; transposed: the entries of the rows of level t + dn that point at a).
-__device__ __forceinline__ double cw_couple(int nx, int ny, const double* st, const int* pmap,
-                                            long long DS, int P, int t, int a, int dn,
-                                            const double* y, int transposed) {
-    const int row = nx + 1;
-    const int ja = a / row, ia = a - ja * row;
-    const int tn = t + dn;
-    double acc = 0.0;
-    for (int qj = -1; qj <= 1; ++qj) {
-        const int jb = ja + qj;
-        if (jb < 0 || jb > ny) continue;
-        for (int qi = -1; qi <= 1; ++qi) {
-            const int ib = ia + qi;
-            if (ib < 0 || ib > nx) continue;
-            const int bb = jb * row + ib;
-            const double c = transposed ? cd_entry(st, pmap, DS, P, tn, bb, -dn, -qj, -qi)
-                                        : cd_entry(st, pmap, DS, P, t, a, dn, qj, qi);
-            acc += c * y[bb];
-        }
-    }
-    return acc;
-}
-
-// Row form: out[r] = base[r] + sgn * sum_c M[r][c] v[c], with v = vb - (coupling of
-// level t to level t + dn of y) formed in LDS by every workgroup (y null: v = vb).
-template <typename TB>
-__global__ __launch_bounds__(256) void k_cw_rows(int nx, int ny, int nplanes,
-                                                 const double* __restrict__ st,
-                                                 const int* __restrict__ pmap, int t, int dn,
-                                                 int couple_trans, const TB* __restrict__ vb,
-                                                 const double* __restrict__ y,
-                                                 const double* __restrict__ M,
-                                                 const double* __restrict__ base, double sgn,
-                                                 double* __restrict__ out, double* __restrict__ out2) {
-    extern __shared__ double v[];
-    const int P = (nx + 1) * (ny + 1);
-    const long long DS = (long long)P * nplanes;
-    for (int a = threadIdx.x; a < P; a += 256) {
-        double w = (double)vb[a];
-        if (y) w -= cw_couple(nx, ny, st, pmap, DS, P, t, a, dn, y, couple_trans);
-        v[a] = w;
-    }
-    __syncthreads();
+template <typename TV1, typename TB>
+__global__ __launch_bounds__(256) void k_cw_rows(int P, const double* __restrict__ M1,
+                                                 const TV1* __restrict__ v1, double s1,
+                                                 const double* __restrict__ M2,
+                                                 const double* __restrict__ v2, double s2,
+                                                 const TB* __restrict__ base,
+                                                 double* __restrict__ out,
+                                                 double* __restrict__ out2) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r0 = (blockIdx.x * 4 + wave) * CW_ROWS;
-#pragma unroll
-    for (int q = 0; q < CW_ROWS; ++q) {
-        const int r = r0 + q;
-        if (r >= P) break;
-        // four independent partial sums keep several loads of the row in flight
+    const int r = blockIdx.x * 4 + wave;
+    if (r >= P) return;
+    auto rowdot = [&](const double* Mr, auto v) -> double {
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        const double* Mr = M + (long long)r * P;
         int c = lane;
         for (; c + 192 < P; c += 256) {
-            a0 += Mr[c] * v[c];
-            a1 += Mr[c + 64] * v[c + 64];
-            a2 += Mr[c + 128] * v[c + 128];
-            a3 += Mr[c + 192] * v[c + 192];
+            a0 += Mr[c] * (double)v[c];
+            a1 += Mr[c + 64] * (double)v[c + 64];
+            a2 += Mr[c + 128] * (double)v[c + 128];
+            a3 += Mr[c + 192] * (double)v[c + 192];
         }
-        for (; c < P; c += 64) a0 += Mr[c] * v[c];
-        double acc = (a0 + a1) + (a2 + a3);
+        for (; c < P; c += 64) a0 += Mr[c] * (double)v[c];
+        return (a0 + a1) + (a2 + a3);
+    };
+    double acc = s1 * rowdot(M1 + (long long)r * P, v1);
+    if (M2) acc += s2 * rowdot(M2 + (long long)r * P, v2);
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-        if (lane == 0) {
-            const double val = base ? base[r] + sgn * acc : sgn * acc;
-            out[r] = val;
-            if (out2) out2[r] = val;
-        }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) {
+        const double val = base ? (double)base[r] + acc : acc;
+        out[r] = val;
+        if (out2) out2[r] = val;
     }
 }
 
-// Column form: out[r] = base[r] + sgn * sum_c M[c][r] v[c], v as in the row form.
 template <typename TB>
-__global__ __launch_bounds__(64 * CW_CSEG) void k_cw_cols(int nx, int ny, int nplanes,
-                                                          const double* __restrict__ st,
-                                                          const int* __restrict__ pmap, int t,
-                                                          int dn, int couple_trans,
-                                                          const double* __restrict__ vb,
-                                                          const double* __restrict__ y,
-                                                          const double* __restrict__ M,
-                                                          const TB* __restrict__ base, double sgn,
+__global__ __launch_bounds__(64 * CW_CSEG) void k_cw_cols(int P, const double* __restrict__ M1,
+                                                          const double* __restrict__ v1, double s1,
+                                                          const double* __restrict__ M2,
+                                                          const double* __restrict__ v2, double s2,
+                                                          const TB* __restrict__ base,
                                                           double* __restrict__ out) {
-    extern __shared__ double v[];
     __shared__ double part[CW_CSEG][64];
-    const int P = (nx + 1) * (ny + 1);
-    const long long DS = (long long)P * nplanes;
-    for (int a = threadIdx.x; a < P; a += 64 * CW_CSEG) {
-        double w = vb[a];
-        if (y) w -= cw_couple(nx, ny, st, pmap, DS, P, t, a, dn, y, couple_trans);
-        v[a] = w;
-    }
-    __syncthreads();
     const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
     const int r = blockIdx.x * 64 + lane;
     const int cs = (P + CW_CSEG - 1) / CW_CSEG;
     const int c0 = seg * cs, c1 = min(P, c0 + cs);
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    if (r < P) {
+    auto coldot = [&](const double* M, const double* v) -> double {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         int c = c0;
         for (; c + 3 < c1; c += 4) {
             a0 += M[(long long)c * P + r] * v[c];
@@ -702,13 +714,19 @@ __global__ __launch_bounds__(64 * CW_CSEG) void k_cw_cols(int nx, int ny, int np
             a3 += M[(long long)(c + 3) * P + r] * v[c + 3];
         }
         for (; c < c1; ++c) a0 += M[(long long)c * P + r] * v[c];
+        return (a0 + a1) + (a2 + a3);
+    };
+    double acc = 0.0;
+    if (r < P) {
+        acc = s1 * coldot(M1, v1);
+        if (M2) acc += s2 * coldot(M2, v2);
     }
-    part[seg][lane] = (a0 + a1) + (a2 + a3);
+    part[seg][lane] = acc;
     __syncthreads();
     if (seg == 0 && r < P) {
         double sum = 0.0;
         for (int q = 0; q < CW_CSEG; ++q) sum += part[q][lane];
-        out[r] = base ? (double)base[r] + sgn * sum : sgn * sum;
+        out[r] = base ? (double)base[r] + sum : sum;
     }
 }
 
@@ -728,42 +746,41 @@ __global__ void k_cw_out(long long n, const double* __restrict__ xo, TIO* __rest
 
 template <typename TIO>
 static void cw_solve(hipStream_t s, const Level& L, int trans, const TIO* b, TIO* x,
-                     const double* Dinv, const double* G, double* work) {
+                     const double* Dinv, const double* G, const double* H, const double* MT,
+                     double* work) {
     const int P = (L.nx + 1) * (L.ny + 1), nt = L.nt;
     const long long PP = (long long)P * P, n = (long long)P * (nt + 1);
     double* z = work;
     double* xo = work + n;
-    const size_t lds = (size_t)P * sizeof(double);
-    const dim3 grow((P + 4 * CW_ROWS - 1) / (4 * CW_ROWS)), gcol((P + 63) / 64);
+    const dim3 grow((P + 3) / 4), gcol((P + 63) / 64);
     const double* nul = nullptr;
     if (!trans) {
-        // z_t = D'^{-1}_t (b_t - L_t z_{t-1}); x_nt = z_nt
+        // z_t = D'^{-1}_t b_t - H_t z_{t-1};  x_nt = z_nt
         for (int t = 0; t <= nt; ++t)
-            hipLaunchKernelGGL(k_cw_rows<TIO>, grow, dim3(256), lds, s, L.nx, L.ny, L.nplanes,
-                               L.st64, L.plane_map, t, -1, 0, b + (long long)t * P,
-                               t > 0 ? z + (long long)(t - 1) * P : nul, Dinv + (long long)t * PP,
-                               nul, 1.0, z + (long long)t * P,
-                               t == nt ? xo + (long long)t * P : nullptr);
+            hipLaunchKernelGGL((k_cw_rows<TIO, double>), grow, dim3(256), 0, s, P,
+                               Dinv + (long long)t * PP, b + (long long)t * P, 1.0,
+                               t > 0 ? H + (long long)t * PP : nul,
+                               t > 0 ? z + (long long)(t - 1) * P : nul, -1.0, nul,
+                               z + (long long)t * P, t == nt ? xo + (long long)t * P : nullptr);
         // x_t = z_t - G_t x_{t+1}
         for (int t = nt - 1; t >= 0; --t)
-            hipLaunchKernelGGL(k_cw_rows<double>, grow, dim3(256), lds, s, L.nx, L.ny, L.nplanes,
-                               L.st64, L.plane_map, t, 0, 0, xo + (long long)(t + 1) * P, nul,
-                               G + (long long)t * PP, z + (long long)t * P, -1.0,
-                               xo + (long long)t * P, nullptr);
+            hipLaunchKernelGGL((k_cw_rows<double, double>), grow, dim3(256), 0, s, P,
+                               G + (long long)t * PP, xo + (long long)(t + 1) * P, -1.0, nul, nul,
+                               0.0, z + (long long)t * P, xo + (long long)t * P, nullptr);
     } else {
         // w_0 = b_0, w_t = b_t - G_{t-1}^T w_{t-1}
         hipLaunchKernelGGL(k_cw_in<TIO>, dim3((P + 255) / 256), dim3(256), 0, s, (long long)P, b, z);
         for (int t = 1; t <= nt; ++t)
-            hipLaunchKernelGGL(k_cw_cols<TIO>, gcol, dim3(64 * CW_CSEG), lds, s, L.nx, L.ny,
-                               L.nplanes, L.st64, L.plane_map, t, 0, 0, z + (long long)(t - 1) * P,
-                               nul, G + (long long)(t - 1) * PP, b + (long long)t * P, -1.0,
-                               z + (long long)t * P);
-        // x_t = D'^{-T}_t (w_t - L_{t+1}^T x_{t+1})
+            hipLaunchKernelGGL(k_cw_cols<TIO>, gcol, dim3(64 * CW_CSEG), 0, s, P,
+                               G + (long long)(t - 1) * PP, z + (long long)(t - 1) * P, -1.0, nul,
+                               nul, 0.0, b + (long long)t * P, z + (long long)t * P);
+        // x_t = D'^{-T}_t w_t - MT_t^T x_{t+1}
         for (int t = nt; t >= 0; --t)
-            hipLaunchKernelGGL(k_cw_cols<double>, gcol, dim3(64 * CW_CSEG), lds, s, L.nx, L.ny,
-                               L.nplanes, L.st64, L.plane_map, t, 1, 1, z + (long long)t * P,
-                               t < nt ? xo + (long long)(t + 1) * P : nul, Dinv + (long long)t * PP,
-                               (const double*)nullptr, 1.0, xo + (long long)t * P);
+            hipLaunchKernelGGL(k_cw_cols<double>, gcol, dim3(64 * CW_CSEG), 0, s, P,
+                               Dinv + (long long)t * PP, z + (long long)t * P, 1.0,
+                               t < nt ? MT + (long long)t * PP : nul,
+                               t < nt ? xo + (long long)(t + 1) * P : nul, -1.0, nul,
+                               xo + (long long)t * P);
     }
     hipLaunchKernelGGL(k_cw_out<TIO>, dim3((unsigned)std::min<long long>((n + 255) / 256, 4096)),
                        dim3(256), 0, s, n, xo, x);
@@ -789,13 +806,13 @@ void launch_coarse_factor(hipStream_t s, const Level& L, double* Ag, double* Din
 
 void launch_coarse_direct(hipStream_t s, const Level& L, int prec_io, int trans, const void* b,
                           void* x, const double* Dinv, const double* G, const double* H,
-                          const double* M, double* work) {
+                          const double* M, double* work, int wide) {
     const int P = (L.nx + 1) * (L.ny + 1);
-    if (!(H && M)) {
+    if (wide) {
         if (prec_io == 0)
-            cw_solve<double>(s, L, trans, (const double*)b, (double*)x, Dinv, G, work);
+            cw_solve<double>(s, L, trans, (const double*)b, (double*)x, Dinv, G, H, M, work);
         else
-            cw_solve<float>(s, L, trans, (const float*)b, (float*)x, Dinv, G, work);
+            cw_solve<float>(s, L, trans, (const float*)b, (float*)x, Dinv, G, H, M, work);
         return;
     }
     if (H && M) {

@@ -266,6 +266,8 @@ size_t carve(st_handle* h, char* base) {
                 h->cd_A = coarse_direct_lds((int)P) > CD_LDS_MAX ? c.take<double>((size_t)P * P)
                                                                  : nullptr;
             } else {
+                h->cd_H = c.take<double>((size_t)P * P * (Lc.nt + 1));
+                h->cd_M = c.take<double>((size_t)P * P * std::max(Lc.nt, 1));
                 h->cd_A = c.take<double>((size_t)P * P);
                 h->cd_W = c.take<double>((size_t)P * CW_PANEL_NB);
                 h->cd_R = c.take<double>((size_t)P * CW_PANEL_NB);
@@ -523,17 +525,18 @@ st_status coarse_factor(st_handle* h) {
     const Level& L = h->lev[h->nlev - 1];
     hipStream_t s = h->stream;
     if (h->cd_wide) {
-        launch_coarse_factor_wide(s, L, h->lds_max, h->cd_A, h->cd_Dinv, h->cd_G, h->cd_panel,
-                                  h->cd_colk, h->cd_W, h->cd_R, h->cd_perm, h->cd_idx, h->cd_status);
+        launch_coarse_factor_wide(s, L, h->lds_max, h->cd_A, h->cd_Dinv, h->cd_G, h->cd_H, h->cd_M,
+                                  h->cd_panel, h->cd_colk, h->cd_W, h->cd_R, h->cd_perm, h->cd_idx,
+                                  h->cd_status);
         const hipError_t le = hipGetLastError();
         if (le != hipSuccess) {
             // a panel over 64 KB of LDS may be refused at launch: panels in global memory
             if (h->lds_max <= 65536) return ST_ERR_HIP;
             HIPCHK(hipStreamSynchronize(s));
             h->lds_max = 65536;
-            launch_coarse_factor_wide(s, L, h->lds_max, h->cd_A, h->cd_Dinv, h->cd_G, h->cd_panel,
-                                      h->cd_colk, h->cd_W, h->cd_R, h->cd_perm, h->cd_idx,
-                                      h->cd_status);
+            launch_coarse_factor_wide(s, L, h->lds_max, h->cd_A, h->cd_Dinv, h->cd_G, h->cd_H,
+                                      h->cd_M, h->cd_panel, h->cd_colk, h->cd_W, h->cd_R, h->cd_perm,
+                                      h->cd_idx, h->cd_status);
         }
     } else
         launch_coarse_factor(s, L, h->cd_A, h->cd_Dinv, h->cd_G, h->cd_H, h->cd_M, h->cd_colk,
@@ -562,7 +565,7 @@ void vcycle(st_handle* h, int l, const void* b, void* x, int trans) {
         Timed t(h, KC_COARSE, 0);
         if (!(o.flags & ST_FLAG_COARSE_GMRES) && h->cd_ok)
             launch_coarse_direct(s, L, p, trans, b, x, h->cd_Dinv, h->cd_G, h->cd_H, h->cd_M,
-                                 h->coarseWork);
+                                 h->coarseWork, h->cd_wide ? 1 : 0);
         else
             launch_coarse_solve(s, L, p, trans, b, x, h->coarseV, h->coarseWork, o.coarse_max_it,
                                 o.coarse_restart, o.coarse_rtol, 1);

@@ -213,13 +213,16 @@ size_t coarse_direct_lds(int P);
 // perm, idx: P ints.
 constexpr int CW_PANEL_NB = 16;
 void launch_coarse_factor_wide(hipStream_t s, const Level& L, int lds_max, double* A,
-                               double* Dinv, double* G, double* panel, double* colk, double* W,
-                               double* R, int* perm, int* idx, int* status);
+                               double* Dinv, double* G, double* H, double* MT, double* panel,
+                               double* colk, double* W, double* R, int* perm, int* idx,
+                               int* status);
 void launch_coarse_factor(hipStream_t s, const Level& L, double* Ag, double* Dinv, double* G,
                           double* H, double* M, double* colk, int* perm, int* status);
+// wide: the wide solve (H = D'^{-1} L, M = L D'^{-1} per time level); else the
+// one-workgroup fast solve (H = D'^{-1} L, M = D'^{-T} L^T).
 void launch_coarse_direct(hipStream_t s, const Level& L, int prec_io, int trans, const void* b,
                           void* x, const double* Dinv, const double* G, const double* H,
-                          const double* M, double* work);
+                          const double* M, double* work, int wide);
 
 // Right-hand side, objective, sensitivities, filter.
 void launch_load_uniform(hipStream_t s, const FineGeom& g, double q0, double dx, double dt,
