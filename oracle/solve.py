@@ -164,9 +164,10 @@ class BlockTimeSystem:
             self._lu[ck] = spla.splu(sp.csc_matrix(D.T if transpose else D))
         return self._lu[ck]
 
-    def gauss_seidel(self, fm, tol=1e-13, max_sweeps=200, transpose=False, x0=None):
+    def gauss_seidel(self, fm, tol=1e-13, max_sweeps=200, transpose=False, x0=None, log=None):
         """Block GS sweeps (forward in time; backward for the transpose) until
-        ||fm - A s|| <= tol*||fm||.  Returns (s, sweeps, rel_res)."""
+        ||fm - A s|| <= tol*||fm||.  Returns (s, sweeps, rel_res).  log: a
+        callable that receives (sweep, rel_res) after every sweep."""
         g, P = self.g, self.P
         F = np.asarray(fm, dtype=np.float64).reshape(g.nt + 1, P)
         S = np.zeros_like(F) if x0 is None else np.array(x0, dtype=np.float64).reshape(g.nt + 1, P)
@@ -191,6 +192,8 @@ class BlockTimeSystem:
                 S[n] = self._diag_lu(n, transpose).solve(rhs)
             r = F.ravel() - self.matvec(S.ravel(), transpose=transpose)
             rel = np.linalg.norm(r) / nf if nf > 0 else np.linalg.norm(r)
+            if log is not None:
+                log(sweep, rel)
             if rel <= tol:
                 return S.ravel(), sweep, rel
         return S.ravel(), max_sweeps, rel

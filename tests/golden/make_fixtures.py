@@ -13,7 +13,7 @@ seeded inputs of paper_2508_09589_amd/inputs.py; nothing comes from the GPU.
                  block Gauss-Seidel solves; no cancellation).
   medium_256.npz  the state of the medium workload (256^2 x 256, smooth
                  time-varying density seed 1) by block Gauss-Seidel in time to
-                 a relative residual of 1e-13: ||s||, the full time levels
+                 a relative residual of 3e-12: ||s||, the full time levels
                  n = 128 and 256 and 20000 random nodes.
 The large workload is checked without a fixture: the oracle recomputes the
 residual of the GPU solution at every node (tests/test_gpu_fullsize.py).
@@ -106,8 +106,9 @@ def medium():
     k, C, _, _ = simp(rho, MAT)
     t = time.time()
     bs = BlockTimeSystem(g, k, C, dirichlet_mask(g, [PATCH_LEFT_CENTRED]))
-    s, sweeps, rel = bs.gauss_seidel(bs.masked_rhs(load_vector(g, 1.0)), tol=1e-13,
-                                     max_sweeps=300)
+    s, sweeps, rel = bs.gauss_seidel(bs.masked_rhs(load_vector(g, 1.0)), tol=3e-12,
+                                     max_sweeps=80,
+                                     log=lambda k, r: print(f"sweep {k}: {r:.3e}", flush=True))
     S = s.reshape(g.shape_nodes)
     nodes = np.random.default_rng(6).choice(g.n_nodes, 20000, replace=False)
     levels = np.array([128, 256])

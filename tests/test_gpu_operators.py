@@ -324,3 +324,25 @@ def test_direct_coarse_solve_is_exact(torch_cuda, nx, ny, nt, tv):
     import scipy.sparse as sp
     assert rel(xg, solve_direct(sp.csr_matrix(c.Jm.T), b)) < 1e-11
     p.close()
+
+
+@pytest.mark.parametrize("n,nt,design", [(32, 128, "random"), (32, 256, "sink"), (16, 512, "random")])
+def test_wide_coarse_solve_is_exact_at_size(torch_cuda, n, nt, design):
+    """The wide factorisation and sweeps at the sizes the 8-level hierarchies
+    reach (33^2-node planes over 129 and 257 time levels, 17^2 over 513): on a
+    one-level hierarchy the V-cycle is the exact solve, so its residual under
+    the matrix-free fine operator (itself checked against the oracle) is at
+    rounding level, forward and transposed."""
+    import torch
+    from paper_2508_09589_amd import Problem
+    from paper_2508_09589_amd.inputs import heat_sink_density
+    rng = np.random.default_rng(1)
+    rho = rng.uniform(0.001, 1, (nt, n, n)) if design == "random" else heat_sink_density(n)
+    p = Problem(n, n, nt, torch.tensor(rho), max_levels=1)
+    shp = p.level_shape(0)
+    for trans in (False, True):
+        b = torch.tensor(rng.standard_normal(shp), device="cuda")
+        x = p.debug_vcycle(b, transpose=trans)
+        r = b - p.debug_apply(0, x, transpose=trans)
+        assert float(r.norm() / b.norm()) < 1e-13, (trans, float(r.norm() / b.norm()))
+    p.close()
