@@ -177,6 +177,12 @@ def test_bf16_stencil_applies(torch_cuda, tv):
             y = p.debug_apply(l, _t(xt).reshape(p.level_shape(l)), transpose=trans, mixed=True)
             assert np.max(np.abs(y.cpu().numpy().ravel() - exact)) <= 1e-5 * np.max(np.abs(Al.data)) * \
                 np.max(np.abs(xt))
+            # distance of the BF16 operator from the exact FP64 one on a random
+            # vector: the stated bound for BF16 coarse levels is 1e-2 (2-norm)
+            y = p.debug_apply(l, _t(x).reshape(p.level_shape(l)), transpose=trans, mixed=True)
+            d = rel(y.cpu().numpy(), (Al.T if trans else Al) @ x)
+            print(f"level {l} trans={trans}: BF16 apply vs exact {d:.2e}", flush=True)
+            assert d <= 1e-2, (l, trans, d)
     p.close()
 
 
