@@ -106,3 +106,46 @@ def test_level_transpose_identity():
         v = rng.standard_normal(Pm[l].shape[1])
         w = rng.standard_normal(Pm[l].shape[0])
         assert abs((Pm[l] @ v) @ w - v @ (Pm[l].T @ w)) < 1e-13 * np.linalg.norm(v) * np.linalg.norm(w) * 4
+
+
+@pytest.mark.parametrize("tv,full", [(False, False), (True, False), (True, True)])
+def test_time_offset_blocks_are_symmetric_in_space(tv, full):
+    """Every time-offset block of every Galerkin level is symmetric in space:
+    A(p, p + (dn, dj, di)) = A(q, q + (dn, -dj, -di)) with q = p + (0, dj, di)
+    (each slab's element matrices are k A~ + C B~ with spatial factors M, S
+    that are symmetric, the prolongation is a tensor product and the Dirichlet
+    set of a level is the same at every time level but the first, which is
+    all identity rows).  The GPU's FP32 and BF16 stencils store 15 of the 27
+    entries of a row on this basis; the mirror of a lower entry (dj < 0, or
+    dj = 0 and di < 0) is its neighbour's upper one.  Also on a 16 x 12 x 16
+    grid with an extra patch on another edge."""
+    for (n, ny, nt, patch) in [(16, 16, 16, PATCH), (16, 12, 16, PATCH + [(3, 0.3, 0.2)])]:
+        g = Grid(n, ny, nt, 1.0 / max(n, ny), 1.0 / nt)
+        rng = np.random.default_rng(3)
+        rho = rng.uniform(1e-3, 1, (nt, ny, n) if tv else (ny, n))
+        k = 1e-3 + (1 - 1e-3) * rho ** 3
+        C = 0.5 + rho
+        mask = dirichlet_mask(g, patch)
+        Jm, _ = apply_dirichlet(assemble_matrix(g, k, C), np.zeros(g.n_nodes), mask)
+        lv = build_hierarchy(n, ny, nt, g.dx, g.dt, 1.0, 1e-3, 1.5, 0.5, max_coarse_nodes=100,
+                             full=full)
+        A, masks, Pm = build_operators(lv, Jm, mask)
+        assert len(lv) >= 3
+        for l in range(len(lv)):
+            st = stencil_of(A[l], lv[l])          # [27, nt+1, ny+1, nx+1]
+            L = lv[l]
+            scale = np.max(np.abs(st))
+            checked = 0
+            for dn in (-1, 0, 1):
+                for dj in (-1, 0, 1):
+                    for di in (-1, 0, 1):
+                        d = (dn + 1) * 9 + (dj + 1) * 3 + (di + 1)
+                        dm = (dn + 1) * 9 + (-dj + 1) * 3 + (-di + 1)
+                        # rows p whose neighbour q = p + (0, dj, di) exists
+                        j0, j1 = max(0, -dj), L["ny"] + 1 - max(0, dj)
+                        i0, i1 = max(0, -di), L["nx"] + 1 - max(0, di)
+                        a = st[d][:, j0:j1, i0:i1]
+                        b = st[dm][:, j0 + dj:j1 + dj, i0 + di:i1 + di]
+                        assert np.max(np.abs(a - b)) <= 1e-14 * scale, (l, dn, dj, di)
+                        checked += a.size
+            assert checked > 0
