@@ -437,24 +437,15 @@ void launch_stencil_invdiag(hipStream_t s, const Level& L, double* invd64, float
                        L.nplanes, L.st64, L.plane_map, invd64, invd32);
 }
 
-__global__ void k_stencil_cast(long long n, const double* __restrict__ in, float* __restrict__ o32,
-                               uint16_t* __restrict__ o16) {
-    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n;
-         t += (long long)gridDim.x * blockDim.x) {
-        const float f = (float)in[t];
-        if (o32) o32[t] = f;
-        if (o16) o16[t] = f32_to_bf16(f);
-    }
-}
-
-// Compensated FP32 centres of a BF16 stencil (layout in stencil_core.hpp):
-// per plane, node r and time offset g = dn + 1,
-//   rows:    cen[g]     = sum_q A_g,q(r)            - sum_{q != centre} bf16(A_g,q(r))
-//   columns: cen[3 + g] = sum_q A_g,8-q(r + off_q)  - sum_{q != centre} bf16(A_g,8-q(r + off_q))
-// where A_g,q(r) = st[g*9 + q][plane][r] and the column sum runs over the
-// in-domain neighbours r + off_q (their entries pointing back at r).
-__global__ void k_stencil_centres(int nx, int ny, int nplanes, const double* __restrict__ st,
-                                  float* __restrict__ cen) {
+// Symmetric FP32 / BF16 copies of the FP64 stencil (layout in
+// stencil_core.hpp), with the compensated FP32 centres of the BF16 form: per
+// plane, node r and time offset g = dn + 1, over the nine values v_q the apply
+// uses (v_q = A_{g,q}(r) for q >= 4, A_{g,8-q}(r + off_q) for q < 4 and an
+// in-domain neighbour):
+//     cen[g] = sum_q v_q - sum_{q != 4} bf16(v_q).
+__global__ void k_stencil_sym(int nx, int ny, int nplanes, const double* __restrict__ st,
+                              float* __restrict__ o32, uint16_t* __restrict__ o16,
+                              float* __restrict__ cen) {
     const int rowp = nx + 1;
     const long long P = (long long)rowp * (ny + 1);
     const long long DS = P * nplanes;
@@ -465,31 +456,30 @@ __global__ void k_stencil_centres(int nx, int ny, int nplanes, const double* __r
         const int j = (int)(r / rowp), i = (int)(r - (long long)j * rowp);
         const double* sp = st + (long long)pl * P;
         for (int g = 0; g < 3; ++g) {
-            double rs = 0.0, rr = 0.0, cs = 0.0, cr = 0.0;
+            double sum = 0.0, rounded = 0.0;
             for (int q = 0; q < 9; ++q) {
-                const double a = sp[(long long)(g * 9 + q) * DS + r];
-                rs += a;
-                if (q != 4) rr += (double)bf16_to_f32(f32_to_bf16((float)a));
-                const int di = q % 3 - 1, dj = q / 3 - 1;
-                if (i + di < 0 || i + di > nx || j + dj < 0 || j + dj > ny) continue;
-                const double b = sp[(long long)(g * 9 + 8 - q) * DS + r + dj * rowp + di];
-                cs += b;
-                if (q != 4) cr += (double)bf16_to_f32(f32_to_bf16((float)b));
+                double v;
+                if (q >= 4) {
+                    v = sp[(long long)(g * 9 + q) * DS + r];
+                    if (o32) o32[(long long)(g * 5 + q - 4) * DS + t] = (float)v;
+                    if (o16 && q > 4) o16[(long long)(g * 4 + q - 5) * DS + t] = f32_to_bf16((float)v);
+                } else {
+                    const int di = q % 3 - 1, dj = q / 3 - 1;
+                    if (i + di < 0 || i + di > nx || j + dj < 0 || j + dj > ny) continue;
+                    v = sp[(long long)(g * 9 + 8 - q) * DS + r + dj * rowp + di];
+                }
+                sum += v;
+                if (q != 4) rounded += (double)bf16_to_f32(f32_to_bf16((float)v));
             }
-            cen[(long long)g * DS + t] = (float)(rs - rr);
-            cen[(long long)(3 + g) * DS + t] = (float)(cs - cr);
+            if (cen) cen[(long long)g * DS + t] = (float)(sum - rounded);
         }
     }
 }
 
 void launch_stencil_cast(hipStream_t s, const Level& L, float* st32, uint16_t* st16) {
-    const long long n = 27LL * L.nplanes * (L.nx + 1) * (L.ny + 1);
-    hipLaunchKernelGGL(k_stencil_cast, dim3(grid_for(n)), dim3(256), 0, s, n, L.st64, st32, st16);
-    if (st16 && L.cen32) {
-        const long long m = (long long)L.nplanes * (L.nx + 1) * (L.ny + 1);
-        hipLaunchKernelGGL(k_stencil_centres, dim3(grid_for(m)), dim3(256), 0, s, L.nx, L.ny,
-                           L.nplanes, L.st64, L.cen32);
-    }
+    const long long m = (long long)L.nplanes * (L.nx + 1) * (L.ny + 1);
+    hipLaunchKernelGGL(k_stencil_sym, dim3(grid_for(m)), dim3(256), 0, s, L.nx, L.ny, L.nplanes,
+                       L.st64, st32, st16, st16 ? L.cen32 : nullptr);
 }
 
 // ---------------------------------------------------------------------------

@@ -238,10 +238,12 @@ size_t carve(st_handle* h, char* base) {
             // coarse levels hold Galerkin stencils; a one-level hierarchy
             // needs the fine stencil for its coarsest-level solve
             L.st64 = c.take<double>((size_t)27 * P * (L.nt + 1));
-            L.st32 = (mixed && L.sprec == 1 && l > 0) ? c.take<float>((size_t)27 * P * (L.nt + 1)) : nullptr;
-            L.st16 = (mixed && L.sprec == 2 && l > 0) ? c.take<uint16_t>((size_t)27 * P * (L.nt + 1)) : nullptr;
+            // FP32 / BF16 copies in symmetric form: 15 FP32 entries, or 12 BF16
+            // entries plus 3 compensated FP32 centres, per row
+            L.st32 = (mixed && L.sprec == 1 && l > 0) ? c.take<float>((size_t)15 * P * (L.nt + 1)) : nullptr;
+            L.st16 = (mixed && L.sprec == 2 && l > 0) ? c.take<uint16_t>((size_t)12 * P * (L.nt + 1)) : nullptr;
             // (decided by the options, never by a pointer: sizing passes get null ones)
-            L.cen32 = (mixed && L.sprec == 2 && l > 0) ? c.take<float>((size_t)6 * P * (L.nt + 1)) : nullptr;
+            L.cen32 = (mixed && L.sprec == 2 && l > 0) ? c.take<float>((size_t)3 * P * (L.nt + 1)) : nullptr;
         }
         const bool coarsest = l == h->nlev - 1;
         L.x = (l > 0) ? (void*)c.take<char>(L.nn * vb) : nullptr;
@@ -409,10 +411,10 @@ int64_t fine_coef_bytes(const st_handle* h, int vb) {
 // Operator applications on a level.  Level 0 is matrix-free; coarse levels
 // use their Galerkin stencil.  prec: storage/arithmetic precision (0 FP64,
 // 1 the level's V-cycle precision when mixed).
-// Bytes of one stored stencil row: 27 coefficients in FP64 or FP32, or 24 in
-// BF16 plus three compensated FP32 centres.
+// Bytes of one stored stencil row: 27 coefficients in FP64; in symmetric form
+// 15 in FP32, or 12 in BF16 plus three compensated FP32 centres.
 static int64_t stencil_row_bytes(const Level& L, int prec) {
-    return prec == 0 ? 27 * 8 : (L.sprec == 2 ? 24 * 2 + 3 * 4 : 27 * 4);
+    return prec == 0 ? 27 * 8 : (L.sprec == 2 ? 12 * 2 + 3 * 4 : 15 * 4);
 }
 
 void level_apply(st_handle* h, int l, int prec, int trans, const void* x, void* y, const void* b,

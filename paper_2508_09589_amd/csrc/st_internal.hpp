@@ -103,7 +103,7 @@ struct Level {
     double* st64 = nullptr;        // [27][nplanes][ny+1][nx+1]
     float* st32 = nullptr;
     uint16_t* st16 = nullptr;
-    float* cen32 = nullptr;        // BF16 stencils: compensated centres [6][nplanes][ny+1][nx+1]
+    float* cen32 = nullptr;        // BF16 stencils: compensated centres [3][nplanes][ny+1][nx+1]
     double* invd64 = nullptr;
     float* invd32 = nullptr;
     void* x = nullptr;             // V-cycle vectors (vprec)

@@ -6,13 +6,21 @@
 // identical rows share storage.  Storage is FP64, FP32 or BF16 (upper half of
 // an FP32, round to nearest even).
 //
-// BF16 stencils keep their three in-plane centres (di = dj = 0, d = 4, 13, 22)
-// in FP32 instead, compensated so that rounding leaves the sums over each
-// time offset intact: cen[g][plane][r] (g = dn + 1) makes every row's sum over
-// the 9 entries of offset dn exact (forward apply), cen[3 + g][plane][r] makes
-// the matching column sums exact (transposed apply).  Those sums fix how the
-// operator acts on fields that are constant in space; an insulated domain has
-// near-null modes of that kind, which plain BF16 rounding would perturb.
+// The FP32 and BF16 copies are stored in symmetric form.  Every time-offset
+// block of a Galerkin level is symmetric in space,
+//     A(p, p + (dn, dj, di)) = A(q, q + (dn, -dj, -di)),  q = p + (0, dj, di),
+// so of the nine in-plane entries q = (dj+1)*3 + (di+1) of a time offset only
+// q >= 4 (the centre and the four "upper" neighbours) are stored; entry q < 4
+// of row r is entry 8 - q of the neighbour row r + off_q.  FP32: sym[g*5 +
+// q - 4][plane][r] (15 per row, g = dn + 1).  BF16: sym[g*4 + q - 5][plane][r]
+// (12 per row), the three centres in FP32 instead, compensated so that
+// rounding leaves the sums over each time offset intact: cen[g][plane][r] =
+// the exact FP64 sum of the nine values the apply uses for row r and offset
+// dn minus the eight rounded off-centre ones.  By the symmetry the transposed
+// apply uses the same values for its column sums, so the same centres serve
+// it.  Those sums fix how the operator acts on fields that are constant in
+// space; an insulated domain has near-null modes of that kind, which plain
+// BF16 rounding would perturb.  The FP64 stencil keeps all 27 entries.
 #pragma once
 #include <type_traits>
 
@@ -42,6 +50,12 @@ template <> __device__ __forceinline__ double ldcoef<double, double>(const doubl
     return *p;
 }
 
+// Index of stored entry (g, q), q >= 4 (q >= 5 for BF16, whose centres live
+// in the FP32 array), in a symmetric stencil array.
+template <bool BF16> __device__ __forceinline__ int sym_index(int g, int q) {
+    return BF16 ? g * 4 + (q - 5) : g * 5 + (q - 4);
+}
+
 // Rows of y = A x (TRANS: A^T x) at in-plane position r = j (nx+1) + i for the
 // time levels n0 <= n < n1; emit(n, idx, value) receives each one.  The
 // thread keeps the x values of levels n-1, n, n+1 around r in registers (9 new
@@ -56,17 +70,24 @@ __device__ __forceinline__ void stencil_march_rows(int nx, int ny, int nt, int n
                                                    const T* __restrict__ x, int r, int n0, int n1,
                                                    Emit&& emit) {
     constexpr bool CEN = std::is_same<S, uint16_t>::value;   // compensated FP32 centres
+    constexpr bool SYM = !std::is_same<S, double>::value;     // symmetric (15- or 12-entry) storage
     const int rowp = nx + 1;
     const int P = rowp * (ny + 1);
     const int j = r / rowp, i = r - j * rowp;
     const long long DS = (long long)P * nplanes;
+    // Every load below is unconditional: a neighbour outside the plane reads
+    // the row itself (off = 0) and its x value is replaced by zero, so the
+    // coefficient it pairs with may be any finite number; time levels outside
+    // [0, nt] read plane 0 and meet x planes of zeros.  (Loads under a lane
+    // condition become branches, each closed by a wait for its load.)
     unsigned valid = 0;
     int off[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         const int di = q % 3 - 1, dj = q / 3 - 1;
-        off[q] = dj * rowp + di;
-        if (i + di >= 0 && i + di <= nx && j + dj >= 0 && j + dj <= ny) valid |= 1u << q;
+        const bool in = i + di >= 0 && i + di <= nx && j + dj >= 0 && j + dj <= ny;
+        off[q] = in ? dj * rowp + di : 0;
+        if (in) valid |= 1u << q;
     }
     auto load_plane = [&](int n, TC u[9]) {
         if (n < 0 || n > nt) {
@@ -76,7 +97,10 @@ __device__ __forceinline__ void stencil_march_rows(int nx, int ny, int nt, int n
         }
         const T* xp = x + (long long)n * P + r;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) u[q] = ((valid >> q) & 1u) ? (TC)xp[off[q]] : (TC)0;
+        for (int q = 0; q < 9; ++q) {
+            const TC v = (TC)xp[off[q]];
+            u[q] = ((valid >> q) & 1u) ? v : (TC)0;
+        }
     };
     TC xm[9], xc[9], xp[9], c[27];
     load_plane(n0 - 1, xm);
@@ -93,28 +117,49 @@ __device__ __forceinline__ void stencil_march_rows(int nx, int ny, int nt, int n
             key1 = pc;
             key2 = pp;
             if (!TRANS) {
-                const S* sp = st + (long long)pc * P + r;
+                if (SYM) {
+                    // row r's entry (g, q): stored at r for q >= 4, the
+                    // neighbour's (g, 8 - q) for q < 4
 #pragma unroll
-                for (int d = 0; d < 27; ++d) {
-                    if (CEN && d % 9 == 4)
-                        c[d] = (TC)cen[(long long)(d / 9) * DS + (long long)pc * P + r];
-                    else
-                        c[d] = ldcoef<TC, S>(sp + (long long)d * DS);
+                    for (int g = 0; g < 3; ++g)
+#pragma unroll
+                        for (int q = 0; q < 9; ++q) {
+                            const int qs = q >= 4 ? q : 8 - q;
+                            const long long rr = (long long)pc * P + r + (q >= 4 ? 0 : off[q]);
+                            if (CEN && q == 4)
+                                c[g * 9 + q] = (TC)cen[(long long)g * DS + rr];
+                            else
+                                c[g * 9 + q] = ldcoef<TC, S>(st + (long long)sym_index<CEN>(g, qs) * DS + rr);
+                        }
+                } else {
+                    const S* sp = st + (long long)pc * P + r;
+#pragma unroll
+                    for (int d = 0; d < 27; ++d) c[d] = ldcoef<TC, S>(sp + (long long)d * DS);
                 }
             } else {
 #pragma unroll
                 for (int dn = -1; dn <= 1; ++dn) {
-                    const int pl = dn < 0 ? pm : (dn == 0 ? pc : pp);
+                    // plane of level n + dn (plane 0 past either end)
+                    const int pl = dn < 0 ? (pm < 0 ? 0 : pm) : (dn == 0 ? pc : (pp < 0 ? 0 : pp));
+                    const int gt = 1 - dn;   // time-offset group of the row that points back
 #pragma unroll
                     for (int q = 0; q < 9; ++q) {
                         const int d = (dn + 1) * 9 + q;
-                        if (CEN && q == 4)
-                            c[d] = pl >= 0 ? (TC)cen[(long long)(4 - dn) * DS + (long long)pl * P + r]
-                                           : (TC)0;
-                        else
-                            c[d] = (pl >= 0 && ((valid >> q) & 1u))
-                                       ? ldcoef<TC, S>(st + (long long)(26 - d) * DS + (long long)pl * P + r + off[q])
-                                       : (TC)0;
+                        // A^T(r, r + off_q) at offset dn = entry (gt, 8 - q) of
+                        // row r + off_q on level n + dn; in symmetric storage
+                        // that is stored there for q <= 4 and, for q > 4, is
+                        // entry (gt, q) of row r itself
+                        if (SYM) {
+                            const bool own = q > 4;
+                            const long long rr = (long long)pl * P + r + (own ? 0 : off[q]);
+                            const int qs = own ? q : 8 - q;
+                            if (CEN && q == 4)
+                                c[d] = (TC)cen[(long long)gt * DS + (long long)pl * P + r];
+                            else
+                                c[d] = ldcoef<TC, S>(st + (long long)sym_index<CEN>(gt, qs) * DS + rr);
+                        } else {
+                            c[d] = ldcoef<TC, S>(st + (long long)(26 - d) * DS + (long long)pl * P + r + off[q]);
+                        }
                     }
                 }
             }

@@ -97,13 +97,13 @@ def test_setup_rejects_null_pointers_without_gpu():
 
 @pytest.mark.parametrize("nx,nt,tv", [(64, 64, 1), (96, 48, 0), (256, 256, 1)])
 def test_bf16_footprint_counts_compensated_centres(nx, nt, tv):
-    """BF16 coarse stencils hold 27 BF16 coefficients plus 6 FP32 compensated
-    centres per stored row (78 bytes) where FP32 stencils hold 108: the
-    sizing pass must count both arrays, level by level."""
+    """Coarse stencils are stored in symmetric form: 15 FP32 coefficients per
+    row (60 bytes), or 12 BF16 ones plus 3 FP32 compensated centres (36
+    bytes): the sizing pass must count both arrays, level by level."""
     from oracle.hierarchy import build_hierarchy
     lv = build_hierarchy(nx, nx, nt, 1.0 / nx, 1.0 / nt, 1.0, 1e-3, 1.0, 1.0)
     rows = sum((L["nx"] + 1) * (L["ny"] + 1) * (L["nt"] + 1) for L in lv[1:])
     rc, b32 = _fp(nx, nx, nt, tv, precision=L.ST_MIXED, bf16_from_level=0)
     rc2, b16 = _fp(nx, nx, nt, tv, precision=L.ST_MIXED, bf16_from_level=1)
     assert rc == 0 and rc2 == 0
-    assert abs((b32 - b16) - (108 - 78) * rows) <= 2 * 256 * len(lv), (b32 - b16, 30 * rows)
+    assert abs((b32 - b16) - (60 - 36) * rows) <= 2 * 256 * len(lv), (b32 - b16, 24 * rows)

@@ -125,7 +125,10 @@ def _bf16_compensated(A, P, by_column):
     node to itself at time offset dn), which instead takes the exact sum of
     its group minus the rounded rest.  The group is a row's entries of one
     time offset (forward apply) or a column's (by_column, transposed apply),
-    so those sums survive the rounding exactly."""
+    so those sums survive the rounding exactly.  The GPU stores the
+    symmetric half of each time-offset block and reads a lower entry from the
+    neighbouring row's upper one: the same numbers, to rounding of the FP64
+    Galerkin product, so this model covers that storage too."""
     import scipy.sparse as sp
     C = sp.coo_matrix(A)
     i, j, v = C.row, C.col, C.data
