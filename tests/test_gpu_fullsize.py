@@ -5,6 +5,8 @@ FGMRES(30) on the medium grid, FGMRES(20) on the large one, relative residual
 own element matrices at every node: of the medium grid (256^2 x 256, 17M
 nodes) and, one time level at a time, of the large one (512^2 x 1024, 269M
 nodes)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -109,3 +111,60 @@ def test_large_residual_full_field(torch_cuda):
     assert np.max(np.abs(r)) <= rmax * (1 + 1e-12)
     on_mask = nodes[mask.ravel()[nodes]]
     assert np.all(Tn.ravel()[on_mask] == 0.0)
+
+
+MEDIUM_FIXTURE = os.path.join(os.path.dirname(__file__), "golden", "medium_256.npz")
+
+
+@pytest.mark.skipif(not os.path.exists(MEDIUM_FIXTURE), reason="medium oracle fixture not written")
+def test_medium_error_against_oracle(torch_cuda):
+    """Error of the GPU solution against the oracle's state of the medium
+    workload (block Gauss-Seidel in time to its rounding floor, written by
+    tests/golden/make_fixtures.py), over the two full time levels n = 128, 256
+    and 20000 random nodes the fixture holds:
+      * FP64 and mixed in parity mode (rtol 1e-11, or to stagnation: FP64
+        rounding leaves the residual of this grid near 5e-12, for the oracle
+        too): ||T - T_oracle|| / ||T_oracle|| <= 1e-10 on the sample;
+      * at the benchmark's rtol 1e-8: kappa = (error / residual) of the FP64
+        solve, and the mixed solve's error stays within kappa * 1e-8 (the
+        FP64-refined bound), with both stated.  The two solves stop at
+        nearly the same residual with nearly the same error-to-residual
+        ratio (1.622e-2 both), so the bound is tight by construction; the
+        assertion allows kappa 10% for its being measured on one solve."""
+    import torch
+    from paper_2508_09589_amd import Problem
+    from paper_2508_09589_amd.inputs import WORKLOADS, workload_density
+    fx = np.load(MEDIUM_FIXTURE)
+    w = WORKLOADS["medium"]
+    rho = workload_density("medium")
+    g = Grid(w["nx"], w["ny"], w["nt"], 1.0 / w["nx"], 1.0 / w["nt"])
+    levels, nodes = fx["levels"], fx["nodes"]
+    ref = np.concatenate([fx["s_levels"].ravel(), fx["s_at"]])
+    P = (g.nx + 1) * (g.ny + 1)
+
+    def sample(T):
+        Tn = T.reshape(-1)
+        lv = torch.cat([Tn[int(n) * P:(int(n) + 1) * P] for n in levels]).cpu().numpy()
+        return np.concatenate([lv, Tn[torch.from_numpy(nodes).to(T.device)].cpu().numpy()])
+
+    res = {}
+    for prec in ("fp64", "mixed"):
+        for rtol in (1e-11, 1e-8):
+            kw = dict(bf16_from_level=1, smoother="sstep") if prec == "mixed" else {}
+            p = Problem(g.nx, g.ny, g.nt, torch.tensor(rho), precision=prec, restart=30,
+                        rtol=rtol, max_it=200, **kw)
+            T, info = p.solve(allow_not_converged=rtol < 1e-8)
+            assert info.true_rel_res <= max(rtol, 2e-11), (prec, rtol, info.true_rel_res)
+            err = np.linalg.norm(sample(T) - ref) / np.linalg.norm(ref)
+            p.close()
+            res[prec, rtol] = (err, info.true_rel_res, info.iterations)
+            print(f"medium {prec} rtol {rtol:g}: {info.iterations} its, true rel res "
+                  f"{info.true_rel_res:.2e}, error vs oracle {err:.3e}", flush=True)
+    for prec in ("fp64", "mixed"):
+        assert res[prec, 1e-11][0] <= 1e-10, (prec, res[prec, 1e-11])
+    e64, r64, _ = res["fp64", 1e-8]
+    kappa = e64 / r64
+    em = res["mixed", 1e-8][0]
+    print(f"medium rtol 1e-8: kappa {kappa:.3g}; mixed error {em:.3e} against the FP64-refined "
+          f"bound kappa * 1e-8 = {kappa * 1e-8:.3e}", flush=True)
+    assert em <= 1.1 * kappa * 1e-8, (em, kappa)
