@@ -17,6 +17,8 @@
 // per chunk from its plane and the stiffness of the lower plane is reused when
 // the coefficients do not change in time.  Dirichlet nodes: inputs are masked
 // to zero and rows become identity rows (N J N + I - N).
+#include <type_traits>
+
 #include "st_internal.hpp"
 
 namespace st {
@@ -125,7 +127,7 @@ template <typename T> __device__ __forceinline__ void pin_value(T& v) { asm vola
 constexpr int FA_TX = 64, FA_RY = 2, FA_TY = 4 * FA_RY;
 constexpr int FA_DEPTH_TCONST = 3;   // load distance (loop iterations), see k_fine_apply
 
-template <typename TIN, typename TOUT, typename TC, bool TRANS, bool TCONST, bool CUNI>
+template <typename TIN, typename TOUT, typename TC, bool TRANS, bool TCONST, bool CUNI, bool SMOOTH>
 __global__ __launch_bounds__(256) void k_fine_apply(
     FineGeom g, const TC* __restrict__ kc, const TC* __restrict__ cc, const TIN* __restrict__ x,
     TOUT* __restrict__ y, const TOUT* __restrict__ b, int jacobi,
@@ -140,6 +142,14 @@ __global__ __launch_bounds__(256) void k_fine_apply(
     __shared__ TC cs[CUNI ? 1 : 2][CUNI ? 1 : NE];
 
     if (skip && *skip) return;
+    // SMOOTH: y = scale D^{-1} A x off the Dirichlet rows, scale x on them
+    // (the smoother's basis vectors); the scale goes into the reciprocal
+    // diagonal once instead of into every output.
+    if (SMOOTH) {
+        jacobi = 1;
+        b = nullptr;
+        dir_rows = 1;
+    }
     // XCD-aware tile order: hardware workgroup b runs on XCD b % 8.
     const int bid = blockIdx.x;
     const int lin = (bid & 7) * per_xcd + (bid >> 3);
@@ -246,14 +256,17 @@ __global__ __launch_bounds__(256) void k_fine_apply(
             }
     }
     TC ke[RY + 1][2], ce[RY + 1][2];
+    // time-constant coefficients are read once: the time-step and mass
+    // factors go into them there instead of into every level's products
+    const TC fk = TCONST ? (TC)g.dt6 : (TC)1, fc = TCONST ? (TC)g.mw : (TC)1;
     auto read_c = [&](int s) {
 #pragma unroll
         for (int m = 0; m < RY + 1; ++m)
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                ke[m][c] = ks[s & 1][(ry0 + m) * EX + tx + c];
-                ce[m][c] = CUNI ? (((cval >> (m * 2 + c)) & 1u) ? (TC)g.c0 : (TC)0)
-                                : cs[CUNI ? 0 : (s & 1)][CUNI ? 0 : (ry0 + m) * EX + tx + c];
+                ke[m][c] = fk * ks[s & 1][(ry0 + m) * EX + tx + c];
+                ce[m][c] = fc * (CUNI ? (((cval >> (m * 2 + c)) & 1u) ? (TC)g.c0 : (TC)0)
+                                      : cs[CUNI ? 0 : (s & 1)][CUNI ? 0 : (ry0 + m) * EX + tx + c]);
             }
     };
     auto read_x = [&](int n, TC u[RY + 2][3]) {
@@ -264,8 +277,9 @@ __global__ __launch_bounds__(256) void k_fine_apply(
             for (int c = 0; c < 3; ++c) u[m][c] = sx[(ry0 + m) * WX + tx + c];
     };
 
-    const TC kt = (TC)g.dt6;
-    const TC mw = (TC)g.mw;
+    // time-step and mass factors still to apply (1 where read_c did)
+    const TC kt = TCONST ? (TC)1 : (TC)g.dt6;
+    const TC mw = TCONST ? (TC)1 : (TC)g.mw;
     const TC sc = scale ? (TC)(*scale) : (TC)1;
     // 6 * stiffness and 36/dx^2 * mass at row m of the window.
     auto stiff = [&](const TC u[RY + 2][3], int m) -> TC {
@@ -340,6 +354,12 @@ __global__ __launch_bounds__(256) void k_fine_apply(
     auto emit = [&](int n, int m, TC v, TC rdiag, int q) {
         if (!((own >> m) & 1u)) return;
         const bool dir = dir_rows && ((g.ic_dir && n == 0) || ((opatch >> m) & 1u));
+        if (SMOOTH) {
+            // rdiag carries the scale already
+            const TC val = dir ? (TC)xd[q][m] * sc : v * rdiag;
+            buf_st<TOUT>((TOUT)val, rsy, oo[m] * (unsigned)sizeof(TOUT), uniform((unsigned)n * pout));
+            return;
+        }
         TC val = dir ? (TC)xd[q][m] : v;
         if (b) val = (TC)bv[q][m] - val;
         if (jacobi && !dir) val *= rdiag;
@@ -387,9 +407,9 @@ __global__ __launch_bounds__(256) void k_fine_apply(
             Rlo[m] = mw * mass(ulo, m);
             const TC dl = (TC)8 * kt * (ke[m][0] + ke[m][1] + ke[m + 1][0] + ke[m + 1][1]);
             const TC du = (TC)4 * mw * (ce[m][0] + ce[m][1] + ce[m + 1][0] + ce[m + 1][1]);
-            rmid[m] = (TC)1 / (dl + dl + du);
-            rfirst[m] = (TC)1 / dl;
-            rlast[m] = (TC)1 / (dl + du);
+            rmid[m] = (SMOOTH ? sc : (TC)1) / (dl + dl + du);
+            rfirst[m] = (SMOOTH ? sc : (TC)1) / dl;
+            rlast[m] = (SMOOTH ? sc : (TC)1) / (dl + du);
             pin_value(rmid[m]);
             pin_value(rfirst[m]);
         }
@@ -424,8 +444,9 @@ __global__ __launch_bounds__(256) void k_fine_apply(
                 const TC sk = ke[m][0] + ke[m][1] + ke[m + 1][0] + ke[m + 1][1];
                 const TC sc4 = ce[m][0] + ce[m][1] + ce[m + 1][0] + ce[m + 1][1];
                 const TC dlo = (TC)8 * kt * sk;
-                if (s >= n0)
-                    emit(s, m, acc[m] + bottom, jacobi ? recip(dacc[m] + dlo) : (TC)1, q);
+                const TC rd = SMOOTH ? recip(dacc[m] + dlo) * sc
+                                     : (jacobi ? recip(dacc[m] + dlo) : (TC)1);
+                if (s >= n0) emit(s, m, acc[m] + bottom, rd, q);
                 dacc[m] = dlo + (TC)4 * mw * sc4;
             }
             acc[m] = top;
@@ -449,7 +470,10 @@ __global__ __launch_bounds__(256) void k_fine_apply(
         const int q = (sb + 1 - sa) % DEPTH;
 #pragma unroll
         for (int m = 0; m < RY; ++m)
-            emit(nt, m, acc[m], TCONST ? rlast[m] : (jacobi ? recip(dacc[m]) : (TC)1), q);
+            emit(nt, m, acc[m],
+                 TCONST ? rlast[m]
+                        : (SMOOTH ? recip(dacc[m]) * sc : (jacobi ? recip(dacc[m]) : (TC)1)),
+                 q);
     }
 }
 
@@ -478,9 +502,22 @@ static void fine_dispatch(hipStream_t s, const FineGeom& g, const TC* kc, const 
     TOUT* yo = (TOUT*)y;
     const TOUT* bi = (const TOUT*)b;
     const int px = (int)per_xcd;
-#define FA_LAUNCH(TR, TCN, CU)                                                                  \
-    hipLaunchKernelGGL((k_fine_apply<TIN, TOUT, TC, TR, TCN, CU>), grid, block, 0, s, g, kc, cc, \
-                       xi, yo, bi, jacobi, scale, skip, gx, gy, nchunk, px, mask_in, dir_rows)
+    // The smoother's basis applies (Jacobi-scaled, no b, Dirichlet rows
+    // copied) get their own instantiation when input, output and arithmetic
+    // share one precision.
+    constexpr bool ONE = std::is_same<TIN, TOUT>::value && std::is_same<TIN, TC>::value;
+    const bool smooth = ONE && jacobi && !b && dir_rows;
+#define FA_LAUNCH(TR, TCN, CU)                                                                 \
+    do {                                                                                       \
+        if (smooth)                                                                            \
+            hipLaunchKernelGGL((k_fine_apply<TIN, TOUT, TC, TR, TCN, CU, ONE>), grid, block, 0, s, \
+                               g, kc, cc, xi, yo, bi, jacobi, scale, skip, gx, gy, nchunk, px,     \
+                               mask_in, dir_rows);                                             \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_fine_apply<TIN, TOUT, TC, TR, TCN, CU, false>), grid, block, 0, \
+                               s, g, kc, cc, xi, yo, bi, jacobi, scale, skip, gx, gy, nchunk, px,  \
+                               mask_in, dir_rows);                                             \
+    } while (0)
     const bool cu = g.cuniform != 0;
     if (g.tconst) {
         if (trans) {

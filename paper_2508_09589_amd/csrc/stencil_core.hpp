@@ -50,6 +50,28 @@ template <> __device__ __forceinline__ double ldcoef<double, double>(const doubl
     return *p;
 }
 
+// Address of element e of an array whose base is the same for the whole
+// wave: a scalar base plus a 32-bit per-lane byte offset (no 64-bit vector
+// address per load).
+template <typename S> __device__ __forceinline__ const S* at_elem(const S* base, unsigned e) {
+    return (const S*)((const char*)base + e * (unsigned)sizeof(S));
+}
+// The same with the base moved to scalar registers explicitly (it is
+// wave-uniform), so that the compiler cannot fold it into a 64-bit per-lane
+// address.
+template <typename S> __device__ __forceinline__ const S* at_elem_u(const S* base, unsigned e) {
+    typedef const S __attribute__((address_space(1))) GS;
+    const unsigned long long v = (unsigned long long)base;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    GS* g = (GS*)(((unsigned long long)hi << 32) | lo);
+    // the 32-bit offset is formed here, next to its load (a hoisted 64-bit
+    // copy would defeat the scalar-base addressing form)
+    unsigned b = e * (unsigned)sizeof(S);
+    asm volatile("" : "+v"(b));
+    return (const S*)((const __attribute__((address_space(1))) char*)g + b);
+}
+
 // Index of stored entry (g, q), q >= 4 (q >= 5 for BF16, whose centres live
 // in the FP32 array), in a symmetric stencil array.
 template <bool BF16> __device__ __forceinline__ int sym_index(int g, int q) {
@@ -62,6 +84,15 @@ template <bool BF16> __device__ __forceinline__ int sym_index(int g, int q) {
 // loads per level).  The 27 coefficients of a row depend on the plane index
 // only, so they are loaded again only when plane_map changes (time-invariant
 // operators load them a handful of times per column).
+//
+// Loads of x are guarded lane by lane (a neighbour outside the plane would
+// read another row, or outside the array): the three of one grid row share an
+// address and differ by immediate offsets, and on interior waves the guards
+// cost no branch.  Loads of coefficients are not guarded, so that a reload of
+// a row's coefficients has no branch (each would close with a wait for its
+// load): a neighbour outside the plane reads row r itself, and the number it
+// gets meets an x value of zero.  Their addresses are a wave-uniform base
+// (plane and entry) plus a 32-bit lane offset.
 template <typename T, typename S, typename TC, bool TRANS, typename Emit>
 __device__ __forceinline__ void stencil_march_rows(int nx, int ny, int nt, int nplanes,
                                                    const S* __restrict__ st,
@@ -75,20 +106,16 @@ __device__ __forceinline__ void stencil_march_rows(int nx, int ny, int nt, int n
     const int P = rowp * (ny + 1);
     const int j = r / rowp, i = r - j * rowp;
     const long long DS = (long long)P * nplanes;
-    // Every load below is unconditional: a neighbour outside the plane reads
-    // the row itself (off = 0) and its x value is replaced by zero, so the
-    // coefficient it pairs with may be any finite number; time levels outside
-    // [0, nt] read plane 0 and meet x planes of zeros.  (Loads under a lane
-    // condition become branches, each closed by a wait for its load.)
     unsigned valid = 0;
     int off[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         const int di = q % 3 - 1, dj = q / 3 - 1;
-        const bool in = i + di >= 0 && i + di <= nx && j + dj >= 0 && j + dj <= ny;
-        off[q] = in ? dj * rowp + di : 0;
-        if (in) valid |= 1u << q;
+        off[q] = dj * rowp + di;
+        if (i + di >= 0 && i + di <= nx && j + dj >= 0 && j + dj <= ny) valid |= 1u << q;
     }
+    // in-plane index of neighbour q for a coefficient load (r outside the plane)
+    auto ce = [&](int q) -> unsigned { return (unsigned)(((valid >> q) & 1u) ? r + off[q] : r); };
     auto load_plane = [&](int n, TC u[9]) {
         if (n < 0 || n > nt) {
 #pragma unroll
@@ -97,10 +124,7 @@ __device__ __forceinline__ void stencil_march_rows(int nx, int ny, int nt, int n
         }
         const T* xp = x + (long long)n * P + r;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            const TC v = (TC)xp[off[q]];
-            u[q] = ((valid >> q) & 1u) ? v : (TC)0;
-        }
+        for (int q = 0; q < 9; ++q) u[q] = ((valid >> q) & 1u) ? (TC)xp[off[q]] : (TC)0;
     };
     TC xm[9], xc[9], xp[9], c[27];
     load_plane(n0 - 1, xm);
@@ -108,57 +132,62 @@ __device__ __forceinline__ void stencil_march_rows(int nx, int ny, int nt, int n
     int key0 = -2, key1 = -2, key2 = -2;
     for (int n = n0; n < n1; ++n) {
         load_plane(n + 1, xp);
-        const int pm = n > 0 ? pmap[n - 1] : -1;
-        const int pc = pmap[n];
-        const int pp = n < nt ? pmap[n + 1] : -1;
+        const int pm = n > 0 ? __builtin_amdgcn_readfirstlane(pmap[n - 1]) : -1;
+        const int pc = __builtin_amdgcn_readfirstlane(pmap[n]);
+        const int pp = n < nt ? __builtin_amdgcn_readfirstlane(pmap[n + 1]) : -1;
         const bool same = TRANS ? (pm == key0 && pc == key1 && pp == key2) : (pc == key1);
         if (!same) {
             key0 = pm;
             key1 = pc;
             key2 = pp;
             if (!TRANS) {
-                if (SYM) {
-                    // row r's entry (g, q): stored at r for q >= 4, the
-                    // neighbour's (g, 8 - q) for q < 4
+                const long long pb = (long long)pc * P;
 #pragma unroll
-                    for (int g = 0; g < 3; ++g)
+                for (int g = 0; g < 3; ++g)
 #pragma unroll
-                        for (int q = 0; q < 9; ++q) {
-                            const int qs = q >= 4 ? q : 8 - q;
-                            const long long rr = (long long)pc * P + r + (q >= 4 ? 0 : off[q]);
-                            if (CEN && q == 4)
-                                c[g * 9 + q] = (TC)cen[(long long)g * DS + rr];
-                            else
-                                c[g * 9 + q] = ldcoef<TC, S>(st + (long long)sym_index<CEN>(g, qs) * DS + rr);
+                    for (int q = 0; q < 9; ++q) {
+                        if (SYM) {
+                            // row r's entry (g, q): stored at r for q >= 4,
+                            // the neighbour's (g, 8 - q) for q < 4
+                            if (CEN && q == 4) {
+                                c[g * 9 + q] = (TC)*at_elem_u(cen + (long long)g * DS + pb, (unsigned)r);
+                            } else {
+                                const int qs = q >= 4 ? q : 8 - q;
+                                c[g * 9 + q] = ldcoef<TC, S>(at_elem_u(
+                                    st + (long long)sym_index<CEN>(g, qs) * DS + pb,
+                                    q >= 4 ? (unsigned)r : ce(q)));
+                            }
+                        } else {
+                            c[g * 9 + q] = ldcoef<TC, S>(
+                                at_elem_u(st + (long long)(g * 9 + q) * DS + pb, (unsigned)r));
                         }
-                } else {
-                    const S* sp = st + (long long)pc * P + r;
-#pragma unroll
-                    for (int d = 0; d < 27; ++d) c[d] = ldcoef<TC, S>(sp + (long long)d * DS);
-                }
+                    }
             } else {
 #pragma unroll
                 for (int dn = -1; dn <= 1; ++dn) {
-                    // plane of level n + dn (plane 0 past either end)
+                    // plane of level n + dn (plane 0 past either end, where
+                    // the x level is zero)
                     const int pl = dn < 0 ? (pm < 0 ? 0 : pm) : (dn == 0 ? pc : (pp < 0 ? 0 : pp));
+                    const long long pb = (long long)pl * P;
                     const int gt = 1 - dn;   // time-offset group of the row that points back
 #pragma unroll
                     for (int q = 0; q < 9; ++q) {
                         const int d = (dn + 1) * 9 + q;
                         // A^T(r, r + off_q) at offset dn = entry (gt, 8 - q) of
                         // row r + off_q on level n + dn; in symmetric storage
-                        // that is stored there for q <= 4 and, for q > 4, is
-                        // entry (gt, q) of row r itself
+                        // that is entry (gt, q) of row r itself
                         if (SYM) {
-                            const bool own = q > 4;
-                            const long long rr = (long long)pl * P + r + (own ? 0 : off[q]);
-                            const int qs = own ? q : 8 - q;
-                            if (CEN && q == 4)
-                                c[d] = (TC)cen[(long long)gt * DS + (long long)pl * P + r];
-                            else
-                                c[d] = ldcoef<TC, S>(st + (long long)sym_index<CEN>(gt, qs) * DS + rr);
+                            if (CEN && q == 4) {
+                                c[d] = (TC)*at_elem_u(cen + (long long)gt * DS + pb, (unsigned)r);
+                            } else {
+                                const bool own = q > 4;
+                                c[d] = ldcoef<TC, S>(at_elem_u(
+                                    st + (long long)sym_index<CEN>(gt, own ? q : 8 - q) * DS + pb,
+                                    own ? (unsigned)r : ce(q)));
+                            }
                         } else {
-                            c[d] = ldcoef<TC, S>(st + (long long)(26 - d) * DS + (long long)pl * P + r + off[q]);
+                            c[d] = ldcoef<TC, S>(
+                                at_elem_u(st + (long long)(26 - d) * DS + pb, ce(q)));
                         }
                     }
                 }
