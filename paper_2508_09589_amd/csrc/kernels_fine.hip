@@ -294,11 +294,13 @@ __global__ __launch_bounds__(256) void k_fine_apply(
     };
     auto mass = [&](const TC u[RY + 2][3], int m) -> TC {
         const TC cSW = ce[m][0], cSE = ce[m][1], cNW = ce[m + 1][0], cNE = ce[m + 1][1];
+        // the factor 2 goes onto the coefficient sums (the same exact
+        // scaling; with time-constant coefficients they are loop-invariant)
         TC v = (TC)4 * u[m + 1][1] * (cSW + cSE + cNW + cNE);
-        v += (TC)2 * u[m + 1][0] * (cSW + cNW);
-        v += (TC)2 * u[m + 1][2] * (cSE + cNE);
-        v += (TC)2 * u[m][1] * (cSW + cSE);
-        v += (TC)2 * u[m + 2][1] * (cNW + cNE);
+        v += u[m + 1][0] * ((TC)2 * (cSW + cNW));
+        v += u[m + 1][2] * ((TC)2 * (cSE + cNE));
+        v += u[m][1] * ((TC)2 * (cSW + cSE));
+        v += u[m + 2][1] * ((TC)2 * (cNW + cNE));
         v += cSW * u[m][0] + cSE * u[m][2] + cNW * u[m + 2][0] + cNE * u[m + 2][2];
         return v;
     };

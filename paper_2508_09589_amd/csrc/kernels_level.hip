@@ -98,8 +98,62 @@ static inline dim3 plane_grid(const Level& L) {
 // Restriction b_c = P_m^T r_f = P^T N_f r_f.  Space: coarse (I, J, n) gathers
 // fine (2I+a, 2J+c, n), a, c in {-1, 0, 1}, weight w(a) w(c) with w(0) = 1,
 // w(+-1) = 1/2.  Time: coarse (i, j, N) gathers fine (i, j, 2N+a).
+//
+// Space semi-coarsening, the common case and the one on the largest grids:
+// a thread takes one coarse node through TR_LV time levels at a time, all of
+// their loads issued before any sum (each level on its own would wait a
+// whole memory latency for a few bytes).  Loads are unconditional: a
+// neighbour outside the plane reads the centre and is not summed.  The sum
+// takes the terms in the same order as the definition, skipping the same
+// ones.
+constexpr int TR_LV = 2;
 template <typename T>
-__global__ void k_restrict(int how, int nxf, int nyf, int ntf, int nxc, int nyc, int ntc,
+__global__ void k_restrict_space(int nxf, int nyf, int nt, int nxc, int nyc, double inv_rowc,
+                                 const uint8_t* __restrict__ maskf, const T* __restrict__ rf,
+                                 T* __restrict__ bc) {
+    const int rowc = nxc + 1, Pc = rowc * (nyc + 1);
+    const long long rowf = nxf + 1, Pf = rowf * (nyf + 1);
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= Pc) return;
+    const int J = row_of(r, rowc, inv_rowc), I = r - J * rowc;
+    long long fo[9];   // in-plane index of fine neighbour q (the centre when outside)
+    unsigned in = 0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const int fj = 2 * J + q / 3 - 1, fi = 2 * I + q % 3 - 1;
+        const bool ok = fj >= 0 && fj <= nyf && fi >= 0 && fi <= nxf;
+        fo[q] = ok ? (long long)fj * rowf + fi : (long long)(2 * J) * rowf + 2 * I;
+        if (ok) in |= 1u << q;
+    }
+    for (int n0 = blockIdx.y * TR_LV; n0 <= nt; n0 += gridDim.y * TR_LV) {
+        T v[TR_LV][9];
+        uint8_t mk[TR_LV][9];
+#pragma unroll
+        for (int u = 0; u < TR_LV; ++u) {
+            const long long pf = (long long)min(n0 + u, nt) * Pf;   // past nt: not stored
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                v[u][q] = rf[pf + fo[q]];
+                mk[u][q] = maskf[pf + fo[q]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < TR_LV; ++u) {
+            if (n0 + u > nt) break;
+            double acc = 0.0;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const double w = (q / 3 == 1 ? 1.0 : 0.5) * (q % 3 == 1 ? 1.0 : 0.5);
+                if (((in >> q) & 1u) && !mk[u][q]) acc += w * (double)v[u][q];
+            }
+            bc[(long long)(n0 + u) * Pc + r] = (T)acc;
+        }
+    }
+}
+
+// Time semi-coarsening (how = 2) and full space-time coarsening (how = 3).
+template <typename T, int how>
+__global__ void k_restrict(int nxf, int nyf, int ntf, int nxc, int nyc, int ntc,
                            double inv_rowc, const uint8_t* __restrict__ maskf,
                            const T* __restrict__ rf, T* __restrict__ bc) {
     const int rowc = nxc + 1, Pc = rowc * (nyc + 1);
@@ -110,26 +164,13 @@ __global__ void k_restrict(int how, int nxf, int nyf, int ntf, int nxc, int nyc,
     for (int n = blockIdx.y; n <= ntc; n += gridDim.y) {
         const long long idx = (long long)n * Pc + r;
         double acc = 0.0;
-        if (how == 1) {
-            for (int c = -1; c <= 1; ++c) {
-                const int fj = 2 * J + c;
-                if (fj < 0 || fj > nyf) continue;
-                const double wc = c == 0 ? 1.0 : 0.5;
-                for (int a = -1; a <= 1; ++a) {
-                    const int fi = 2 * I + a;
-                    if (fi < 0 || fi > nxf) continue;
-                    const long long f = (long long)n * Pf + (long long)fj * rowf + fi;
-                    if (maskf[f]) continue;
-                    acc += wc * (a == 0 ? 1.0 : 0.5) * (double)rf[f];
-                }
-            }
-        } else if (how == 2) {
+        if (how == 2) {
             for (int a = -1; a <= 1; ++a) {
                 const int fn = 2 * n + a;
-                if (fn < 0 || fn > ntf) continue;
+                if (fn < 0 || fn > ntf) continue;   // uniform
                 const long long f = (long long)fn * Pf + r;
-                if (maskf[f]) continue;
-                acc += (a == 0 ? 1.0 : 0.5) * (double)rf[f];
+                const T v = rf[f];
+                if (!maskf[f]) acc += (a == 0 ? 1.0 : 0.5) * (double)v;
             }
         } else {   // full space-time coarsening: the product of both
             for (int d = -1; d <= 1; ++d) {
@@ -154,21 +195,95 @@ __global__ void k_restrict(int how, int nxf, int nyf, int ntf, int nxc, int nyc,
     }
 }
 
+// Grid of a transfer that takes lv time levels per thread and step.
+static inline dim3 level_grid(const Level& L, int lv) {
+    const long long P = (long long)(L.nx + 1) * (L.ny + 1);
+    const long long steps = (L.nt + 1 + lv - 1) / lv;
+    return dim3((unsigned)((P + 255) / 256), (unsigned)(steps < 65535 ? steps : 65535));
+}
+
 void launch_restrict(hipStream_t s, const Level& F, const Level& C, int prec, const void* rf,
                      void* bc) {
-    const dim3 grid = plane_grid(C);
     const double inv = 1.0 / (C.nx + 1);
-    if (prec == 0)
-        hipLaunchKernelGGL(k_restrict<double>, grid, dim3(256), 0, s, C.how, F.nx, F.ny, F.nt,
-                           C.nx, C.ny, C.nt, inv, F.mask, (const double*)rf, (double*)bc);
-    else
-        hipLaunchKernelGGL(k_restrict<float>, grid, dim3(256), 0, s, C.how, F.nx, F.ny, F.nt,
-                           C.nx, C.ny, C.nt, inv, F.mask, (const float*)rf, (float*)bc);
+    if (C.how == 1) {
+        const dim3 grid = level_grid(C, TR_LV);
+        if (prec == 0)
+            hipLaunchKernelGGL(k_restrict_space<double>, grid, dim3(256), 0, s, F.nx, F.ny, C.nt,
+                               C.nx, C.ny, inv, F.mask, (const double*)rf, (double*)bc);
+        else
+            hipLaunchKernelGGL(k_restrict_space<float>, grid, dim3(256), 0, s, F.nx, F.ny, C.nt,
+                               C.nx, C.ny, inv, F.mask, (const float*)rf, (float*)bc);
+        return;
+    }
+    const dim3 grid = plane_grid(C);
+#define RS_LAUNCH(T, H)                                                                         \
+    hipLaunchKernelGGL((k_restrict<T, H>), grid, dim3(256), 0, s, F.nx, F.ny, F.nt, C.nx, C.ny,  \
+                       C.nt, inv, F.mask, (const T*)rf, (T*)bc)
+    if (prec == 0) {
+        if (C.how == 2)
+            RS_LAUNCH(double, 2);
+        else
+            RS_LAUNCH(double, 3);
+    } else {
+        if (C.how == 2)
+            RS_LAUNCH(float, 2);
+        else
+            RS_LAUNCH(float, 3);
+    }
+#undef RS_LAUNCH
 }
 
 // Prolongation x_f (+)= P_m e_c: zero at fine Dirichlet nodes.
-template <typename T>
-__global__ void k_prolong(int how, int nxf, int nyf, int ntf, int nxc, int nyc, int ntc,
+//
+// Space semi-coarsening: as the restriction, TP_LV time levels per thread
+// and step with every load issued first; the four coarse neighbours are
+// loaded without a branch (a missing second one repeats the first) and the
+// parity cases selected afterwards.
+constexpr int TP_LV = 4;
+template <typename T, bool ACC>
+__global__ void k_prolong_space(int nxf, int nyf, int nt, int nxc, int nyc, double inv_rowf,
+                                const uint8_t* __restrict__ maskf, const T* __restrict__ ec,
+                                T* __restrict__ xf) {
+    const int rowf = nxf + 1, Pf = rowf * (nyf + 1);
+    const long long rowc = nxc + 1, Pc = rowc * (nyc + 1);
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= Pf) return;
+    const int j = row_of(r, rowf, inv_rowf), i = r - j * rowf;
+    const bool io = i & 1, jo = j & 1;
+    const long long c00 = (long long)(j >> 1) * rowc + (i >> 1);
+    const long long c01 = c00 + (io ? 1 : 0), c10 = c00 + (jo ? rowc : 0);
+    const long long c11 = c10 + (io ? 1 : 0);
+    for (int n0 = blockIdx.y * TP_LV; n0 <= nt; n0 += gridDim.y * TP_LV) {
+        T a[TP_LV][4], xo[TP_LV];
+        uint8_t mk[TP_LV];
+#pragma unroll
+        for (int u = 0; u < TP_LV; ++u) {
+            const int n = min(n0 + u, nt);   // past nt: not stored
+            const long long pc = (long long)n * Pc, idx = (long long)n * Pf + r;
+            a[u][0] = ec[pc + c00];
+            a[u][1] = ec[pc + c01];
+            a[u][2] = ec[pc + c10];
+            a[u][3] = ec[pc + c11];
+            mk[u] = maskf[idx];
+            xo[u] = ACC ? xf[idx] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < TP_LV; ++u) {
+            if (n0 + u > nt) break;
+            const double a00 = (double)a[u][0], a01 = (double)a[u][1];
+            const double a10 = (double)a[u][2], a11 = (double)a[u][3];
+            const double vx = 0.5 * (a00 + a01), vy = 0.5 * (a00 + a10);
+            const double vxy = 0.25 * (a00 + a01 + a10 + a11);
+            const double v = mk[u] ? 0.0 : (io ? (jo ? vxy : vx) : (jo ? vy : a00));
+            const long long idx = (long long)(n0 + u) * Pf + r;
+            xf[idx] = ACC ? (T)((double)xo[u] + v) : (T)v;
+        }
+    }
+}
+
+// Time semi-coarsening (how = 2) and full space-time coarsening (how = 3).
+template <typename T, int how>
+__global__ void k_prolong(int nxf, int nyf, int ntf, int nxc, int nyc, int ntc,
                           double inv_rowf, const uint8_t* __restrict__ maskf,
                           const T* __restrict__ ec, T* __restrict__ xf, int accumulate) {
     const int rowf = nxf + 1, Pf = rowf * (nyf + 1);
@@ -179,26 +294,9 @@ __global__ void k_prolong(int how, int nxf, int nyf, int ntf, int nxc, int nyc, 
     for (int n = blockIdx.y; n <= ntf; n += gridDim.y) {
         const long long idx = (long long)n * Pf + r;
         double v = 0.0;
-        if (!maskf[idx]) {
-            if (how == 1) {
-                const int i0 = i >> 1, j0 = j >> 1;
-                const bool io = i & 1, jo = j & 1;
-                const long long base = (long long)n * Pc;
-                if (!io && !jo) {
-                    v = (double)ec[base + (long long)j0 * rowc + i0];
-                } else if (io && !jo) {
-                    v = 0.5 * ((double)ec[base + (long long)j0 * rowc + i0] +
-                               (double)ec[base + (long long)j0 * rowc + i0 + 1]);
-                } else if (!io && jo) {
-                    v = 0.5 * ((double)ec[base + (long long)j0 * rowc + i0] +
-                               (double)ec[base + (long long)(j0 + 1) * rowc + i0]);
-                } else {
-                    v = 0.25 * ((double)ec[base + (long long)j0 * rowc + i0] +
-                                (double)ec[base + (long long)j0 * rowc + i0 + 1] +
-                                (double)ec[base + (long long)(j0 + 1) * rowc + i0] +
-                                (double)ec[base + (long long)(j0 + 1) * rowc + i0 + 1]);
-                }
-            } else if (how == 2) {
+        const bool dir = maskf[idx] != 0;
+        if (!dir) {
+            if (how == 2) {
                 const int n0 = n >> 1;
                 if (!(n & 1))
                     v = (double)ec[(long long)n0 * Pc + r];
@@ -225,16 +323,42 @@ __global__ void k_prolong(int how, int nxf, int nyf, int ntf, int nxc, int nyc, 
 
 void launch_prolong(hipStream_t s, const Level& F, const Level& C, int prec, const void* ec,
                     void* xf, int accumulate) {
-    const dim3 grid = plane_grid(F);
     const double inv = 1.0 / (F.nx + 1);
-    if (prec == 0)
-        hipLaunchKernelGGL(k_prolong<double>, grid, dim3(256), 0, s, C.how, F.nx, F.ny, F.nt,
-                           C.nx, C.ny, C.nt, inv, F.mask, (const double*)ec, (double*)xf,
-                           accumulate);
-    else
-        hipLaunchKernelGGL(k_prolong<float>, grid, dim3(256), 0, s, C.how, F.nx, F.ny, F.nt,
-                           C.nx, C.ny, C.nt, inv, F.mask, (const float*)ec, (float*)xf,
-                           accumulate);
+    if (C.how == 1) {
+        const dim3 grid = level_grid(F, TP_LV);
+#define PS_LAUNCH(T, A)                                                                        \
+    hipLaunchKernelGGL((k_prolong_space<T, A>), grid, dim3(256), 0, s, F.nx, F.ny, F.nt, C.nx,  \
+                       C.ny, inv, F.mask, (const T*)ec, (T*)xf)
+        if (prec == 0) {
+            if (accumulate)
+                PS_LAUNCH(double, true);
+            else
+                PS_LAUNCH(double, false);
+        } else {
+            if (accumulate)
+                PS_LAUNCH(float, true);
+            else
+                PS_LAUNCH(float, false);
+        }
+#undef PS_LAUNCH
+        return;
+    }
+    const dim3 grid = plane_grid(F);
+#define PL_LAUNCH(T, H)                                                                        \
+    hipLaunchKernelGGL((k_prolong<T, H>), grid, dim3(256), 0, s, F.nx, F.ny, F.nt, C.nx, C.ny,   \
+                       C.nt, inv, F.mask, (const T*)ec, (T*)xf, accumulate)
+    if (prec == 0) {
+        if (C.how == 2)
+            PL_LAUNCH(double, 2);
+        else
+            PL_LAUNCH(double, 3);
+    } else {
+        if (C.how == 2)
+            PL_LAUNCH(float, 2);
+        else
+            PL_LAUNCH(float, 3);
+    }
+#undef PL_LAUNCH
 }
 
 // Coarse Dirichlet mask: a coarse node is Dirichlet when every fine node in the
