@@ -28,14 +28,19 @@ __global__ __launch_bounds__(256) void k_stencil_march(
     const T* __restrict__ invd, const double* __restrict__ scale, const int* __restrict__ skip,
     int nchunk, int gx, int nblk, int per_xcd) {
     if (skip && *skip) return;
-    // Workgroup (node block bx, time chunk by).  per_xcd > 0: XCD-aware
-    // order -- hardware workgroup b runs on XCD b % 8, so each XCD takes a
-    // contiguous range of (bx, by) and the rows above and below a block,
-    // whose coefficients the symmetric form reads, come from the same L2.
-    const int bid = blockIdx.x;
-    const int lin = per_xcd > 0 ? (bid & 7) * per_xcd + (bid >> 3) : bid;
-    if (lin >= nblk) return;
-    const int by = lin / gx, bx = lin - by * gx;
+    // Workgroup (node block bx, time chunk by): the 2-D grid's, or with
+    // per_xcd > 0 an XCD-aware order over a 1-D grid -- hardware workgroup b
+    // runs on XCD b % 8, so each XCD takes a contiguous range of (bx, by) and
+    // the rows above and below a block, whose coefficients the symmetric
+    // form reads, come from the same L2.
+    int bx = blockIdx.x, by = blockIdx.y;
+    if (per_xcd > 0) {
+        const int bid = blockIdx.x;
+        const int lin = (bid & 7) * per_xcd + (bid >> 3);
+        if (lin >= nblk) return;
+        by = lin / gx;
+        bx = lin - by * gx;
+    }
     const int P = (nx + 1) * (ny + 1);
     const int r = bx * blockDim.x + threadIdx.x;
     if (r >= P) return;
@@ -69,7 +74,7 @@ static void stencil_dispatch(hipStream_t s, const Level& L, const S* st, int tra
     // grid 369 ms against 440)
     const bool tv = 2 * L.nplanes > L.nt + 1;
     const int per_xcd = tv ? (nblk + 7) / 8 : 0;
-    const dim3 grid(tv ? 8 * per_xcd : nblk);
+    const dim3 grid = tv ? dim3(8 * per_xcd) : dim3(gx, gy);
     if (trans)
         hipLaunchKernelGGL((k_stencil_march<T, S, TC, true>), grid, dim3(256), 0, s, L.nx, L.ny,
                            L.nt, L.nplanes, st, L.cen32, L.plane_map, (const T*)x, (T*)y,

@@ -127,62 +127,6 @@ __device__ __forceinline__ void stencil_march_rows(int nx, int ny, int nt, int n
         for (int q = 0; q < 9; ++q) u[q] = ((valid >> q) & 1u) ? (TC)xp[off[q]] : (TC)0;
     };
     TC xm[9], xc[9], xp[9], c[27];
-    // the 27 coefficients of row r at level n (planes pm, pc, pp of levels
-    // n-1, n, n+1; -1 past either end)
-    auto load_coefs = [&](int pm, int pc, int pp) {
-        if (!TRANS) {
-            const long long pb = (long long)pc * P;
-#pragma unroll
-            for (int g = 0; g < 3; ++g)
-#pragma unroll
-                for (int q = 0; q < 9; ++q) {
-                    if (SYM) {
-                        // row r's entry (g, q): stored at r for q >= 4,
-                        // the neighbour's (g, 8 - q) for q < 4
-                        if (CEN && q == 4) {
-                            c[g * 9 + q] = (TC)*at_elem_u(cen + (long long)g * DS + pb, (unsigned)r);
-                        } else {
-                            const int qs = q >= 4 ? q : 8 - q;
-                            c[g * 9 + q] = ldcoef<TC, S>(at_elem_u(
-                                st + (long long)sym_index<CEN>(g, qs) * DS + pb,
-                                q >= 4 ? (unsigned)r : ce(q)));
-                        }
-                    } else {
-                        c[g * 9 + q] = ldcoef<TC, S>(
-                            at_elem_u(st + (long long)(g * 9 + q) * DS + pb, (unsigned)r));
-                    }
-                }
-        } else {
-#pragma unroll
-            for (int dn = -1; dn <= 1; ++dn) {
-                // plane of level n + dn (plane 0 past either end, where
-                // the x level is zero)
-                const int pl = dn < 0 ? (pm < 0 ? 0 : pm) : (dn == 0 ? pc : (pp < 0 ? 0 : pp));
-                const long long pb = (long long)pl * P;
-                const int gt = 1 - dn;   // time-offset group of the row that points back
-#pragma unroll
-                for (int q = 0; q < 9; ++q) {
-                    const int d = (dn + 1) * 9 + q;
-                    // A^T(r, r + off_q) at offset dn = entry (gt, 8 - q) of
-                    // row r + off_q on level n + dn; in symmetric storage
-                    // that is entry (gt, q) of row r itself
-                    if (SYM) {
-                        if (CEN && q == 4) {
-                            c[d] = (TC)*at_elem_u(cen + (long long)gt * DS + pb, (unsigned)r);
-                        } else {
-                            const bool own = q > 4;
-                            c[d] = ldcoef<TC, S>(at_elem_u(
-                                st + (long long)sym_index<CEN>(gt, own ? q : 8 - q) * DS + pb,
-                                own ? (unsigned)r : ce(q)));
-                        }
-                    } else {
-                        c[d] = ldcoef<TC, S>(
-                            at_elem_u(st + (long long)(26 - d) * DS + pb, ce(q)));
-                    }
-                }
-            }
-        }
-    };
     load_plane(n0 - 1, xm);
     load_plane(n0, xc);
     int key0 = -2, key1 = -2, key2 = -2;
@@ -196,7 +140,58 @@ __device__ __forceinline__ void stencil_march_rows(int nx, int ny, int nt, int n
             key0 = pm;
             key1 = pc;
             key2 = pp;
-            load_coefs(pm, pc, pp);
+            if (!TRANS) {
+                const long long pb = (long long)pc * P;
+#pragma unroll
+                for (int g = 0; g < 3; ++g)
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) {
+                        if (SYM) {
+                            // row r's entry (g, q): stored at r for q >= 4,
+                            // the neighbour's (g, 8 - q) for q < 4
+                            if (CEN && q == 4) {
+                                c[g * 9 + q] = (TC)*at_elem_u(cen + (long long)g * DS + pb, (unsigned)r);
+                            } else {
+                                const int qs = q >= 4 ? q : 8 - q;
+                                c[g * 9 + q] = ldcoef<TC, S>(at_elem_u(
+                                    st + (long long)sym_index<CEN>(g, qs) * DS + pb,
+                                    q >= 4 ? (unsigned)r : ce(q)));
+                            }
+                        } else {
+                            c[g * 9 + q] = ldcoef<TC, S>(
+                                at_elem_u(st + (long long)(g * 9 + q) * DS + pb, (unsigned)r));
+                        }
+                    }
+            } else {
+#pragma unroll
+                for (int dn = -1; dn <= 1; ++dn) {
+                    // plane of level n + dn (plane 0 past either end, where
+                    // the x level is zero)
+                    const int pl = dn < 0 ? (pm < 0 ? 0 : pm) : (dn == 0 ? pc : (pp < 0 ? 0 : pp));
+                    const long long pb = (long long)pl * P;
+                    const int gt = 1 - dn;   // time-offset group of the row that points back
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) {
+                        const int d = (dn + 1) * 9 + q;
+                        // A^T(r, r + off_q) at offset dn = entry (gt, 8 - q) of
+                        // row r + off_q on level n + dn; in symmetric storage
+                        // that is entry (gt, q) of row r itself
+                        if (SYM) {
+                            if (CEN && q == 4) {
+                                c[d] = (TC)*at_elem_u(cen + (long long)gt * DS + pb, (unsigned)r);
+                            } else {
+                                const bool own = q > 4;
+                                c[d] = ldcoef<TC, S>(at_elem_u(
+                                    st + (long long)sym_index<CEN>(gt, own ? q : 8 - q) * DS + pb,
+                                    own ? (unsigned)r : ce(q)));
+                            }
+                        } else {
+                            c[d] = ldcoef<TC, S>(
+                                at_elem_u(st + (long long)(26 - d) * DS + pb, ce(q)));
+                        }
+                    }
+                }
+            }
         }
         TC acc = 0;
 #pragma unroll
