@@ -68,10 +68,10 @@ static void stencil_dispatch(hipStream_t s, const Level& L, const S* st, int tra
     const int gy = (L.nt + 1 + nchunk - 1) / nchunk;
     const int nblk = gx * gy;
     // XCD-aware order for operators whose coefficients change in time (every
-    // level reloads them, and neighbouring blocks share rows of them: medium
-    // grid 32 -> 29.5 ms of stencil applies per solve); a time-constant
-    // operator keeps the plain order, which measured faster there (large
-    // grid 369 ms against 440)
+    // level reloads them, and neighbouring blocks share rows of them: on a
+    // 256^2 x 256 hierarchy 32 -> 29.5 ms of stencil applies per solve); a
+    // time-constant operator keeps the plain order, which measured faster
+    // there (512^2 x 1024 hierarchy: 369 ms against 440)
     const bool tv = 2 * L.nplanes > L.nt + 1;
     const int per_xcd = tv ? (nblk + 7) / 8 : 0;
     const dim3 grid = tv ? dim3(8 * per_xcd) : dim3(gx, gy);
