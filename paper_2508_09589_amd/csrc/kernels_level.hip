@@ -57,14 +57,197 @@ __global__ __launch_bounds__(256) void k_stencil_march(
                                         });
 }
 
+// Lane l of the wave receives v of lane l - 1 (lane_prev) or l + 1
+// (lane_next); the lanes at the ends of the wave receive zero.  A DPP
+// whole-wave shift, no LDS.
+__device__ __forceinline__ float lane_prev(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float lane_next(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                 0x130, 0xf, 0xf, true));
+}
+
+// The forward FP32 apply with the in-plane neighbours taken from adjacent
+// lanes.  A wave covers 64 consecutive in-plane nodes and produces the 62
+// inside them (lanes 0 and 63 only load): per time level it loads three
+// node segments, one per grid row j-1, j, j+1, and the left and right
+// neighbours of a node are the values of the lanes beside it.  Consecutive
+// lanes hold consecutive in-plane indices, also across the end of a grid
+// row, so lane l +- 1 holds node r +- 1; where that is not a neighbour (i = 0
+// or i = nx, or a row outside the plane) the coefficient is set to zero at
+// load time, and a segment load outside the plane is clamped into it (a
+// finite value times zero).  Three loads per level instead of nine leave the
+// registers for loading two levels ahead: level k lives in register set
+// (k - n0 + 1) mod 4 from its load (two steps before its first use) to its
+// last use, and the loop is unrolled by four so that each set has a fixed
+// name.  x, b, invd and y go through buffer resources: a level outside
+// [0, nt] (or past the chunk) and the stores of the two loading-only lanes
+// take an offset past the resource's end, which reads zero and writes
+// nothing, so that no load or store sits behind a branch (a branch's join
+// makes the compiler wait for every load in flight, the ones ahead too).
+// Arrays up to 2 GiB (the offsets are 32-bit).  Same epilogue as
+// k_stencil_march; HB, HD: b and invd given.
+constexpr int SW_OUT = 62;
+constexpr unsigned SW_OOB = 0x80000000u;   // offset past the end of every resource here
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t lv_rsrc(const void* p, long long bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float lv_ld(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+template <typename S, bool HB, bool HD>
+__global__ __launch_bounds__(256) void k_stencil_wave(
+    int nx, int ny, int nt, int nplanes, const S* __restrict__ st, const float* __restrict__ cen,
+    const int* __restrict__ pmap, const float* __restrict__ x, float* __restrict__ y,
+    const float* __restrict__ b, const float* __restrict__ invd, const double* __restrict__ scale,
+    const int* __restrict__ skip, int nchunk, int gx, int nblk, int per_xcd) {
+    if (skip && *skip) return;
+    int bx = blockIdx.x, by = blockIdx.y;
+    if (per_xcd > 0) {
+        const int bid = blockIdx.x;
+        const int lin = (bid & 7) * per_xcd + (bid >> 3);
+        if (lin >= nblk) return;
+        by = lin / gx;
+        bx = lin - by * gx;
+    }
+    constexpr bool CEN = std::is_same<S, uint16_t>::value;
+    const int rowp = nx + 1;
+    const int P = rowp * (ny + 1);
+    const int lane = threadIdx.x & 63;
+    const int first = (bx * 4 + (int)(threadIdx.x >> 6)) * SW_OUT;   // first output node of the wave
+    if (first >= P) return;
+    const int n0 = by * nchunk;
+    if (n0 > nt) return;
+    const int n1 = min(n0 + nchunk, nt + 1);
+    const int rl = first + lane - 1;                 // this lane's node (-1 or >= P on halo lanes)
+    const bool out = lane >= 1 && lane <= SW_OUT && rl < P;
+    const int r = min(max(rl, 0), P - 1);            // in-plane node for coefficient, b, invd loads
+    const int j = r / rowp, i = r - j * rowp;
+    unsigned valid = 0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const int di = q % 3 - 1, dj = q / 3 - 1;
+        if (i + di >= 0 && i + di <= nx && j + dj >= 0 && j + dj <= ny) valid |= 1u << q;
+    }
+    const unsigned PB = (unsigned)P * 4u;            // bytes per level
+    unsigned seg[3];                                 // byte offset of the segment load per grid row
+#pragma unroll
+    for (int d = 0; d < 3; ++d) seg[d] = (unsigned)min(max(rl + (d - 1) * rowp, 0), P - 1) * 4u;
+    const unsigned rb = (unsigned)r * 4u;
+    const unsigned ob = out ? rb : SW_OOB;           // store offset within a level
+    const long long DS = (long long)P * nplanes;
+    const float sc = scale ? (float)(*scale) : 1.f;
+    const long long vbytes = (long long)(nt + 1) * P * 4;
+    const __amdgpu_buffer_rsrc_t xr = lv_rsrc(x, vbytes), yr = lv_rsrc(y, vbytes);
+    const __amdgpu_buffer_rsrc_t br = lv_rsrc(b, HB ? vbytes : 0), dr = lv_rsrc(invd, HD ? vbytes : 0);
+    // the chunk's plane indices, one per lane (nchunk <= 32), read back with
+    // readlane: a load of pmap[n] inside the loop would be a vector load whose
+    // wait also drains the levels loaded ahead
+    const int pml = n0 + lane < n1 ? pmap[n0 + lane] : 0;
+
+    // level k (zero outside [0, nt]; not needed past n1)
+    auto load_level = [&](int k, float (&u)[3]) {
+        const unsigned kb = (k >= 0 && k <= min(nt, n1)) ? (unsigned)k * PB : SW_OOB;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) u[d] = lv_ld(xr, kb + seg[d]);
+    };
+    float c[27];
+    auto load_coefs = [&](int pc) {
+        const long long pb = (long long)pc * P;
+#pragma unroll
+        for (int g = 0; g < 3; ++g)
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const int di = q % 3 - 1, dj = q / 3 - 1;
+                const bool ok = (valid >> q) & 1u;
+                float v;
+                if (CEN && q == 4) {
+                    v = *at_elem_u(cen + (long long)g * DS + pb, (unsigned)r);
+                } else {
+                    // row r's entry (g, q): stored at r for q >= 4, the
+                    // neighbour's (g, 8 - q) for q < 4
+                    const int qs = q >= 4 ? q : 8 - q;
+                    const unsigned e = q >= 4 ? (unsigned)r : (ok ? (unsigned)(r + dj * rowp + di) : (unsigned)r);
+                    v = ldcoef<float, S>(at_elem_u(st + (long long)sym_index<CEN>(g, qs) * DS + pb, e));
+                }
+                c[g * 9 + q] = ok ? v : 0.f;
+            }
+    };
+    auto row_sum = [&](const float* cg, const float (&u)[3], float acc) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            acc += cg[d * 3 + 0] * lane_prev(u[d]);
+            acc += cg[d * 3 + 1] * u[d];
+            acc += cg[d * 3 + 2] * lane_next(u[d]);
+        }
+        return acc;
+    };
+    int key = __builtin_amdgcn_readlane(pml, 0);
+    // the first level's coefficients before any x load is in flight (their
+    // waits would drain those loads)
+    load_coefs(key);
+    // step n: levels n - 1, n, n + 1 of x in A, B, C and b, invd of level n
+    // in bc, dc; level n + 2 of x goes into D, b and invd of level n + 1 into
+    // bn, dn.  The scheduling barrier keeps those loads ahead of the
+    // arithmetic, so that its waits leave them in flight.
+    auto step = [&](int n, const float (&A)[3], const float (&B)[3], const float (&C)[3],
+                    float (&D)[3], float bc, float dc, float& bn, float& dn) {
+        // steps past the chunk (n >= n1) keep the last plane, load nothing
+        // and store nothing
+        const int pc = __builtin_amdgcn_readlane(pml, min(n, n1 - 1) - n0);
+        if (pc != key) {
+            key = pc;
+            load_coefs(pc);
+        }
+        load_level(n + 2, D);
+        const unsigned nb = n + 1 < n1 ? (unsigned)(n + 1) * PB + rb : SW_OOB;
+        if (HB) bn = lv_ld(br, nb);
+        if (HD) dn = lv_ld(dr, nb);
+        __builtin_amdgcn_sched_barrier(0);
+        float acc = row_sum(c, A, 0.f);
+        acc = row_sum(c + 9, B, acc);
+        acc = row_sum(c + 18, C, acc);
+        float v = acc;
+        if (HB) v = bc - v;
+        if (HD) v *= dc;
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v * sc), yr,
+                                              out && n < n1 ? (unsigned)n * PB + rb : SW_OOB, 0, 0);
+    };
+    float R0[3], R1[3], R2[3], R3[3];
+    float b0 = 0.f, b1 = 0.f, d0 = 1.f, d1 = 1.f;
+    if (HB) b0 = lv_ld(br, (unsigned)n0 * PB + rb);
+    if (HD) d0 = lv_ld(dr, (unsigned)n0 * PB + rb);
+    load_level(n0 - 1, R0);
+    load_level(n0, R1);
+    load_level(n0 + 1, R2);
+    // no exit between the four steps: a load whose value only a later step
+    // uses would be moved behind such an exit, after the arithmetic
+    for (int n = n0; n < n1; n += 4) {
+        step(n, R0, R1, R2, R3, b0, d0, b1, d1);
+        step(n + 1, R1, R2, R3, R0, b1, d1, b0, d0);
+        step(n + 2, R2, R3, R0, R1, b0, d0, b1, d1);
+        step(n + 3, R3, R0, R1, R2, b1, d1, b0, d0);
+    }
+}
+
 template <typename T, typename S, typename TC>
 static void stencil_dispatch(hipStream_t s, const Level& L, const S* st, int trans, const void* x,
                              void* y, const void* b, const void* invd, const double* scale,
                              const int* skip) {
     const int P = (L.nx + 1) * (L.ny + 1);
-    const int gx = (P + 255) / 256;
+    // the FP32 forward apply runs as k_stencil_wave (4 x 62 nodes per block)
+    // where its 32-bit buffer offsets reach every level
+    const bool wave = std::is_same<T, float>::value && !trans &&
+                      (long long)(L.nt + 1) * P * 4 < (long long)SW_OOB;
+    const int gx = wave ? (P + 4 * SW_OUT - 1) / (4 * SW_OUT) : (P + 255) / 256;
     int nchunk = 32;
-    while (nchunk > 2 && (long long)gx * ((L.nt + 1 + nchunk - 1) / nchunk) < 2048) nchunk /= 2;
+    // (k_stencil_wave runs its levels four at a time)
+    while (nchunk > (wave ? 4 : 2) && (long long)gx * ((L.nt + 1 + nchunk - 1) / nchunk) < 2048)
+        nchunk /= 2;
     const int gy = (L.nt + 1 + nchunk - 1) / nchunk;
     const int nblk = gx * gy;
     // XCD-aware order for operators whose coefficients change in time (every
@@ -79,7 +262,20 @@ static void stencil_dispatch(hipStream_t s, const Level& L, const S* st, int tra
         hipLaunchKernelGGL((k_stencil_march<T, S, TC, true>), grid, dim3(256), 0, s, L.nx, L.ny,
                            L.nt, L.nplanes, st, L.cen32, L.plane_map, (const T*)x, (T*)y,
                            (const T*)b, (const T*)invd, scale, skip, nchunk, gx, nblk, per_xcd);
-    else
+    else if constexpr (std::is_same<T, float>::value) {
+        if (wave) {
+            auto kern = b ? (invd ? k_stencil_wave<S, true, true> : k_stencil_wave<S, true, false>)
+                          : (invd ? k_stencil_wave<S, false, true> : k_stencil_wave<S, false, false>);
+            hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, L.nx, L.ny, L.nt, L.nplanes, st,
+                               L.cen32, L.plane_map, (const float*)x, (float*)y, (const float*)b,
+                               (const float*)invd, scale, skip, nchunk, gx, nblk, per_xcd);
+        } else {
+            hipLaunchKernelGGL((k_stencil_march<T, S, TC, false>), grid, dim3(256), 0, s, L.nx,
+                               L.ny, L.nt, L.nplanes, st, L.cen32, L.plane_map, (const T*)x,
+                               (T*)y, (const T*)b, (const T*)invd, scale, skip, nchunk, gx, nblk,
+                               per_xcd);
+        }
+    } else
         hipLaunchKernelGGL((k_stencil_march<T, S, TC, false>), grid, dim3(256), 0, s, L.nx, L.ny,
                            L.nt, L.nplanes, st, L.cen32, L.plane_map, (const T*)x, (T*)y,
                            (const T*)b, (const T*)invd, scale, skip, nchunk, gx, nblk, per_xcd);
