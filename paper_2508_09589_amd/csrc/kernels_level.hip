@@ -73,7 +73,12 @@ __device__ __forceinline__ float lane_next(float v) {
 // lanes.  A wave covers 64 consecutive in-plane nodes and produces the 62
 // inside them (lanes 0 and 63 only load): per time level it loads three
 // node segments, one per grid row j-1, j, j+1, and the left and right
-// neighbours of a node are the values of the lanes beside it.  Consecutive
+// neighbours of a node are the values of the lanes beside it.  The
+// coefficient of row r for its left neighbour r - 1 is kept by lane l - 1
+// (moved there once, when the coefficients are loaded), which forms the
+// nine products with its own x values; one shift per level brings their sum
+// to lane l (the right neighbours likewise): two lane shifts per level
+// instead of one per product.  Consecutive
 // lanes hold consecutive in-plane indices, also across the end of a grid
 // row, so lane l +- 1 holds node r +- 1; where that is not a neighbour (i = 0
 // or i = nx, or a row outside the plane) the coefficient is set to zero at
@@ -144,7 +149,7 @@ __global__ __launch_bounds__(256) void k_stencil_wave(
     const long long vbytes = (long long)(nt + 1) * P * 4;
     const __amdgpu_buffer_rsrc_t xr = lv_rsrc(x, vbytes), yr = lv_rsrc(y, vbytes);
     const __amdgpu_buffer_rsrc_t br = lv_rsrc(b, HB ? vbytes : 0), dr = lv_rsrc(invd, HD ? vbytes : 0);
-    // the chunk's plane indices, one per lane (nchunk <= 32), read back with
+    // the chunk's plane indices, one per lane (nchunk <= 64), read back with
     // readlane: a load of pmap[n] inside the loop would be a vector load whose
     // wait also drains the levels loaded ahead
     const int pml = n0 + lane < n1 ? pmap[n0 + lane] : 0;
@@ -174,17 +179,21 @@ __global__ __launch_bounds__(256) void k_stencil_wave(
                     const unsigned e = q >= 4 ? (unsigned)r : (ok ? (unsigned)(r + dj * rowp + di) : (unsigned)r);
                     v = ldcoef<float, S>(at_elem_u(st + (long long)sym_index<CEN>(g, qs) * DS + pb, e));
                 }
-                c[g * 9 + q] = ok ? v : 0.f;
+                v = ok ? v : 0.f;
+                // a left-neighbour coefficient moves to the lane of that
+                // neighbour, a right-neighbour one likewise
+                c[g * 9 + q] = di < 0 ? lane_next(v) : (di > 0 ? lane_prev(v) : v);
             }
     };
-    auto row_sum = [&](const float* cg, const float (&u)[3], float acc) {
+    // sums over one level's three rows: the node's own column into acc, the
+    // products its left and right neighbours need into sl and sr
+    auto row_sum = [&](const float* cg, const float (&u)[3], float& acc, float& sl, float& sr) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            acc += cg[d * 3 + 0] * lane_prev(u[d]);
+            sl += cg[d * 3 + 0] * u[d];
             acc += cg[d * 3 + 1] * u[d];
-            acc += cg[d * 3 + 2] * lane_next(u[d]);
+            sr += cg[d * 3 + 2] * u[d];
         }
-        return acc;
     };
     int key = __builtin_amdgcn_readlane(pml, 0);
     // the first level's coefficients before any x load is in flight (their
@@ -208,10 +217,12 @@ __global__ __launch_bounds__(256) void k_stencil_wave(
         if (HB) bn = lv_ld(br, nb);
         if (HD) dn = lv_ld(dr, nb);
         __builtin_amdgcn_sched_barrier(0);
-        float acc = row_sum(c, A, 0.f);
-        acc = row_sum(c + 9, B, acc);
-        acc = row_sum(c + 18, C, acc);
-        float v = acc;
+        float acc = 0.f, sl = 0.f, sr = 0.f;
+        row_sum(c, A, acc, sl, sr);
+        row_sum(c + 9, B, acc, sl, sr);
+        row_sum(c + 18, C, acc, sl, sr);
+        // lane l - 1 holds the products with node r - 1 that row r needs
+        float v = acc + lane_prev(sl) + lane_next(sr);
         if (HB) v = bc - v;
         if (HD) v *= dc;
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v * sc), yr,
@@ -244,20 +255,24 @@ static void stencil_dispatch(hipStream_t s, const Level& L, const S* st, int tra
     const bool wave = std::is_same<T, float>::value && !trans &&
                       (long long)(L.nt + 1) * P * 4 < (long long)SW_OOB;
     const int gx = wave ? (P + 4 * SW_OUT - 1) / (4 * SW_OUT) : (P + 255) / 256;
-    int nchunk = 32;
-    // (k_stencil_wave runs its levels four at a time)
+    // (k_stencil_wave runs its levels four at a time; 64 levels per chunk
+    // rather than 32 drop half its extra loads at the chunk boundaries)
+    int nchunk = wave ? 64 : 32;
     while (nchunk > (wave ? 4 : 2) && (long long)gx * ((L.nt + 1 + nchunk - 1) / nchunk) < 2048)
         nchunk /= 2;
     const int gy = (L.nt + 1 + nchunk - 1) / nchunk;
     const int nblk = gx * gy;
-    // XCD-aware order for operators whose coefficients change in time (every
-    // level reloads them, and neighbouring blocks share rows of them: on a
-    // 256^2 x 256 hierarchy 32 -> 29.5 ms of stencil applies per solve); a
-    // time-constant operator keeps the plain order, which measured faster
-    // there (512^2 x 1024 hierarchy: 369 ms against 440)
+    // XCD-aware order (each XCD takes a contiguous range of blocks, so the
+    // grid rows above and below a block, which its neighbours read too, come
+    // from the same L2): for k_stencil_wave always (512^2 x 1024 hierarchy:
+    // 293 -> 271 ms of stencil applies per solve), for k_stencil_march where
+    // the coefficients change in time (every level reloads them, and
+    // neighbouring blocks share rows of them: on a 256^2 x 256 hierarchy 32 ->
+    // 29.5 ms per solve); a time-constant operator measured faster in the
+    // plain order with k_stencil_march (369 ms against 440)
     const bool tv = 2 * L.nplanes > L.nt + 1;
-    const int per_xcd = tv ? (nblk + 7) / 8 : 0;
-    const dim3 grid = tv ? dim3(8 * per_xcd) : dim3(gx, gy);
+    const int per_xcd = (tv || wave) ? (nblk + 7) / 8 : 0;
+    const dim3 grid = per_xcd > 0 ? dim3(8 * per_xcd) : dim3(gx, gy);
     if (trans)
         hipLaunchKernelGGL((k_stencil_march<T, S, TC, true>), grid, dim3(256), 0, s, L.nx, L.ny,
                            L.nt, L.nplanes, st, L.cen32, L.plane_map, (const T*)x, (T*)y,

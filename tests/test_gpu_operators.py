@@ -205,6 +205,37 @@ def test_mixed_precision_applies(torch_cuda, tv):
     p.close()
 
 
+@pytest.mark.parametrize("tv,bf16", [(False, False), (True, False), (True, True)])
+def test_stencil_apply_wide_planes(torch_cuda, tv, bf16):
+    """FP32 and BF16 coarse applies on planes that span several 64-lane waves
+    (the forward apply takes a node's in-plane neighbours from the lanes
+    beside it, 62 outputs per wave): planes of 713 and 192 nodes (11 full
+    waves and a ragged one; rows 31 and 16 nodes wide, so waves cross row
+    ends), 71 and 36 time levels (chunks of four with a ragged last one).
+    Forward and transposed against the oracle operator, under the BF16
+    storage model for BF16, 1e-5, and on a field that is non-zero on one
+    node only (every neighbour coefficient of that column in place)."""
+    import scipy.sparse as sp
+    c = Case(60, 44, 70, tv=tv, seed=21)
+    p = c.problem(precision="mixed", bf16_from_level=1 if bf16 else 0)
+    A, masks, Pm = c.ops
+    rng = np.random.default_rng(8)
+    assert len(c.levels) >= 4
+    for l in range(1, len(c.levels)):
+        Al = sp.csr_matrix(A[l])
+        P = (c.levels[l]["nx"] + 1) * (c.levels[l]["ny"] + 1)
+        x = rng.standard_normal(Al.shape[0])
+        e = np.zeros(Al.shape[0])
+        e[(c.levels[l]["nt"] // 2) * P + P // 2 + 7] = 1.0
+        for trans in (False, True):
+            Ab = _bf16_compensated(Al, P, by_column=trans) if bf16 else Al
+            for v in (x, e):
+                y = p.debug_apply(l, _t(v).reshape(p.level_shape(l)), transpose=trans, mixed=True)
+                ref = (Ab.T if trans else Ab) @ v
+                assert rel(y.cpu().numpy(), ref) < 1e-5, (l, trans, rel(y.cpu().numpy(), ref))
+    p.close()
+
+
 @pytest.mark.parametrize("level", [0, 1, 2])
 def test_smoother_matches_oracle_gmres(torch_cuda, level):
     """One Jacobi-GMRES smoothing (10 iterations, CGS, left Jacobi) on a level,
