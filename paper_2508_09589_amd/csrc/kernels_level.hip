@@ -104,7 +104,7 @@ __device__ __forceinline__ float lv_ld(__amdgpu_buffer_rsrc_t r, unsigned off) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 
-template <typename S, bool HB, bool HD>
+template <typename S, bool HB, bool HD, bool TRANS>
 __global__ __launch_bounds__(256) void k_stencil_wave(
     int nx, int ny, int nt, int nplanes, const S* __restrict__ st, const float* __restrict__ cen,
     const int* __restrict__ pmap, const float* __restrict__ x, float* __restrict__ y,
@@ -149,35 +149,51 @@ __global__ __launch_bounds__(256) void k_stencil_wave(
     const long long vbytes = (long long)(nt + 1) * P * 4;
     const __amdgpu_buffer_rsrc_t xr = lv_rsrc(x, vbytes), yr = lv_rsrc(y, vbytes);
     const __amdgpu_buffer_rsrc_t br = lv_rsrc(b, HB ? vbytes : 0), dr = lv_rsrc(invd, HD ? vbytes : 0);
-    // the chunk's plane indices, one per lane (nchunk <= 64), read back with
+    // the plane indices of the chunk's levels, one per lane, read back with
     // readlane: a load of pmap[n] inside the loop would be a vector load whose
-    // wait also drains the levels loaded ahead
-    const int pml = n0 + lane < n1 ? pmap[n0 + lane] : 0;
+    // wait also drains the levels loaded ahead.  The transpose also takes the
+    // levels before and after the chunk (nchunk + 2 <= 64); a level outside
+    // [0, nt] reads plane 0, whose numbers meet a zero x.
+    const int pl0 = TRANS ? n0 - 1 : n0;
+    const int pk = pl0 + lane;
+    const int pml = (pk < (TRANS ? n1 + 1 : n1) && pk >= 0 && pk <= nt) ? pmap[pk] : 0;
 
     // level k (zero outside [0, nt]; not needed past n1)
-    auto load_level = [&](int k, float (&u)[3]) {
+    auto load_level = [&](int k, float (&u)[3]) __attribute__((always_inline)) {
         const unsigned kb = (k >= 0 && k <= min(nt, n1)) ? (unsigned)k * PB : SW_OOB;
 #pragma unroll
         for (int d = 0; d < 3; ++d) u[d] = lv_ld(xr, kb + seg[d]);
     };
     float c[27];
-    auto load_coefs = [&](int pc) {
-        const long long pb = (long long)pc * P;
+    // c[(dn + 1) * 9 + q] multiplies x at level n + dn, in-plane node r + off_q.
+    // Forward: entry (dn + 1, q) of row r on level n's plane pc.  Transpose:
+    // entry (1 - dn, 8 - q) of row r + off_q on level n + dn's plane (pm, pc,
+    // pp); in symmetric storage that is entry (1 - dn, q) of row r itself
+    // for q > 4.
+    auto load_coefs = [&](int pm, int pc, int pp) __attribute__((always_inline)) {
 #pragma unroll
         for (int g = 0; g < 3; ++g)
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
                 const int di = q % 3 - 1, dj = q / 3 - 1;
                 const bool ok = (valid >> q) & 1u;
+                const unsigned nb = ok ? (unsigned)(r + dj * rowp + di) : (unsigned)r;
+                const int gs = TRANS ? 2 - g : g;
+                const long long pb = (long long)(TRANS ? (g == 0 ? pm : (g == 1 ? pc : pp)) : pc) * P;
                 float v;
                 if (CEN && q == 4) {
-                    v = *at_elem_u(cen + (long long)g * DS + pb, (unsigned)r);
-                } else {
+                    v = *at_elem_u(cen + (long long)gs * DS + pb, (unsigned)r);
+                } else if (!TRANS) {
                     // row r's entry (g, q): stored at r for q >= 4, the
                     // neighbour's (g, 8 - q) for q < 4
                     const int qs = q >= 4 ? q : 8 - q;
-                    const unsigned e = q >= 4 ? (unsigned)r : (ok ? (unsigned)(r + dj * rowp + di) : (unsigned)r);
-                    v = ldcoef<float, S>(at_elem_u(st + (long long)sym_index<CEN>(g, qs) * DS + pb, e));
+                    v = ldcoef<float, S>(at_elem_u(st + (long long)sym_index<CEN>(gs, qs) * DS + pb,
+                                                   q >= 4 ? (unsigned)r : nb));
+                } else {
+                    const bool own = q > 4;
+                    v = ldcoef<float, S>(at_elem_u(
+                        st + (long long)sym_index<CEN>(gs, own ? q : 8 - q) * DS + pb,
+                        own ? (unsigned)r : nb));
                 }
                 v = ok ? v : 0.f;
                 // a left-neighbour coefficient moves to the lane of that
@@ -187,7 +203,8 @@ __global__ __launch_bounds__(256) void k_stencil_wave(
     };
     // sums over one level's three rows: the node's own column into acc, the
     // products its left and right neighbours need into sl and sr
-    auto row_sum = [&](const float* cg, const float (&u)[3], float& acc, float& sl, float& sr) {
+    auto row_sum = [&](const float* cg, const float (&u)[3], float& acc, float& sl, float& sr)
+        __attribute__((always_inline)) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             sl += cg[d * 3 + 0] * u[d];
@@ -195,22 +212,37 @@ __global__ __launch_bounds__(256) void k_stencil_wave(
             sr += cg[d * 3 + 2] * u[d];
         }
     };
-    int key = __builtin_amdgcn_readlane(pml, 0);
+    int key = __builtin_amdgcn_readlane(pml, 0), keyc = 0, keyp = 0;
+    if (TRANS) {
+        keyc = __builtin_amdgcn_readlane(pml, 1);
+        keyp = __builtin_amdgcn_readlane(pml, 2);
+    }
     // the first level's coefficients before any x load is in flight (their
     // waits would drain those loads)
-    load_coefs(key);
+    load_coefs(key, TRANS ? keyc : key, keyp);
     // step n: levels n - 1, n, n + 1 of x in A, B, C and b, invd of level n
     // in bc, dc; level n + 2 of x goes into D, b and invd of level n + 1 into
     // bn, dn.  The scheduling barrier keeps those loads ahead of the
     // arithmetic, so that its waits leave them in flight.
     auto step = [&](int n, const float (&A)[3], const float (&B)[3], const float (&C)[3],
-                    float (&D)[3], float bc, float dc, float& bn, float& dn) {
-        // steps past the chunk (n >= n1) keep the last plane, load nothing
+                    float (&D)[3], float bc, float dc, float& bn, float& dn)
+        __attribute__((always_inline)) {
+        // steps past the chunk (n >= n1) keep the last planes, load nothing
         // and store nothing
-        const int pc = __builtin_amdgcn_readlane(pml, min(n, n1 - 1) - n0);
-        if (pc != key) {
-            key = pc;
-            load_coefs(pc);
+        const int i0 = min(n, n1 - 1) - n0;
+        const int p0 = __builtin_amdgcn_readlane(pml, i0);
+        if (TRANS) {
+            const int p1 = __builtin_amdgcn_readlane(pml, i0 + 1);
+            const int p2 = __builtin_amdgcn_readlane(pml, i0 + 2);
+            if (p0 != key || p1 != keyc || p2 != keyp) {
+                key = p0;
+                keyc = p1;
+                keyp = p2;
+                load_coefs(p0, p1, p2);
+            }
+        } else if (p0 != key) {
+            key = p0;
+            load_coefs(p0, p0, p0);
         }
         load_level(n + 2, D);
         const unsigned nb = n + 1 < n1 ? (unsigned)(n + 1) * PB + rb : SW_OOB;
@@ -250,14 +282,15 @@ static void stencil_dispatch(hipStream_t s, const Level& L, const S* st, int tra
                              void* y, const void* b, const void* invd, const double* scale,
                              const int* skip) {
     const int P = (L.nx + 1) * (L.ny + 1);
-    // the FP32 forward apply runs as k_stencil_wave (4 x 62 nodes per block)
-    // where its 32-bit buffer offsets reach every level
-    const bool wave = std::is_same<T, float>::value && !trans &&
+    // FP32 applies run as k_stencil_wave (4 x 62 nodes per block) where its
+    // 32-bit buffer offsets reach every level
+    const bool wave = std::is_same<T, float>::value &&
                       (long long)(L.nt + 1) * P * 4 < (long long)SW_OOB;
     const int gx = wave ? (P + 4 * SW_OUT - 1) / (4 * SW_OUT) : (P + 255) / 256;
     // (k_stencil_wave runs its levels four at a time; 64 levels per chunk
-    // rather than 32 drop half its extra loads at the chunk boundaries)
-    int nchunk = wave ? 64 : 32;
+    // rather than 32 drop half its extra loads at the chunk boundaries; its
+    // transpose keeps the planes of nchunk + 2 levels in one register)
+    int nchunk = wave && !trans ? 64 : 32;
     while (nchunk > (wave ? 4 : 2) && (long long)gx * ((L.nt + 1 + nchunk - 1) / nchunk) < 2048)
         nchunk /= 2;
     const int gy = (L.nt + 1 + nchunk - 1) / nchunk;
@@ -273,24 +306,25 @@ static void stencil_dispatch(hipStream_t s, const Level& L, const S* st, int tra
     const bool tv = 2 * L.nplanes > L.nt + 1;
     const int per_xcd = (tv || wave) ? (nblk + 7) / 8 : 0;
     const dim3 grid = per_xcd > 0 ? dim3(8 * per_xcd) : dim3(gx, gy);
+    if constexpr (std::is_same<T, float>::value) {
+        if (wave) {
+            auto pick = [&](auto tr) {
+                constexpr bool TR = decltype(tr)::value;
+                return b ? (invd ? k_stencil_wave<S, true, true, TR> : k_stencil_wave<S, true, false, TR>)
+                         : (invd ? k_stencil_wave<S, false, true, TR> : k_stencil_wave<S, false, false, TR>);
+            };
+            auto kern = trans ? pick(std::true_type{}) : pick(std::false_type{});
+            hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, L.nx, L.ny, L.nt, L.nplanes, st,
+                               L.cen32, L.plane_map, (const float*)x, (float*)y, (const float*)b,
+                               (const float*)invd, scale, skip, nchunk, gx, nblk, per_xcd);
+            return;
+        }
+    }
     if (trans)
         hipLaunchKernelGGL((k_stencil_march<T, S, TC, true>), grid, dim3(256), 0, s, L.nx, L.ny,
                            L.nt, L.nplanes, st, L.cen32, L.plane_map, (const T*)x, (T*)y,
                            (const T*)b, (const T*)invd, scale, skip, nchunk, gx, nblk, per_xcd);
-    else if constexpr (std::is_same<T, float>::value) {
-        if (wave) {
-            auto kern = b ? (invd ? k_stencil_wave<S, true, true> : k_stencil_wave<S, true, false>)
-                          : (invd ? k_stencil_wave<S, false, true> : k_stencil_wave<S, false, false>);
-            hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, L.nx, L.ny, L.nt, L.nplanes, st,
-                               L.cen32, L.plane_map, (const float*)x, (float*)y, (const float*)b,
-                               (const float*)invd, scale, skip, nchunk, gx, nblk, per_xcd);
-        } else {
-            hipLaunchKernelGGL((k_stencil_march<T, S, TC, false>), grid, dim3(256), 0, s, L.nx,
-                               L.ny, L.nt, L.nplanes, st, L.cen32, L.plane_map, (const T*)x,
-                               (T*)y, (const T*)b, (const T*)invd, scale, skip, nchunk, gx, nblk,
-                               per_xcd);
-        }
-    } else
+    else
         hipLaunchKernelGGL((k_stencil_march<T, S, TC, false>), grid, dim3(256), 0, s, L.nx, L.ny,
                            L.nt, L.nplanes, st, L.cen32, L.plane_map, (const T*)x, (T*)y,
                            (const T*)b, (const T*)invd, scale, skip, nchunk, gx, nblk, per_xcd);
