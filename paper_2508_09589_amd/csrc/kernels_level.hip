@@ -69,25 +69,25 @@ __device__ __forceinline__ float lane_next(float v) {
                                                                  0x130, 0xf, 0xf, true));
 }
 
-// The forward FP32 apply with the in-plane neighbours taken from adjacent
-// lanes.  A wave covers 64 consecutive in-plane nodes and produces the 62
-// inside them (lanes 0 and 63 only load): per time level it loads three
-// node segments, one per grid row j-1, j, j+1, and the left and right
-// neighbours of a node are the values of the lanes beside it.  The
-// coefficient of row r for its left neighbour r - 1 is kept by lane l - 1
-// (moved there once, when the coefficients are loaded), which forms the
-// nine products with its own x values; one shift per level brings their sum
-// to lane l (the right neighbours likewise): two lane shifts per level
-// instead of one per product.  Consecutive
-// lanes hold consecutive in-plane indices, also across the end of a grid
-// row, so lane l +- 1 holds node r +- 1; where that is not a neighbour (i = 0
-// or i = nx, or a row outside the plane) the coefficient is set to zero at
-// load time, and a segment load outside the plane is clamped into it (a
-// finite value times zero).  Three loads per level instead of nine leave the
-// registers for loading two levels ahead: level k lives in register set
-// (k - n0 + 1) mod 4 from its load (two steps before its first use) to its
-// last use, and the loop is unrolled by four so that each set has a fixed
-// name.  x, b, invd and y go through buffer resources: a level outside
+// FP32 apply (TRANS: transposed apply) with the in-plane neighbours taken
+// from adjacent lanes.  A wave covers 64 consecutive in-plane nodes and
+// produces the 62 inside them (lanes 0 and 63 only load): per time level it
+// loads three node segments, one per grid row j-1, j, j+1.  Consecutive lanes
+// hold consecutive in-plane indices, also across the end of a grid row, so
+// lane l +- 1 holds node r +- 1; where that is not a neighbour (i = 0 or
+// i = nx, or a row outside the plane) the coefficient is set to zero at load
+// time, and a segment load outside the plane is clamped into it (a finite
+// value times zero).  The coefficient of row r for its left neighbour r - 1
+// is kept by lane l - 1 (moved there once, when the coefficients are
+// loaded), which forms the nine products with its own x values; one shift
+// per level brings their sum to lane l (the right neighbours likewise): two
+// lane shifts per level instead of one per product.
+//
+// Three loads per level instead of nine leave the registers for loading x
+// two levels ahead (b and invd one level ahead): level k lives in register
+// set (k - n0 + 1) mod 4 from its load (two steps before its first use) to
+// its last use, and the loop is unrolled by four so that each set has a
+// fixed name.  x, b, invd and y go through buffer resources: a level outside
 // [0, nt] (or past the chunk) and the stores of the two loading-only lanes
 // take an offset past the resource's end, which reads zero and writes
 // nothing, so that no load or store sits behind a branch (a branch's join

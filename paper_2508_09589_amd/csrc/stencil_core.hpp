@@ -1,5 +1,6 @@
-// 27-point stencil rows of a coarse level, shared by the stand-alone stencil
-// apply and the fused smoother kernels.
+// 27-point stencil rows of a coarse level: the row march of the FP64 stencil
+// apply and of the fused small-level smoother kernels (the stand-alone FP32
+// applies take the wave form, k_stencil_wave).
 //
 // Stencil layout: st[d][plane][j][i], d = (dn+1)*9 + (dj+1)*3 + (di+1) holds
 // A(node, node + (di, dj, dn)); plane = plane_map[n] so that time levels with
