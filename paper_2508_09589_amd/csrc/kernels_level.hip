@@ -68,6 +68,21 @@ __device__ __forceinline__ float lane_next(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
                                                                  0x130, 0xf, 0xf, true));
 }
+// The same for FP64 values: both 32-bit halves shifted.
+__device__ __forceinline__ double lane_prev(double v) {
+    typedef int i32x2 __attribute__((ext_vector_type(2)));
+    i32x2 h = __builtin_bit_cast(i32x2, v);
+    h.x = __builtin_amdgcn_update_dpp(0, h.x, 0x138, 0xf, 0xf, true);
+    h.y = __builtin_amdgcn_update_dpp(0, h.y, 0x138, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, h);
+}
+__device__ __forceinline__ double lane_next(double v) {
+    typedef int i32x2 __attribute__((ext_vector_type(2)));
+    i32x2 h = __builtin_bit_cast(i32x2, v);
+    h.x = __builtin_amdgcn_update_dpp(0, h.x, 0x130, 0xf, 0xf, true);
+    h.y = __builtin_amdgcn_update_dpp(0, h.y, 0x130, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, h);
+}
 
 // FP32 apply (TRANS: transposed apply) with the in-plane neighbours taken
 // from adjacent lanes.  A wave covers 64 consecutive in-plane nodes and
@@ -100,15 +115,26 @@ constexpr unsigned SW_OOB = 0x80000000u;   // offset past the end of every resou
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t lv_rsrc(const void* p, long long bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
-__device__ __forceinline__ float lv_ld(__amdgpu_buffer_rsrc_t r, unsigned off) {
+template <typename T> __device__ __forceinline__ T lv_ld(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <> __device__ __forceinline__ float lv_ld<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
+template <> __device__ __forceinline__ double lv_ld<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void lv_st(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void lv_st(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
 
-template <typename S, bool HB, bool HD, bool TRANS>
+template <typename T, typename S, bool HB, bool HD, bool TRANS>
 __global__ __launch_bounds__(256) void k_stencil_wave(
     int nx, int ny, int nt, int nplanes, const S* __restrict__ st, const float* __restrict__ cen,
-    const int* __restrict__ pmap, const float* __restrict__ x, float* __restrict__ y,
-    const float* __restrict__ b, const float* __restrict__ invd, const double* __restrict__ scale,
+    const int* __restrict__ pmap, const T* __restrict__ x, T* __restrict__ y,
+    const T* __restrict__ b, const T* __restrict__ invd, const double* __restrict__ scale,
     const int* __restrict__ skip, int nchunk, int gx, int nblk, int per_xcd) {
     if (skip && *skip) return;
     int bx = blockIdx.x, by = blockIdx.y;
@@ -120,6 +146,8 @@ __global__ __launch_bounds__(256) void k_stencil_wave(
         bx = lin - by * gx;
     }
     constexpr bool CEN = std::is_same<S, uint16_t>::value;
+    constexpr bool SYM = !std::is_same<S, double>::value;   // symmetric (15- or 12-entry) storage
+    constexpr unsigned ES = sizeof(T);
     const int rowp = nx + 1;
     const int P = rowp * (ny + 1);
     const int lane = threadIdx.x & 63;
@@ -138,15 +166,15 @@ __global__ __launch_bounds__(256) void k_stencil_wave(
         const int di = q % 3 - 1, dj = q / 3 - 1;
         if (i + di >= 0 && i + di <= nx && j + dj >= 0 && j + dj <= ny) valid |= 1u << q;
     }
-    const unsigned PB = (unsigned)P * 4u;            // bytes per level
+    const unsigned PB = (unsigned)P * ES;            // bytes per level
     unsigned seg[3];                                 // byte offset of the segment load per grid row
 #pragma unroll
-    for (int d = 0; d < 3; ++d) seg[d] = (unsigned)min(max(rl + (d - 1) * rowp, 0), P - 1) * 4u;
-    const unsigned rb = (unsigned)r * 4u;
+    for (int d = 0; d < 3; ++d) seg[d] = (unsigned)min(max(rl + (d - 1) * rowp, 0), P - 1) * ES;
+    const unsigned rb = (unsigned)r * ES;
     const unsigned ob = out ? rb : SW_OOB;           // store offset within a level
     const long long DS = (long long)P * nplanes;
-    const float sc = scale ? (float)(*scale) : 1.f;
-    const long long vbytes = (long long)(nt + 1) * P * 4;
+    const T sc = scale ? (T)(*scale) : (T)1;
+    const long long vbytes = (long long)(nt + 1) * P * ES;
     const __amdgpu_buffer_rsrc_t xr = lv_rsrc(x, vbytes), yr = lv_rsrc(y, vbytes);
     const __amdgpu_buffer_rsrc_t br = lv_rsrc(b, HB ? vbytes : 0), dr = lv_rsrc(invd, HD ? vbytes : 0);
     // the plane indices of the chunk's levels, one per lane, read back with
@@ -159,17 +187,18 @@ __global__ __launch_bounds__(256) void k_stencil_wave(
     const int pml = (pk < (TRANS ? n1 + 1 : n1) && pk >= 0 && pk <= nt) ? pmap[pk] : 0;
 
     // level k (zero outside [0, nt]; not needed past n1)
-    auto load_level = [&](int k, float (&u)[3]) __attribute__((always_inline)) {
+    auto load_level = [&](int k, T (&u)[3]) __attribute__((always_inline)) {
         const unsigned kb = (k >= 0 && k <= min(nt, n1)) ? (unsigned)k * PB : SW_OOB;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) u[d] = lv_ld(xr, kb + seg[d]);
+        for (int d = 0; d < 3; ++d) u[d] = lv_ld<T>(xr, kb + seg[d]);
     };
-    float c[27];
+    T c[27];
     // c[(dn + 1) * 9 + q] multiplies x at level n + dn, in-plane node r + off_q.
     // Forward: entry (dn + 1, q) of row r on level n's plane pc.  Transpose:
     // entry (1 - dn, 8 - q) of row r + off_q on level n + dn's plane (pm, pc,
     // pp); in symmetric storage that is entry (1 - dn, q) of row r itself
-    // for q > 4.
+    // for q > 4.  FP64 storage holds all 27 entries of every row: the
+    // transpose reads entry 26 - ((dn + 1) * 9 + q) of row r + off_q.
     auto load_coefs = [&](int pm, int pc, int pp) __attribute__((always_inline)) {
 #pragma unroll
         for (int g = 0; g < 3; ++g)
@@ -180,22 +209,25 @@ __global__ __launch_bounds__(256) void k_stencil_wave(
                 const unsigned nb = ok ? (unsigned)(r + dj * rowp + di) : (unsigned)r;
                 const int gs = TRANS ? 2 - g : g;
                 const long long pb = (long long)(TRANS ? (g == 0 ? pm : (g == 1 ? pc : pp)) : pc) * P;
-                float v;
-                if (CEN && q == 4) {
+                T v;
+                if (!SYM) {
+                    const int dd = TRANS ? 26 - (g * 9 + q) : g * 9 + q;
+                    v = ldcoef<T, S>(at_elem_u(st + (long long)dd * DS + pb, TRANS ? nb : (unsigned)r));
+                } else if (CEN && q == 4) {
                     v = *at_elem_u(cen + (long long)gs * DS + pb, (unsigned)r);
                 } else if (!TRANS) {
                     // row r's entry (g, q): stored at r for q >= 4, the
                     // neighbour's (g, 8 - q) for q < 4
                     const int qs = q >= 4 ? q : 8 - q;
-                    v = ldcoef<float, S>(at_elem_u(st + (long long)sym_index<CEN>(gs, qs) * DS + pb,
-                                                   q >= 4 ? (unsigned)r : nb));
+                    v = ldcoef<T, S>(at_elem_u(st + (long long)sym_index<CEN>(gs, qs) * DS + pb,
+                                               q >= 4 ? (unsigned)r : nb));
                 } else {
                     const bool own = q > 4;
-                    v = ldcoef<float, S>(at_elem_u(
+                    v = ldcoef<T, S>(at_elem_u(
                         st + (long long)sym_index<CEN>(gs, own ? q : 8 - q) * DS + pb,
                         own ? (unsigned)r : nb));
                 }
-                v = ok ? v : 0.f;
+                v = ok ? v : (T)0;
                 // a left-neighbour coefficient moves to the lane of that
                 // neighbour, a right-neighbour one likewise
                 c[g * 9 + q] = di < 0 ? lane_next(v) : (di > 0 ? lane_prev(v) : v);
@@ -203,7 +235,7 @@ __global__ __launch_bounds__(256) void k_stencil_wave(
     };
     // sums over one level's three rows: the node's own column into acc, the
     // products its left and right neighbours need into sl and sr
-    auto row_sum = [&](const float* cg, const float (&u)[3], float& acc, float& sl, float& sr)
+    auto row_sum = [&](const T* cg, const T (&u)[3], T& acc, T& sl, T& sr)
         __attribute__((always_inline)) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -224,8 +256,8 @@ __global__ __launch_bounds__(256) void k_stencil_wave(
     // in bc, dc; level n + 2 of x goes into D, b and invd of level n + 1 into
     // bn, dn.  The scheduling barrier keeps those loads ahead of the
     // arithmetic, so that its waits leave them in flight.
-    auto step = [&](int n, const float (&A)[3], const float (&B)[3], const float (&C)[3],
-                    float (&D)[3], float bc, float dc, float& bn, float& dn)
+    auto step = [&](int n, const T (&A)[3], const T (&B)[3], const T (&C)[3], T (&D)[3], T bc,
+                    T dc, T& bn, T& dn)
         __attribute__((always_inline)) {
         // steps past the chunk (n >= n1) keep the last planes, load nothing
         // and store nothing
@@ -246,24 +278,23 @@ __global__ __launch_bounds__(256) void k_stencil_wave(
         }
         load_level(n + 2, D);
         const unsigned nb = n + 1 < n1 ? (unsigned)(n + 1) * PB + rb : SW_OOB;
-        if (HB) bn = lv_ld(br, nb);
-        if (HD) dn = lv_ld(dr, nb);
+        if (HB) bn = lv_ld<T>(br, nb);
+        if (HD) dn = lv_ld<T>(dr, nb);
         __builtin_amdgcn_sched_barrier(0);
-        float acc = 0.f, sl = 0.f, sr = 0.f;
+        T acc = 0, sl = 0, sr = 0;
         row_sum(c, A, acc, sl, sr);
         row_sum(c + 9, B, acc, sl, sr);
         row_sum(c + 18, C, acc, sl, sr);
         // lane l - 1 holds the products with node r - 1 that row r needs
-        float v = acc + lane_prev(sl) + lane_next(sr);
+        T v = acc + lane_prev(sl) + lane_next(sr);
         if (HB) v = bc - v;
         if (HD) v *= dc;
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v * sc), yr,
-                                              out && n < n1 ? (unsigned)n * PB + rb : SW_OOB, 0, 0);
+        lv_st(v * sc, yr, out && n < n1 ? (unsigned)n * PB + rb : SW_OOB);
     };
-    float R0[3], R1[3], R2[3], R3[3];
-    float b0 = 0.f, b1 = 0.f, d0 = 1.f, d1 = 1.f;
-    if (HB) b0 = lv_ld(br, (unsigned)n0 * PB + rb);
-    if (HD) d0 = lv_ld(dr, (unsigned)n0 * PB + rb);
+    T R0[3], R1[3], R2[3], R3[3];
+    T b0 = 0, b1 = 0, d0 = 1, d1 = 1;
+    if (HB) b0 = lv_ld<T>(br, (unsigned)n0 * PB + rb);
+    if (HD) d0 = lv_ld<T>(dr, (unsigned)n0 * PB + rb);
     load_level(n0 - 1, R0);
     load_level(n0, R1);
     load_level(n0 + 1, R2);
@@ -282,10 +313,9 @@ static void stencil_dispatch(hipStream_t s, const Level& L, const S* st, int tra
                              void* y, const void* b, const void* invd, const double* scale,
                              const int* skip) {
     const int P = (L.nx + 1) * (L.ny + 1);
-    // FP32 applies run as k_stencil_wave (4 x 62 nodes per block) where its
+    // applies run as k_stencil_wave (4 x 62 nodes per block) where its
     // 32-bit buffer offsets reach every level
-    const bool wave = std::is_same<T, float>::value &&
-                      (long long)(L.nt + 1) * P * 4 < (long long)SW_OOB;
+    const bool wave = (long long)(L.nt + 1) * P * (long long)sizeof(T) < (long long)SW_OOB;
     const int gx = wave ? (P + 4 * SW_OUT - 1) / (4 * SW_OUT) : (P + 255) / 256;
     // (k_stencil_wave runs its levels four at a time; 64 levels per chunk
     // rather than 32 drop half its extra loads at the chunk boundaries; its
@@ -306,19 +336,17 @@ static void stencil_dispatch(hipStream_t s, const Level& L, const S* st, int tra
     const bool tv = 2 * L.nplanes > L.nt + 1;
     const int per_xcd = (tv || wave) ? (nblk + 7) / 8 : 0;
     const dim3 grid = per_xcd > 0 ? dim3(8 * per_xcd) : dim3(gx, gy);
-    if constexpr (std::is_same<T, float>::value) {
-        if (wave) {
-            auto pick = [&](auto tr) {
-                constexpr bool TR = decltype(tr)::value;
-                return b ? (invd ? k_stencil_wave<S, true, true, TR> : k_stencil_wave<S, true, false, TR>)
-                         : (invd ? k_stencil_wave<S, false, true, TR> : k_stencil_wave<S, false, false, TR>);
-            };
-            auto kern = trans ? pick(std::true_type{}) : pick(std::false_type{});
-            hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, L.nx, L.ny, L.nt, L.nplanes, st,
-                               L.cen32, L.plane_map, (const float*)x, (float*)y, (const float*)b,
-                               (const float*)invd, scale, skip, nchunk, gx, nblk, per_xcd);
-            return;
-        }
+    if (wave) {
+        auto pick = [&](auto tr) {
+            constexpr bool TR = decltype(tr)::value;
+            return b ? (invd ? k_stencil_wave<T, S, true, true, TR> : k_stencil_wave<T, S, true, false, TR>)
+                     : (invd ? k_stencil_wave<T, S, false, true, TR> : k_stencil_wave<T, S, false, false, TR>);
+        };
+        auto kern = trans ? pick(std::true_type{}) : pick(std::false_type{});
+        hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, L.nx, L.ny, L.nt, L.nplanes, st, L.cen32,
+                           L.plane_map, (const T*)x, (T*)y, (const T*)b, (const T*)invd, scale,
+                           skip, nchunk, gx, nblk, per_xcd);
+        return;
     }
     if (trans)
         hipLaunchKernelGGL((k_stencil_march<T, S, TC, true>), grid, dim3(256), 0, s, L.nx, L.ny,
