@@ -205,19 +205,22 @@ def test_mixed_precision_applies(torch_cuda, tv):
     p.close()
 
 
-@pytest.mark.parametrize("tv,bf16", [(False, False), (True, False), (True, True)])
-def test_stencil_apply_wide_planes(torch_cuda, tv, bf16):
-    """FP32 and BF16 coarse applies on planes that span several 64-lane waves
-    (the forward apply takes a node's in-plane neighbours from the lanes
-    beside it, 62 outputs per wave): planes of 713 and 192 nodes (11 full
-    waves and a ragged one; rows 31 and 16 nodes wide, so waves cross row
-    ends), 71 and 36 time levels (chunks of four with a ragged last one).
-    Forward and transposed against the oracle operator, under the BF16
-    storage model for BF16, 1e-5, and on a field that is non-zero on one
-    node only (every neighbour coefficient of that column in place)."""
+@pytest.mark.parametrize("tv,prec", [(False, "fp32"), (True, "fp32"), (True, "bf16"), (False, "fp64"),
+                                     (True, "fp64")])
+def test_stencil_apply_wide_planes(torch_cuda, tv, prec):
+    """Coarse applies on planes that span several 64-lane waves (a node's
+    in-plane neighbours come from the lanes beside it, 62 outputs per wave):
+    planes of 713 and 192 nodes (11 full waves and a ragged one; rows 31 and
+    16 nodes wide, so waves cross row ends), 71 and 36 time levels (chunks of
+    four with a ragged last one).  Forward and transposed against the oracle
+    operator -- under the BF16 storage model for BF16 -- to 1e-5 in FP32 and
+    BF16 storage and 1e-13 in FP64, on a random field and on a field that is
+    non-zero on one node only (every neighbour coefficient of that column in
+    place)."""
     import scipy.sparse as sp
     c = Case(60, 44, 70, tv=tv, seed=21)
-    p = c.problem(precision="mixed", bf16_from_level=1 if bf16 else 0)
+    fp64 = prec == "fp64"
+    p = c.problem(precision="fp64" if fp64 else "mixed", bf16_from_level=1 if prec == "bf16" else 0)
     A, masks, Pm = c.ops
     rng = np.random.default_rng(8)
     assert len(c.levels) >= 4
@@ -228,11 +231,15 @@ def test_stencil_apply_wide_planes(torch_cuda, tv, bf16):
         e = np.zeros(Al.shape[0])
         e[(c.levels[l]["nt"] // 2) * P + P // 2 + 7] = 1.0
         for trans in (False, True):
-            Ab = _bf16_compensated(Al, P, by_column=trans) if bf16 else Al
+            Ab = _bf16_compensated(Al, P, by_column=trans) if prec == "bf16" else Al
             for v in (x, e):
-                y = p.debug_apply(l, _t(v).reshape(p.level_shape(l)), transpose=trans, mixed=True)
+                y = p.debug_apply(l, _t(v).reshape(p.level_shape(l)), transpose=trans,
+                                  mixed=not fp64).cpu().numpy()
                 ref = (Ab.T if trans else Ab) @ v
-                assert rel(y.cpu().numpy(), ref) < 1e-5, (l, trans, rel(y.cpu().numpy(), ref))
+                if fp64:
+                    assert maxrel(y, ref) < 1e-13, (l, trans, maxrel(y, ref))
+                else:
+                    assert rel(y, ref) < 1e-5, (l, trans, rel(y, ref))
     p.close()
 
 
