@@ -244,13 +244,22 @@ __global__ __launch_bounds__(256) void k_stencil_wave(
             sr += cg[d * 3 + 2] * u[d];
         }
     };
+    // The chunk's first three levels of x (and b, invd of its first level)
+    // are loaded while the plane indices, then the first coefficients, come
+    // in: the first step needs all of them, so the coefficients' waits drain
+    // nothing that is loaded ahead.
+    T R0[3], R1[3], R2[3], R3[3];
+    T b0 = 0, b1 = 0, d0 = 1, d1 = 1;
+    if (HB) b0 = lv_ld<T>(br, (unsigned)n0 * PB + rb);
+    if (HD) d0 = lv_ld<T>(dr, (unsigned)n0 * PB + rb);
+    load_level(n0 - 1, R0);
+    load_level(n0, R1);
+    load_level(n0 + 1, R2);
     int key = __builtin_amdgcn_readlane(pml, 0), keyc = 0, keyp = 0;
     if (TRANS) {
         keyc = __builtin_amdgcn_readlane(pml, 1);
         keyp = __builtin_amdgcn_readlane(pml, 2);
     }
-    // the first level's coefficients before any x load is in flight (their
-    // waits would drain those loads)
     load_coefs(key, TRANS ? keyc : key, keyp);
     // step n: levels n - 1, n, n + 1 of x in A, B, C and b, invd of level n
     // in bc, dc; level n + 2 of x goes into D, b and invd of level n + 1 into
@@ -291,13 +300,6 @@ __global__ __launch_bounds__(256) void k_stencil_wave(
         if (HD) v *= dc;
         lv_st(v * sc, yr, out && n < n1 ? (unsigned)n * PB + rb : SW_OOB);
     };
-    T R0[3], R1[3], R2[3], R3[3];
-    T b0 = 0, b1 = 0, d0 = 1, d1 = 1;
-    if (HB) b0 = lv_ld<T>(br, (unsigned)n0 * PB + rb);
-    if (HD) d0 = lv_ld<T>(dr, (unsigned)n0 * PB + rb);
-    load_level(n0 - 1, R0);
-    load_level(n0, R1);
-    load_level(n0 + 1, R2);
     // no exit between the four steps: a load whose value only a later step
     // uses would be moved behind such an exit, after the arithmetic
     for (int n = n0; n < n1; n += 4) {
