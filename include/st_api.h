@@ -73,6 +73,12 @@ enum {
                                    (three passes per step) instead of delayed
                                    CGS2 (two passes; the same iterates in exact
                                    arithmetic)                                  */
+    ST_FLAG_ROW_MARCH = 64,     /* coarse stencil applies by the row march (one
+                                   thread per in-plane node) instead of the wave
+                                   form (a wave per 62 consecutive nodes); the
+                                   library takes the row march by itself for a
+                                   level whose vectors pass 2 GiB.  Test access
+                                   to that path; same results to rounding     */
     ST_FLAG_COARSE_GMRES = 4    /* coarsest level: Jacobi-GMRES (coarse_max_it,
                                    coarse_rtol, coarse_restart) as in §3.2, instead
                                    of the default exact solve by block-tridiagonal
@@ -262,7 +268,7 @@ st_status st_filter(st_handle* h, const double* in_dev, double* out_dev);
 st_status st_set_stream(st_handle* h, void* hip_stream);
 
 /* Replace the option flags (ST_FLAG_TIME_KERNELS and its class mask,
- * ST_FLAG_COARSE_GMRES, ST_FLAG_SSTEP_SMOOTHER, ST_FLAG_OUTER_CGS2) of a built problem; ST_FLAG_NO_PLANE_DEDUP,
+ * ST_FLAG_COARSE_GMRES, ST_FLAG_SSTEP_SMOOTHER, ST_FLAG_OUTER_CGS2, ST_FLAG_ROW_MARCH) of a built problem; ST_FLAG_NO_PLANE_DEDUP,
  * ST_FLAG_FULL_COARSENING and the other options are fixed at setup.  Switching to the exact coarse solve
  * factorises the coarsest operator on the next V-cycle. */
 st_status st_set_flags(st_handle* h, int32_t flags);

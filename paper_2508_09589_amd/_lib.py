@@ -12,7 +12,7 @@ ST_ERR_ARG, ST_ERR_OOM, ST_ERR_HIP, ST_ERR_BREAKDOWN, ST_ERR_STATE = -1, -2, -3,
 ST_FP64, ST_MIXED = 0, 1
 ST_EDGE_X1_LO, ST_EDGE_X1_HI, ST_EDGE_X2_LO, ST_EDGE_X2_HI = 0, 1, 2, 3
 ST_FLAG_TIME_KERNELS, ST_FLAG_NO_PLANE_DEDUP, ST_FLAG_COARSE_GMRES, ST_FLAG_FULL_COARSENING = 1, 2, 4, 8
-ST_FLAG_SSTEP_SMOOTHER, ST_FLAG_OUTER_CGS2 = 16, 32
+ST_FLAG_SSTEP_SMOOTHER, ST_FLAG_OUTER_CGS2, ST_FLAG_ROW_MARCH = 16, 32, 64
 ST_MAX_LEVELS, ST_MAX_PATCHES, ST_MAX_HIST, ST_NUM_KCLASS = 32, 4, 1024, 12
 
 KCLASS_NAMES = ["fine_apply_fp64", "fine_apply_vcycle", "stencil_apply", "smooth_mdot_l0",

@@ -313,11 +313,12 @@ __global__ __launch_bounds__(256) void k_stencil_wave(
 template <typename T, typename S, typename TC>
 static void stencil_dispatch(hipStream_t s, const Level& L, const S* st, int trans, const void* x,
                              void* y, const void* b, const void* invd, const double* scale,
-                             const int* skip) {
+                             const int* skip, bool row_march) {
     const int P = (L.nx + 1) * (L.ny + 1);
     // applies run as k_stencil_wave (4 x 62 nodes per block) where its
     // 32-bit buffer offsets reach every level
-    const bool wave = (long long)(L.nt + 1) * P * (long long)sizeof(T) < (long long)SW_OOB;
+    const bool wave =
+        !row_march && (long long)(L.nt + 1) * P * (long long)sizeof(T) < (long long)SW_OOB;
     const int gx = wave ? (P + 4 * SW_OUT - 1) / (4 * SW_OUT) : (P + 255) / 256;
     // (k_stencil_wave runs its levels four at a time; 64 levels per chunk
     // rather than 32 drop half its extra loads at the chunk boundaries; its
@@ -362,13 +363,16 @@ static void stencil_dispatch(hipStream_t s, const Level& L, const S* st, int tra
 
 void launch_stencil_apply(hipStream_t s, const Level& L, int prec, int trans, const void* x,
                           void* y, const void* b, const void* invd, const double* scale,
-                          const int* skip) {
+                          const int* skip, bool row_march) {
     if (prec == 0)
-        stencil_dispatch<double, double, double>(s, L, L.st64, trans, x, y, b, invd, scale, skip);
+        stencil_dispatch<double, double, double>(s, L, L.st64, trans, x, y, b, invd, scale, skip,
+                                                 row_march);
     else if (L.sprec == 2)
-        stencil_dispatch<float, uint16_t, float>(s, L, L.st16, trans, x, y, b, invd, scale, skip);
+        stencil_dispatch<float, uint16_t, float>(s, L, L.st16, trans, x, y, b, invd, scale, skip,
+                                                 row_march);
     else
-        stencil_dispatch<float, float, float>(s, L, L.st32, trans, x, y, b, invd, scale, skip);
+        stencil_dispatch<float, float, float>(s, L, L.st32, trans, x, y, b, invd, scale, skip,
+                                              row_march);
 }
 
 // Row j of in-plane index r on rows of length rowp, without an integer

@@ -436,7 +436,8 @@ void level_apply(st_handle* h, int l, int prec, int trans, const void* x, void* 
                 (int64_t)L.nn * (int64_t)(2 * vbytes(prec) + (b ? vbytes(prec) : 0) +
                                           (invd ? vbytes(prec) : 0)) +
                     stencil_row_bytes(L, prec) * (L.nx + 1) * (L.ny + 1) * L.nplanes);
-        launch_stencil_apply(h->stream, L, prec, trans, x, y, b, invd, scale, skip);
+        launch_stencil_apply(h->stream, L, prec, trans, x, y, b, invd, scale, skip,
+                             (h->opts.flags & ST_FLAG_ROW_MARCH) != 0);
     }
 }
 

@@ -131,9 +131,11 @@ void launch_fine_apply(hipStream_t s, const FineGeom& g, const Coef& cf, int pre
                        int dir_rows);
 void launch_fine_invdiag(hipStream_t s, const FineGeom& g, const Coef& cf, double dx, double dt,
                          double* invd64, float* invd32, uint8_t* mask);
+// row_march: the row-march kernel instead of the wave form (which it
+// replaces by itself where a level's vectors pass 2 GiB)
 void launch_stencil_apply(hipStream_t s, const Level& L, int prec, int trans, const void* x,
                           void* y, const void* b, const void* invd, const double* scale,
-                          const int* skip);
+                          const int* skip, bool row_march);
 void launch_restrict(hipStream_t s, const Level& F, const Level& C, int prec, const void* rf,
                      void* bc);
 void launch_prolong(hipStream_t s, const Level& F, const Level& C, int prec, const void* ec,

@@ -107,3 +107,12 @@ def test_bf16_footprint_counts_compensated_centres(nx, nt, tv):
     rc2, b16 = _fp(nx, nx, nt, tv, precision=L.ST_MIXED, bf16_from_level=1)
     assert rc == 0 and rc2 == 0
     assert abs((b32 - b16) - (60 - 36) * rows) <= 2 * 256 * len(lv), (b32 - b16, 24 * rows)
+
+
+def test_flag_values_match_the_header():
+    """Every ST_FLAG_* of include/st_api.h has the same value in the binding."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    flags = dict((k, int(v)) for k, v in re.findall(r"\b(ST_FLAG_[A-Z_0-9]+)\s*=\s*(\d+)", src))
+    assert "ST_FLAG_ROW_MARCH" in flags and len(flags) >= 7
+    for k, v in flags.items():
+        assert getattr(L, k) == v, k

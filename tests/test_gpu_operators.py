@@ -216,15 +216,19 @@ def test_stencil_apply_wide_planes(torch_cuda, tv, prec):
     operator -- under the BF16 storage model for BF16 -- to 1e-5 in FP32 and
     BF16 storage and 1e-13 in FP64, on a random field and on a field that is
     non-zero on one node only (every neighbour coefficient of that column in
-    place)."""
+    place).  The same with ST_FLAG_ROW_MARCH, the row-march kernel that the
+    library takes for levels past 2 GiB."""
     import scipy.sparse as sp
+    from paper_2508_09589_amd import _lib as Lb
     c = Case(60, 44, 70, tv=tv, seed=21)
     fp64 = prec == "fp64"
     p = c.problem(precision="fp64" if fp64 else "mixed", bf16_from_level=1 if prec == "bf16" else 0)
     A, masks, Pm = c.ops
     rng = np.random.default_rng(8)
     assert len(c.levels) >= 4
-    for l in range(1, len(c.levels)):
+    flags0 = p.opts.flags
+    for march, l in [(m, l) for m in (False, True) for l in range(1, len(c.levels))]:
+        p.set_flags(flags0 | (Lb.ST_FLAG_ROW_MARCH if march else 0))
         Al = sp.csr_matrix(A[l])
         P = (c.levels[l]["nx"] + 1) * (c.levels[l]["ny"] + 1)
         x = rng.standard_normal(Al.shape[0])
@@ -237,9 +241,9 @@ def test_stencil_apply_wide_planes(torch_cuda, tv, prec):
                                   mixed=not fp64).cpu().numpy()
                 ref = (Ab.T if trans else Ab) @ v
                 if fp64:
-                    assert maxrel(y, ref) < 1e-13, (l, trans, maxrel(y, ref))
+                    assert maxrel(y, ref) < 1e-13, (l, march, trans, maxrel(y, ref))
                 else:
-                    assert rel(y, ref) < 1e-5, (l, trans, rel(y, ref))
+                    assert rel(y, ref) < 1e-5, (l, march, trans, rel(y, ref))
     p.close()
 
 
