@@ -497,6 +497,81 @@ __global__ void k_restrict(int nxf, int nyf, int ntf, int nxc, int nyc, int ntc,
 }
 
 // Grid of a transfer that takes lv time levels per thread and step.
+// Space restriction (P_m^T, nxf = 2 nxc, nyf = 2 nyc) with the horizontal
+// weights taken across lanes.  A wave covers fine columns 2 I0 - 1 ..
+// 2 I0 + 62 of the fine rows 2J - 1, 2J, 2J + 1: each lane sums its column
+// over the three rows (weights 1/2, 1, 1/2; masked fine nodes left out), and
+// the odd lanes, which sit on even fine columns, add half of each
+// neighbour's column sum to their own: coarse nodes I0 .. I0 + 30.  Fine
+// values and masks come through buffer resources, so that a row or column
+// outside the grid reads zero without a branch; all loads of a batch of
+// RW_LV time levels are issued before its arithmetic.  Sums in FP64, as in
+// k_restrict_space.
+constexpr int RW_OUT = 31, RW_LV = 4;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict_wave(int nxf, int nyf, int nt, int nxc, int nyc,
+                                                       int nseg, int nchunk,
+                                                       const uint8_t* __restrict__ maskf,
+                                                       const T* __restrict__ rf, T* __restrict__ bc) {
+    const int lane = threadIdx.x & 63;
+    const int w = blockIdx.x * 4 + (int)(threadIdx.x >> 6);   // wave over (coarse row, segment)
+    const int J = w / nseg;
+    if (J > nyc) return;
+    const int I0 = (w - J * nseg) * RW_OUT;
+    const int n0 = blockIdx.y * nchunk;
+    if (n0 > nt) return;
+    const int n1 = min(n0 + nchunk, nt + 1);
+    const int fi = 2 * I0 - 1 + lane;                          // this lane's fine column
+    const int I = fi >> 1;                                     // coarse column of an odd lane
+    const bool out = (lane & 1) && lane <= 2 * RW_OUT - 1 && I <= nxc;
+    const int rowf = nxf + 1, rowc = nxc + 1;
+    const unsigned Pf = (unsigned)rowf * (unsigned)(nyf + 1), Pc = (unsigned)rowc * (unsigned)(nyc + 1);
+    unsigned fo[3];                                            // in-plane fine node of row d
+    unsigned fin = 0;                                          // bit d: that node is in the grid
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int fj = 2 * J + d - 1;
+        const bool ok = fi >= 0 && fi <= nxf && fj >= 0 && fj <= nyf;
+        fo[d] = ok ? (unsigned)(fj * rowf + fi) : 0u;
+        if (ok) fin |= 1u << d;
+    }
+    const long long nl = nt + 1;
+    const __amdgpu_buffer_rsrc_t rr = lv_rsrc(rf, nl * Pf * (long long)sizeof(T));
+    const __amdgpu_buffer_rsrc_t mr = lv_rsrc(maskf, nl * Pf);
+    const __amdgpu_buffer_rsrc_t cr = lv_rsrc(bc, nl * Pc * (long long)sizeof(T));
+    const unsigned co = (unsigned)(J * rowc + I);
+    for (int nb = n0; nb < n1; nb += RW_LV) {
+        T v[RW_LV][3];
+        unsigned char m[RW_LV][3];
+#pragma unroll
+        for (int u = 0; u < RW_LV; ++u) {
+            // levels past the chunk read nothing and store nothing
+            const bool lv = nb + u < n1;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                // a node outside the grid (or a level past the chunk) reads
+                // at an offset past both resources' ends: zero, no access
+                const bool ok = lv && ((fin >> d) & 1u);
+                const unsigned e = (unsigned)(nb + u) * Pf + fo[d];
+                v[u][d] = lv_ld<T>(rr, ok ? e * (unsigned)sizeof(T) : SW_OOB);
+                m[u][d] = __builtin_amdgcn_raw_buffer_load_b8(mr, ok ? e : SW_OOB, 0, 0);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < RW_LV; ++u) {
+            double col = 0.0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                col += (m[u][d] ? 0.0 : (d == 1 ? 1.0 : 0.5)) * (double)v[u][d];
+            const double r = col + 0.5 * (lane_prev(col) + lane_next(col));
+            const bool st = out && nb + u < n1;
+            lv_st((T)r, cr, st ? ((unsigned)(nb + u) * Pc + co) * (unsigned)sizeof(T) : SW_OOB);
+        }
+    }
+}
+
 static inline dim3 level_grid(const Level& L, int lv) {
     const long long P = (long long)(L.nx + 1) * (L.ny + 1);
     const long long steps = (L.nt + 1 + lv - 1) / lv;
@@ -506,6 +581,27 @@ static inline dim3 level_grid(const Level& L, int lv) {
 void launch_restrict(hipStream_t s, const Level& F, const Level& C, int prec, const void* rf,
                      void* bc) {
     const double inv = 1.0 / (C.nx + 1);
+    const long long Pf = (long long)(F.nx + 1) * (F.ny + 1);
+    const size_t es = prec == 0 ? 8 : 4;
+    if (C.how == 1 && F.nx == 2 * C.nx && F.ny == 2 * C.ny &&
+        (long long)(C.nt + 1) * Pf * (long long)es < (long long)SW_OOB) {
+        // wave form: 31 coarse nodes per wave, chunks of 32 levels (fewer
+        // while the grid does not fill the chip)
+        const int nseg = (C.nx + 1 + RW_OUT - 1) / RW_OUT;
+        const long long waves = (long long)(C.ny + 1) * nseg;
+        const unsigned gx = (unsigned)((waves + 3) / 4);
+        int nchunk = 32;
+        while (nchunk > RW_LV && (long long)gx * ((C.nt + 1 + nchunk - 1) / nchunk) < 2048)
+            nchunk /= 2;
+        const dim3 grid(gx, (unsigned)((C.nt + 1 + nchunk - 1) / nchunk));
+        if (prec == 0)
+            hipLaunchKernelGGL(k_restrict_wave<double>, grid, dim3(256), 0, s, F.nx, F.ny, C.nt,
+                               C.nx, C.ny, nseg, nchunk, F.mask, (const double*)rf, (double*)bc);
+        else
+            hipLaunchKernelGGL(k_restrict_wave<float>, grid, dim3(256), 0, s, F.nx, F.ny, C.nt,
+                               C.nx, C.ny, nseg, nchunk, F.mask, (const float*)rf, (float*)bc);
+        return;
+    }
     if (C.how == 1) {
         const dim3 grid = level_grid(C, TR_LV);
         if (prec == 0)
